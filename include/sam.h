@@ -1,0 +1,305 @@
+/*
+ * sam.h -- C ABI of the MI355X (gfx950) sparse approximate map library.
+ *
+ * The library builds the sparse approximate map (SAM) of Islam, Carr and
+ * Jacobs, "Optimization of Approximate Maps for Linear Systems Arising in
+ * Discretized PDEs": for a source matrix A_k, a target matrix A_0 and a
+ * sparsity pattern S it computes
+ *
+ *     N_k = argmin ||A_k N - A_0||_F  over N with pattern S     (Section 2,
+ *                                                              eq. approx_map)
+ *
+ * column by column as n independent least-squares problems
+ * min_m ||A_k(:,J_j) m - A_0(:,j)||_2 with J_j = S(:,j) (end of Section 2),
+ * together with the residual R_k = A_k N_k - A_0 (eq. res) and its Frobenius
+ * norm, the quality measure of Section 5.  Patterns are the level neighbours
+ * of Section 3, S((I + B)^p) with B = S(A~_k), optionally after one of the
+ * sparsification rules of Section 4 (global threshold, column threshold tau,
+ * fixed count lfil).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - All array arguments are DEVICE pointers owned by the caller unless the
+ *   comment says "host".  The library never frees caller memory.
+ * - Matrices are square n x n in compressed sparse column (CSC) form: colptr
+ *   has n+1 int32 entries with colptr[0] = 0 and colptr[n] = nnz, rowind has
+ *   nnz int32 row indices strictly ascending inside each column, values are
+ *   FP64.  Index counts must fit in int32 (else SAM_ERR_OVERFLOW).
+ * - Every call is asynchronous on the given stream (a hipStream_t passed as
+ *   sam_stream_t; NULL is the default stream) unless documented as
+ *   synchronising.  Host-visible results of asynchronous calls are valid after
+ *   the stream has been synchronised.
+ * - Numerical failures found inside kernels (a numerically rank-deficient
+ *   column block, a non-finite value, an out-of-range index read from caller
+ *   data) are recorded in a per-context device status word and reported by
+ *   sam_sync_status().  Argument errors are returned immediately.
+ * - The library allocates device memory only inside a context (workspace) and
+ *   inside plan / sequence objects, always before any work is enqueued; the
+ *   calls that run kernels on an existing plan or sequence allocate nothing.
+ * - No call throws; every call returns a sam_status.  sam_last_error() gives a
+ *   human-readable message for the last failing call on a context.
+ */
+#ifndef SAM_MI355X_H
+#define SAM_MI355X_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SAM_OK = 0,
+    SAM_ERR_ARG = 1,          /* null pointer, negative size, bad enum value  */
+    SAM_ERR_SHAPE = 2,        /* inconsistent dimensions between arguments    */
+    SAM_ERR_UNSORTED = 3,     /* CSC structure invalid: colptr not monotone,  */
+                              /* rows out of range, unsorted or duplicated    */
+    SAM_ERR_OVERFLOW = 4,     /* an index count does not fit in int32         */
+    SAM_ERR_RANK = 5,         /* a column block is numerically rank deficient */
+    SAM_ERR_NONFINITE = 6,    /* NaN or Inf produced                          */
+    SAM_ERR_HIP = 7,          /* HIP runtime failure (message has the detail) */
+    SAM_ERR_UNSUPPORTED = 8,  /* a column block exceeds the kernels' limits,  */
+                              /* or the context has no device                 */
+    SAM_ERR_NOMEM = 9         /* device allocation failed                     */
+} sam_status;
+
+/* Arithmetic of the least-squares solves.
+ * SAM_PREC_F64: Householder QR, solve and residual in FP64; M values FP64.
+ * SAM_PREC_F32_REFINE: Householder QR and triangular solves in FP32, then one
+ *   seminormal refinement step m += R^{-1} R^{-T} A^T (b - A m) whose residual
+ *   and A^T r are accumulated in FP64 from the FP64 inputs; the per-column
+ *   residual is recomputed in FP64 from the refined m; M values stored FP32. */
+typedef enum { SAM_PREC_F64 = 0, SAM_PREC_F32_REFINE = 1 } sam_precision;
+
+/* Sparsification of A_k before the level expansion (Section 4).  The
+ * diagonal is always kept, also when it is not stored. */
+typedef enum {
+    SAM_SPARSIFY_NONE = 0,    /* B = stored entries of A_k                     */
+    SAM_SPARSIFY_GLOBAL = 1,  /* keep |a_ij| * s_ij > thresh, s_ij =           */
+                              /* (D_ii D_jj)^(-1/2) (global_scale = -1) or     */
+                              /* (D_ii D_jj)^(+1/2) (global_scale = +1, the    */
+                              /* printed form); D_ii = |a_ii|, or 1 if zero    */
+    SAM_SPARSIFY_COLUMN = 2,  /* keep |a_ij| > (1 - tau) max_i |a_ij|          */
+    SAM_SPARSIFY_LFIL = 3     /* keep the diagonal and the lfil-1 largest      */
+                              /* off-diagonal magnitudes (ties: smaller row)   */
+} sam_sparsify;
+
+typedef void* sam_stream_t;   /* a hipStream_t */
+
+typedef struct {
+    int32_t n;                /* order of the matrix                          */
+    int32_t nnz;              /* stored entries                               */
+    const int32_t* colptr;    /* device, n+1                                  */
+    const int32_t* rowind;    /* device, nnz, ascending within each column    */
+    const double* val;        /* device, nnz (may be NULL where documented)   */
+} sam_csc;
+
+typedef struct {
+    int32_t kind;             /* sam_sparsify                                 */
+    int32_t power;            /* p >= 1: S = S((I + B)^p)  (Section 3 levels) */
+    double thresh;            /* SAM_SPARSIFY_GLOBAL                          */
+    int32_t global_scale;     /* -1 (default) or +1, see above                */
+    double tau;               /* SAM_SPARSIFY_COLUMN, 0 <= tau <= 1           */
+    int32_t lfil;             /* SAM_SPARSIFY_LFIL, >= 1                      */
+} sam_pattern_spec;
+
+typedef struct sam_ctx sam_ctx;
+typedef struct sam_plan sam_plan;
+typedef struct sam_seq sam_seq;
+
+#define SAM_NO_DEVICE (-1)
+
+/* ---------------------------------------------------------------- context */
+
+/* Create a context bound to HIP device `device`.  device = SAM_NO_DEVICE
+ * gives a host-only context on which every call validates its arguments and
+ * then returns SAM_ERR_UNSUPPORTED instead of touching a GPU.
+ * Errors: SAM_ERR_ARG (ctx NULL), SAM_ERR_HIP (device not usable). */
+sam_status sam_create(sam_ctx** ctx, int device);
+
+/* Release the context, its workspace and status word.  ctx may be NULL. */
+sam_status sam_destroy(sam_ctx* ctx);
+
+/* Message of the last failing call on ctx (static storage owned by ctx;
+ * "" when none).  Valid until the next call on ctx. */
+const char* sam_last_error(const sam_ctx* ctx);
+
+/* Name of a status code (static string). */
+const char* sam_status_string(sam_status s);
+
+/* Library version string "major.minor.patch" (static). */
+const char* sam_version(void);
+
+/* Synchronise `stream`, read and clear the context's device status word.
+ * Returns the status of the earliest failing column since the last call
+ * (SAM_OK if none) and writes that column to *first_bad_col (host; -1 when
+ * none).  Synchronising. */
+sam_status sam_sync_status(sam_ctx* ctx, sam_stream_t stream, int32_t* first_bad_col);
+
+/* Check the CSC structure of A on the device: colptr[0] = 0, monotone,
+ * colptr[n] = nnz, rows in [0, n), strictly ascending within each column.
+ * Synchronising.  Errors: SAM_ERR_UNSORTED with the first bad column in the
+ * message. */
+sam_status sam_check_csc(sam_ctx* ctx, const sam_csc* A, sam_stream_t stream);
+
+/* ---------------------------------------------------------------- pattern */
+
+/* Sections 3-4: S = S((I + B)^p), B = S(A~_k) plus the diagonal, with A~_k
+ * given by spec->kind.  Column j of S is the set of vertices with a path of
+ * length <= p to j in G(B), rows ascending.  Computes the pattern into the
+ * context and returns nnz(S) in *nnz_S (host).  Synchronising (the count is
+ * needed on the host to size S).  A_k values are read only for the
+ * value-dependent rules.  Errors: SAM_ERR_ARG (power < 1, tau outside [0,1],
+ * lfil < 1, bad kind), SAM_ERR_OVERFLOW (nnz(S) >= 2^31). */
+sam_status sam_pattern_count(sam_ctx* ctx, const sam_csc* Ak, const sam_pattern_spec* spec,
+                             int64_t* nnz_S, sam_stream_t stream);
+
+/* Copy the pattern of the last sam_pattern_count on ctx into caller arrays
+ * S_colptr (n+1) and S_rowind (nnz_S).  Ak and spec must be the ones passed
+ * to that count (same pointers and values), else SAM_ERR_ARG. */
+sam_status sam_pattern_fill(sam_ctx* ctx, const sam_csc* Ak, const sam_pattern_spec* spec,
+                            int32_t* S_colptr, int32_t* S_rowind, sam_stream_t stream);
+
+/* ------------------------------------------------------------------ build */
+
+/* Symbolic analysis of the column problems for the structure of A_k (values
+ * ignored), the structure of A_0 (values ignored) and the pattern S:
+ * row sets I_j = rows(A_k(:,J_j)) (Section 2: the submatrix of A_k selected
+ * by S; rows outside I_j are zero), the position of every A_k and A_0 entry
+ * inside its column block, and the size classes (buckets) the numeric kernels
+ * run in.  The plan keeps pointers to the caller's structure arrays, which
+ * must stay valid and unchanged while the plan is used.  Synchronising.
+ * Errors: SAM_ERR_SHAPE (n mismatch, S size), SAM_ERR_UNSUPPORTED (a column
+ * block larger than the largest kernel class: |I_j| > 128 or |J_j| > 32),
+ * SAM_ERR_OVERFLOW, SAM_ERR_NOMEM. */
+sam_status sam_plan_create(sam_ctx* ctx, const sam_csc* Ak, const sam_csc* A0,
+                           const int32_t* S_colptr, const int32_t* S_rowind, int64_t nnz_S,
+                           sam_plan** plan, sam_stream_t stream);
+
+/* Release a plan (NULL allowed).  Frees device memory: the caller must make
+ * sure no enqueued work still uses it. */
+sam_status sam_plan_destroy(sam_plan* plan);
+
+/* Shape statistics of a plan (host outputs, any may be NULL): number of
+ * columns, max |I_j|, max |J_j|, total gathered entries sum_j nnz(A_k(:,J_j)),
+ * and the column count of each of up to 16 buckets (bucket_cols[16]). */
+sam_status sam_plan_info(const sam_plan* plan, int32_t* n, int32_t* max_rows, int32_t* max_cols,
+                         int64_t* gathered, int32_t* nbuckets, int32_t* bucket_cols);
+
+/* Numeric SAM build on a plan (Section 2): for every column j solve
+ * min ||A_k(I_j,J_j) m - A_0(I_j,j)||_2 by Householder QR and back
+ * substitution (prec selects FP64 or FP32 + FP64-residual refinement), write
+ * m into M_val[S_colptr[j] .. S_colptr[j+1]) (double for SAM_PREC_F64, float
+ * for SAM_PREC_F32_REFINE), and the squared column residual
+ * rho_j = ||A_k(:,J_j) m - A_0(:,j)||^2 into col_res2[j] (optional, may be
+ * NULL).  res2 (optional device scalar) receives sum_j rho_j =
+ * ||A_k M - A_0||_F^2, summed in a fixed order (bitwise reproducible).
+ * Ak_val and A0_val are the values matching the plan's structures.
+ * Allocates nothing; safe to capture in a HIP graph.
+ * Async errors (sam_sync_status): SAM_ERR_RANK, SAM_ERR_NONFINITE. */
+sam_status sam_build_planned(sam_plan* plan, const double* Ak_val, const double* A0_val,
+                             sam_precision prec, void* M_val, double* col_res2, double* res2,
+                             sam_stream_t stream);
+
+/* One-shot build: sam_plan_create + sam_build_planned + sam_plan_destroy.
+ * Synchronising (the plan is symbolic work with host-side sizing). */
+sam_status sam_build(sam_ctx* ctx, const sam_csc* Ak, const sam_csc* A0,
+                     const int32_t* S_colptr, const int32_t* S_rowind, int64_t nnz_S,
+                     sam_precision prec, void* M_val, double* col_res2, double* res2,
+                     sam_stream_t stream);
+
+/* --------------------------------------------------------------- residual */
+
+/* Section 2 eq. (res): res2 = ||A_k M - A_0||_F^2 recomputed explicitly from
+ * the stored map M (pattern M_colptr/M_rowind, values M_val in double for
+ * SAM_PREC_F64 or float for SAM_PREC_F32_REFINE), independently of the
+ * build's per-column residuals; a02 (optional) = ||A_0||_F^2, so that the
+ * relative residual of Section 5 is sqrt(res2 / a02).  Both are device
+ * scalars, summed in a fixed order.  Allocates nothing. */
+sam_status sam_residual(sam_ctx* ctx, const sam_csc* Ak, const sam_csc* A0,
+                        const int32_t* M_colptr, const int32_t* M_rowind, int64_t nnz_M,
+                        const void* M_val, sam_precision prec, double* res2, double* a02,
+                        sam_stream_t stream);
+
+/* ------------------------------------------------------------------ apply */
+
+/* Row view of a CSC pattern for y = M x: T_rowptr (n+1), T_colind (nnz) and
+ * T_perm (nnz) such that row i of M is {(T_colind[e], M_val[T_perm[e]])} for
+ * e in [T_rowptr[i], T_rowptr[i+1]), columns ascending.  Synchronising. */
+sam_status sam_apply_prepare(sam_ctx* ctx, int32_t n, const int32_t* M_colptr,
+                             const int32_t* M_rowind, int64_t nnz, int32_t* T_rowptr,
+                             int32_t* T_colind, int32_t* T_perm, sam_stream_t stream);
+
+/* y = M x (the map applied inside a Krylov iteration), FP64 accumulation in
+ * ascending column order per row (bitwise reproducible).  M_val is double or
+ * float per prec.  Allocates nothing. */
+sam_status sam_apply(sam_ctx* ctx, int32_t n, const int32_t* T_rowptr, const int32_t* T_colind,
+                     const int32_t* T_perm, const void* M_val, sam_precision prec,
+                     const double* x, double* y, sam_stream_t stream);
+
+/* --------------------------------------------------------------- sequence */
+
+/* A sequence A_1..A_N mapped to the target A_0 (Section 2: every source is
+ * mapped back to A_0).  All sources share the structure of `Ak_struct`
+ * (values ignored); their values are passed per run.  The pattern follows
+ * `spec` per source: when the rule does not depend on values
+ * (SAM_SPARSIFY_NONE) the pattern and plan are computed once here, unless
+ * `replan_each_run` is nonzero; value-dependent rules are recomputed for every
+ * source inside each run, sized to the unsparsified bound.  The first run
+ * with a given set of pointers is captured into a HIP graph; later runs with
+ * the same pointers replay it.  M_vals[k] must hold nnz_bound entries
+ * (sam_sequence_info).  Synchronising (create). */
+sam_status sam_sequence_create(sam_ctx* ctx, const sam_csc* A0, const sam_csc* Ak_struct,
+                               const sam_pattern_spec* spec, int32_t n_src, sam_precision prec,
+                               int32_t replan_each_run, sam_seq** seq, sam_stream_t stream);
+
+sam_status sam_sequence_destroy(sam_seq* seq);
+
+/* nnz bound per map (host) and, for source k, the device arrays holding its
+ * pattern after a run (valid until the next run). */
+sam_status sam_sequence_info(const sam_seq* seq, int64_t* nnz_bound);
+sam_status sam_sequence_pattern(const sam_seq* seq, int32_t k, const int32_t** S_colptr,
+                                const int32_t** S_rowind);
+
+/* Build every map of the sequence: Ak_vals (host array of n_src device
+ * pointers), M_vals (host array of n_src device pointers), res2 (device,
+ * n_src doubles: ||A_k M_k - A_0||_F^2).  Graph-replayed after the first call
+ * with the same pointers.  Allocates nothing after the first call. */
+sam_status sam_sequence_run(sam_seq* seq, const double* const* Ak_vals, void* const* M_vals,
+                            double* res2, sam_stream_t stream);
+
+/* -------------------------------------------------------- weights, adjoint */
+
+/* Soft-weighted map (not in the paper; a differentiable relaxation of the
+ * pattern choice): column j solves
+ *     min ||A_k(I_j,J_j) m - A_0(I_j,j)||^2 + sum_l p_l m_l^2,
+ *     p_l = mu (1/w_l - 1),  w in (0, 1] aligned with S's entries,
+ * as the stacked least-squares problem [A; diag(sqrt p)] (w = 1 leaves an
+ * entry unpenalised, w -> 0 removes it).  col_res2 / res2 exclude the
+ * penalty.  Only SAM_PREC_F32_REFINE (with two refinement steps) and
+ * SAM_PREC_F64 are accepted.  Allocates nothing. */
+sam_status sam_build_weighted(sam_plan* plan, const double* Ak_val, const double* A0_val,
+                              const double* w, double mu, sam_precision prec, void* M_val,
+                              double* col_res2, double* res2, sam_stream_t stream);
+
+/* Adjoint of L = dL * ||A_k M - A_0||_F^2 for the soft-weighted map M: the
+ * QR of each stacked block is recomputed (nothing is stored by the forward
+ * pass), lambda = (A^T A + P)^{-1} 2 A^T r with r = A m - b, and
+ *   gAk  (nnz(A_k), overwritten): sum over columns j of
+ *        2 r m^T - r lambda^T - (A lambda) m^T at the stored entries,
+ *   gA0  (nnz(A_0), overwritten): -2 r + A lambda on I_j, 2 A_0(i,j) outside,
+ *   gw   (nnz_S, optional):       mu lambda_l m_l / w_l^2,
+ *   loss (optional device scalar): the value of L.
+ * The A_k gradient is summed per entry in a fixed order (no atomics).
+ * Allocates nothing (uses the plan's gradient staging buffer). */
+sam_status sam_backward(sam_plan* plan, const double* Ak_val, const double* A0_val,
+                        const double* w, double mu, double dL, sam_precision prec,
+                        double* gAk, double* gA0, double* gw, double* loss,
+                        sam_stream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SAM_MI355X_H */

@@ -1,0 +1,772 @@
+// sam_capi.cpp -- host implementation of the C ABI declared in include/sam.h:
+// argument validation, context / plan / sequence objects, device memory
+// management and the launch sequence of the gfx950 kernels.
+#include "sam.h"
+#include "sam_kernels.hpp"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <climits>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+using samk::BucketTable;
+using samk::NumericArgs;
+using samk::NumericVariant;
+
+namespace {
+
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+};
+
+}  // namespace
+
+struct sam_ctx {
+    int device = SAM_NO_DEVICE;
+    std::string err;
+    unsigned long long* d_status = nullptr;
+    DevBuf ws;  // scratch for synchronising calls
+    // last pattern from sam_pattern_count
+    DevBuf S_cp, S_ri;
+    int64_t S_nnz = -1;
+    int S_n = -1;
+    const int32_t* key_cp = nullptr;
+    const int32_t* key_ri = nullptr;
+    const double* key_val = nullptr;
+    sam_pattern_spec key_spec{};
+    int CUs = 256;
+};
+
+namespace {
+
+constexpr unsigned long long kStatusClear = 0x7fffffffffffffffull;
+
+sam_status fail(sam_ctx* ctx, sam_status st, const char* fmt, ...) __attribute__((format(printf, 3, 4)));
+sam_status fail(sam_ctx* ctx, sam_status st, const char* fmt, ...) {
+    if (ctx) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        ctx->err = buf;
+    }
+    return st;
+}
+
+#define HIP_TRY(ctx, expr)                                                                       \
+    do {                                                                                         \
+        hipError_t e_ = (expr);                                                                  \
+        if (e_ != hipSuccess)                                                                    \
+            return fail((ctx), e_ == hipErrorOutOfMemory ? SAM_ERR_NOMEM : SAM_ERR_HIP,          \
+                        "%s: %s (%s:%d)", #expr, hipGetErrorString(e_), __FILE__, __LINE__);     \
+    } while (0)
+
+hipStream_t S(sam_stream_t s) { return reinterpret_cast<hipStream_t>(s); }
+
+size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+
+hipError_t grow(DevBuf& b, size_t bytes) {
+    if (b.bytes >= bytes && b.p) return hipSuccess;
+    if (b.p) {
+        hipError_t e = hipFree(b.p);
+        if (e != hipSuccess) return e;
+        b.p = nullptr;
+        b.bytes = 0;
+    }
+    size_t want = std::max<size_t>(align256(bytes), 256);
+    hipError_t e = hipMalloc(&b.p, want);
+    if (e != hipSuccess) {
+        b.p = nullptr;
+        return e;
+    }
+    b.bytes = want;
+    return hipSuccess;
+}
+
+void release(DevBuf& b) {
+    if (b.p) (void)hipFree(b.p);
+    b.p = nullptr;
+    b.bytes = 0;
+}
+
+// bump allocator over a DevBuf
+struct Carve {
+    char* base;
+    size_t off = 0;
+    explicit Carve(void* p) : base((char*)p) {}
+    template <typename T>
+    T* take(size_t count) {
+        T* r = (T*)(base + off);
+        off += align256(count * sizeof(T));
+        return r;
+    }
+};
+
+sam_status check_ctx(sam_ctx* ctx) {
+    if (!ctx) return SAM_ERR_ARG;
+    ctx->err.clear();
+    return SAM_OK;
+}
+
+sam_status need_device(sam_ctx* ctx) {
+    if (ctx->device == SAM_NO_DEVICE)
+        return fail(ctx, SAM_ERR_UNSUPPORTED, "context has no device (created with SAM_NO_DEVICE)");
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e != hipSuccess) return fail(ctx, SAM_ERR_HIP, "hipSetDevice(%d): %s", ctx->device, hipGetErrorString(e));
+    return SAM_OK;
+}
+
+sam_status check_csc_args(sam_ctx* ctx, const sam_csc* A, const char* name, bool need_val) {
+    if (!A) return fail(ctx, SAM_ERR_ARG, "%s is NULL", name);
+    if (A->n < 0 || A->nnz < 0) return fail(ctx, SAM_ERR_ARG, "%s: negative size (n=%d nnz=%d)", name, A->n, A->nnz);
+    if (!A->colptr) return fail(ctx, SAM_ERR_ARG, "%s: colptr is NULL", name);
+    if (A->nnz > 0 && !A->rowind) return fail(ctx, SAM_ERR_ARG, "%s: rowind is NULL", name);
+    if (need_val && A->nnz > 0 && !A->val) return fail(ctx, SAM_ERR_ARG, "%s: val is NULL", name);
+    return SAM_OK;
+}
+
+sam_status check_spec(sam_ctx* ctx, const sam_pattern_spec* spec) {
+    if (!spec) return fail(ctx, SAM_ERR_ARG, "pattern spec is NULL");
+    if (spec->kind < SAM_SPARSIFY_NONE || spec->kind > SAM_SPARSIFY_LFIL)
+        return fail(ctx, SAM_ERR_ARG, "unknown sparsification kind %d", spec->kind);
+    if (spec->power < 1) return fail(ctx, SAM_ERR_ARG, "power must be >= 1 (got %d)", spec->power);
+    if (spec->kind == SAM_SPARSIFY_COLUMN && !(spec->tau >= 0.0 && spec->tau <= 1.0))
+        return fail(ctx, SAM_ERR_ARG, "tau must lie in [0, 1] (got %g)", spec->tau);
+    if (spec->kind == SAM_SPARSIFY_LFIL && spec->lfil < 1)
+        return fail(ctx, SAM_ERR_ARG, "lfil must be >= 1 (got %d)", spec->lfil);
+    if (spec->kind == SAM_SPARSIFY_GLOBAL && spec->global_scale != -1 && spec->global_scale != 1)
+        return fail(ctx, SAM_ERR_ARG, "global_scale must be -1 or +1 (got %d)", spec->global_scale);
+    return SAM_OK;
+}
+
+samk::SparsifySpec to_sp(const sam_pattern_spec* spec) {
+    samk::SparsifySpec sp;
+    sp.kind = spec->kind;
+    sp.thresh = spec->thresh;
+    sp.global_scale = spec->global_scale;
+    sp.tau = spec->tau;
+    sp.lfil = spec->lfil;
+    return sp;
+}
+
+bool prec_ok(sam_precision p) { return p == SAM_PREC_F64 || p == SAM_PREC_F32_REFINE; }
+
+// read one device int64 value (synchronising)
+template <typename T>
+hipError_t read_back(const T* dptr, T* host, hipStream_t s) {
+    hipError_t e = hipMemcpyAsync(host, dptr, sizeof(T), hipMemcpyDeviceToHost, s);
+    if (e != hipSuccess) return e;
+    return hipStreamSynchronize(s);
+}
+
+// Pattern pipeline: B = sparsify(A_k) (diagonal added), then S = B, and
+// p-1 times S <- expand(S, B).  Produces device arrays into out_cp/out_ri
+// (grown as needed) and the host nnz.
+sam_status compute_pattern(sam_ctx* ctx, const sam_csc* Ak, const sam_pattern_spec* spec, DevBuf& out_cp,
+                           DevBuf& out_ri, int64_t* nnz_out, hipStream_t s) {
+    const int n = Ak->n;
+    samk::SparsifySpec sp = to_sp(spec);
+    // workspace: counts (n int), scan out (n+1 int64), scan temp, D (n double),
+    // B_cp (n+1), B_ri (nnz+n), overflow flag, bad flag
+    const size_t nnzB_bound = (size_t)Ak->nnz + (size_t)n;
+    size_t need = align256((size_t)n * 4) + align256((size_t)(n + 1) * 8) + align256(samk::scan_temp_bytes(n)) +
+                  align256((size_t)n * 8) + align256((size_t)(n + 1) * 4) + align256(nnzB_bound * 4) + 512;
+    HIP_TRY(ctx, grow(ctx->ws, need));
+    Carve cv(ctx->ws.p);
+    int* counts = cv.take<int>(n);
+    int64_t* off = cv.take<int64_t>(n + 1);
+    void* stemp = cv.take<char>(samk::scan_temp_bytes(n));
+    double* D = cv.take<double>(n);
+    int* B_cp = cv.take<int>(n + 1);
+    int* B_ri = cv.take<int>(nnzB_bound);
+    int* flags = cv.take<int>(2);  // [0] overflow, [1] bad column
+    HIP_TRY(ctx, hipMemsetAsync(flags, 0, sizeof(int), s));
+    const int nbad = n;
+    HIP_TRY(ctx, hipMemcpyAsync(flags + 1, &nbad, sizeof(int), hipMemcpyHostToDevice, s));
+    if (n == 0) {
+        HIP_TRY(ctx, grow(out_cp, sizeof(int)));
+        HIP_TRY(ctx, hipMemsetAsync(out_cp.p, 0, sizeof(int), s));
+        *nnz_out = 0;
+        HIP_TRY(ctx, hipStreamSynchronize(s));
+        return SAM_OK;
+    }
+    HIP_TRY(ctx, samk::sparsify_count(n, Ak->colptr, Ak->rowind, Ak->val, sp, D, counts, s));
+    HIP_TRY(ctx, samk::scan_counts(counts, n, off, B_cp, flags, stemp, s));
+    HIP_TRY(ctx, samk::sparsify_fill(n, Ak->colptr, Ak->rowind, Ak->val, sp, D, B_cp, B_ri, s));
+    int64_t nnzB = 0;
+    HIP_TRY(ctx, read_back(off + n, &nnzB, s));
+    const int* cur_cp = B_cp;
+    const int* cur_ri = B_ri;
+    int64_t cur_nnz = nnzB;
+    DevBuf level_cp, level_ri;  // alternating level buffers
+    DevBuf level_cp2, level_ri2;
+    for (int lev = 1; lev < spec->power; ++lev) {
+        HIP_TRY(ctx, samk::expand_count(n, cur_cp, cur_ri, B_cp, B_ri, counts, flags + 1, s));
+        HIP_TRY(ctx, samk::scan_counts(counts, n, off, nullptr, flags, stemp, s));
+        int64_t tot = 0;
+        HIP_TRY(ctx, read_back(off + n, &tot, s));
+        if (tot > INT_MAX) {
+            release(level_cp); release(level_ri); release(level_cp2); release(level_ri2);
+            return fail(ctx, SAM_ERR_OVERFLOW, "pattern level %d has %lld entries (>= 2^31)", lev + 1, (long long)tot);
+        }
+        DevBuf& ncp = (lev & 1) ? level_cp : level_cp2;
+        DevBuf& nri = (lev & 1) ? level_ri : level_ri2;
+        HIP_TRY(ctx, grow(ncp, (size_t)(n + 1) * 4));
+        HIP_TRY(ctx, grow(nri, (size_t)std::max<int64_t>(tot, 1) * 4));
+        HIP_TRY(ctx, samk::scan_counts(counts, n, off, (int*)ncp.p, flags, stemp, s));
+        HIP_TRY(ctx, samk::expand_fill(n, cur_cp, cur_ri, B_cp, B_ri, (int*)ncp.p, (int*)nri.p, s));
+        cur_cp = (int*)ncp.p;
+        cur_ri = (int*)nri.p;
+        cur_nnz = tot;
+    }
+    int hflags[2] = {0, n};
+    HIP_TRY(ctx, hipMemcpyAsync(hflags, flags, sizeof hflags, hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, hipStreamSynchronize(s));
+    sam_status st = SAM_OK;
+    if (hflags[1] != n) st = fail(ctx, SAM_ERR_UNSORTED, "column %d references a column index outside [0, n)", hflags[1]);
+    else if (hflags[0]) st = fail(ctx, SAM_ERR_OVERFLOW, "pattern size does not fit in int32");
+    if (st == SAM_OK) {
+        HIP_TRY(ctx, grow(out_cp, (size_t)(n + 1) * 4));
+        HIP_TRY(ctx, grow(out_ri, (size_t)std::max<int64_t>(cur_nnz, 1) * 4));
+        HIP_TRY(ctx, hipMemcpyAsync(out_cp.p, cur_cp, (size_t)(n + 1) * 4, hipMemcpyDeviceToDevice, s));
+        if (cur_nnz > 0)
+            HIP_TRY(ctx, hipMemcpyAsync(out_ri.p, cur_ri, (size_t)cur_nnz * 4, hipMemcpyDeviceToDevice, s));
+        HIP_TRY(ctx, hipStreamSynchronize(s));
+        *nnz_out = cur_nnz;
+    }
+    release(level_cp); release(level_ri); release(level_cp2); release(level_ri2);
+    return st;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ plan
+
+namespace {
+
+// One (precision, weighted) combination of a plan: the bucket order of the
+// columns and the kernel variant per bucket.
+struct Combo {
+    bool ok = false;
+    std::string why;
+    std::vector<const NumericVariant*> variants;
+    int* queue = nullptr;   // device n
+    int* bstart = nullptr;  // device nb+1
+    std::vector<int> counts;
+};
+
+}  // namespace
+
+struct sam_plan {
+    sam_ctx* ctx = nullptr;
+    int n = 0;
+    int nnzA = 0, nnzA0 = 0;
+    int64_t nnzS = 0;
+    const int *Ak_cp = nullptr, *Ak_ri = nullptr, *A0_cp = nullptr, *A0_ri = nullptr;
+    const int *S_cp = nullptr, *S_ri = nullptr;
+    DevBuf mem;          // nI, eoff, posA, posB, queues, colbuf, reduce temp
+    int* nI = nullptr;
+    int64_t* eoff = nullptr;
+    unsigned char* posA = nullptr;
+    unsigned char* posB = nullptr;
+    double* colbuf = nullptr;
+    void* rtemp = nullptr;
+    int64_t E = 0;
+    int max_rows = 0, max_cols = 0;
+    Combo combo[2][2];  // [prec][weighted]
+    // backward staging (lazily allocated)
+    DevBuf bwd;
+};
+
+namespace {
+
+sam_status plan_combo(sam_plan* pl, int prec, int weighted, void* temp, int* unfit_d, hipStream_t s) {
+    sam_ctx* ctx = pl->ctx;
+    Combo& cb = pl->combo[prec][weighted];
+    int cnt = 0;
+    const NumericVariant* menu = samk::numeric_menu(&cnt);
+    BucketTable tab{};
+    tab.nb = 0;
+    for (int i = 0; i < cnt && tab.nb < samk::kMaxBuckets; ++i) {
+        if (menu[i].prec != prec || menu[i].weighted != weighted) continue;
+        tab.max_rows[tab.nb] = menu[i].max_rows();
+        tab.max_cols[tab.nb] = menu[i].NC;
+        tab.rows_plus_cols = weighted;
+        cb.variants.push_back(&menu[i]);
+        tab.nb++;
+    }
+    HIP_TRY(ctx, hipMemsetAsync(unfit_d, 0, sizeof(int), s));
+    HIP_TRY(ctx, samk::bucket_sort(pl->n, pl->S_cp, pl->nI, tab, cb.queue, cb.bstart, unfit_d, temp, s));
+    std::vector<int> hb(tab.nb + 1, 0);
+    int unfit = 0;
+    HIP_TRY(ctx, hipMemcpyAsync(hb.data(), cb.bstart, sizeof(int) * (tab.nb + 1), hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, hipMemcpyAsync(&unfit, unfit_d, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, hipStreamSynchronize(s));
+    cb.counts.resize(tab.nb);
+    for (int b = 0; b < tab.nb; ++b) cb.counts[b] = hb[b + 1] - hb[b];
+    cb.ok = unfit == 0;
+    if (!cb.ok) {
+        char buf[256];
+        snprintf(buf, sizeof buf,
+                 "%d columns exceed the largest kernel class for %s%s (max |I_j| = %d, max |J_j| = %d)", unfit,
+                 prec ? "FP32+refine" : "FP64", weighted ? " weighted" : "", pl->max_rows, pl->max_cols);
+        cb.why = buf;
+    }
+    return SAM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* sam_version(void) { return "0.1.0"; }
+
+const char* sam_status_string(sam_status s) {
+    switch (s) {
+        case SAM_OK: return "SAM_OK";
+        case SAM_ERR_ARG: return "SAM_ERR_ARG";
+        case SAM_ERR_SHAPE: return "SAM_ERR_SHAPE";
+        case SAM_ERR_UNSORTED: return "SAM_ERR_UNSORTED";
+        case SAM_ERR_OVERFLOW: return "SAM_ERR_OVERFLOW";
+        case SAM_ERR_RANK: return "SAM_ERR_RANK";
+        case SAM_ERR_NONFINITE: return "SAM_ERR_NONFINITE";
+        case SAM_ERR_HIP: return "SAM_ERR_HIP";
+        case SAM_ERR_UNSUPPORTED: return "SAM_ERR_UNSUPPORTED";
+        case SAM_ERR_NOMEM: return "SAM_ERR_NOMEM";
+    }
+    return "SAM_ERR_UNKNOWN";
+}
+
+sam_status sam_create(sam_ctx** out, int device) {
+    if (!out) return SAM_ERR_ARG;
+    *out = nullptr;
+    sam_ctx* ctx = new (std::nothrow) sam_ctx();
+    if (!ctx) return SAM_ERR_NOMEM;
+    ctx->device = device;
+    if (device != SAM_NO_DEVICE) {
+        int ndev = 0;
+        if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) {
+            delete ctx;
+            return SAM_ERR_HIP;
+        }
+        if (hipSetDevice(device) != hipSuccess) {
+            delete ctx;
+            return SAM_ERR_HIP;
+        }
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
+            ctx->CUs = prop.multiProcessorCount;
+        if (hipMalloc(&ctx->d_status, sizeof(unsigned long long)) != hipSuccess) {
+            delete ctx;
+            return SAM_ERR_NOMEM;
+        }
+        unsigned long long clear = kStatusClear;
+        if (hipMemcpy(ctx->d_status, &clear, sizeof clear, hipMemcpyHostToDevice) != hipSuccess) {
+            (void)hipFree(ctx->d_status);
+            delete ctx;
+            return SAM_ERR_HIP;
+        }
+    }
+    *out = ctx;
+    return SAM_OK;
+}
+
+sam_status sam_destroy(sam_ctx* ctx) {
+    if (!ctx) return SAM_OK;
+    if (ctx->device != SAM_NO_DEVICE) {
+        (void)hipSetDevice(ctx->device);
+        (void)hipDeviceSynchronize();
+        if (ctx->d_status) (void)hipFree(ctx->d_status);
+        release(ctx->ws);
+        release(ctx->S_cp);
+        release(ctx->S_ri);
+    }
+    delete ctx;
+    return SAM_OK;
+}
+
+const char* sam_last_error(const sam_ctx* ctx) { return ctx ? ctx->err.c_str() : "context is NULL"; }
+
+sam_status sam_sync_status(sam_ctx* ctx, sam_stream_t stream, int32_t* first_bad_col) {
+    if (check_ctx(ctx)) return SAM_ERR_ARG;
+    if (first_bad_col) *first_bad_col = -1;
+    sam_status st = need_device(ctx);
+    if (st) return st;
+    unsigned long long v = kStatusClear;
+    HIP_TRY(ctx, hipStreamSynchronize(S(stream)));
+    HIP_TRY(ctx, hipMemcpy(&v, ctx->d_status, sizeof v, hipMemcpyDeviceToHost));
+    unsigned long long clear = kStatusClear;
+    HIP_TRY(ctx, hipMemcpy(ctx->d_status, &clear, sizeof clear, hipMemcpyHostToDevice));
+    if (v == kStatusClear) return SAM_OK;
+    const int code = (int)(v & 0xff);
+    const int col = (int)(v >> 8);
+    if (first_bad_col) *first_bad_col = col;
+    const char* what = code == SAM_ERR_RANK        ? "numerically rank deficient column block"
+                       : code == SAM_ERR_NONFINITE ? "non-finite value"
+                       : code == SAM_ERR_UNSORTED  ? "index outside [0, n) in the structure"
+                                                   : "kernel failure";
+    return fail(ctx, (sam_status)code, "%s at column %d", what, col);
+}
+
+sam_status sam_check_csc(sam_ctx* ctx, const sam_csc* A, sam_stream_t stream) {
+    if (check_ctx(ctx)) return SAM_ERR_ARG;
+    sam_status st = check_csc_args(ctx, A, "A", false);
+    if (st) return st;
+    if ((st = need_device(ctx))) return st;
+    hipStream_t s = S(stream);
+    HIP_TRY(ctx, grow(ctx->ws, 256));
+    int* bad = (int*)ctx->ws.p;
+    int h = A->n;
+    HIP_TRY(ctx, hipMemcpyAsync(bad, &h, sizeof h, hipMemcpyHostToDevice, s));
+    HIP_TRY(ctx, samk::check_csc(A->n, A->nnz, A->colptr, A->rowind, bad, s));
+    HIP_TRY(ctx, hipMemcpyAsync(&h, bad, sizeof h, hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, hipStreamSynchronize(s));
+    if (h != A->n) return fail(ctx, SAM_ERR_UNSORTED, "invalid CSC structure at column %d", h);
+    return SAM_OK;
+}
+
+sam_status sam_pattern_count(sam_ctx* ctx, const sam_csc* Ak, const sam_pattern_spec* spec, int64_t* nnz_S,
+                             sam_stream_t stream) {
+    if (check_ctx(ctx)) return SAM_ERR_ARG;
+    sam_status st;
+    if ((st = check_csc_args(ctx, Ak, "Ak", spec && spec->kind != SAM_SPARSIFY_NONE))) return st;
+    if ((st = check_spec(ctx, spec))) return st;
+    if (!nnz_S) return fail(ctx, SAM_ERR_ARG, "nnz_S is NULL");
+    if ((st = need_device(ctx))) return st;
+    ctx->S_nnz = -1;
+    int64_t nnz = 0;
+    st = compute_pattern(ctx, Ak, spec, ctx->S_cp, ctx->S_ri, &nnz, S(stream));
+    if (st) return st;
+    ctx->S_nnz = nnz;
+    ctx->S_n = Ak->n;
+    ctx->key_cp = Ak->colptr;
+    ctx->key_ri = Ak->rowind;
+    ctx->key_val = Ak->val;
+    ctx->key_spec = *spec;
+    *nnz_S = nnz;
+    return SAM_OK;
+}
+
+sam_status sam_pattern_fill(sam_ctx* ctx, const sam_csc* Ak, const sam_pattern_spec* spec, int32_t* S_colptr,
+                            int32_t* S_rowind, sam_stream_t stream) {
+    if (check_ctx(ctx)) return SAM_ERR_ARG;
+    sam_status st;
+    if ((st = check_csc_args(ctx, Ak, "Ak", false))) return st;
+    if ((st = check_spec(ctx, spec))) return st;
+    if (!S_colptr || (!S_rowind && ctx->S_nnz != 0)) return fail(ctx, SAM_ERR_ARG, "output array is NULL");
+    if ((st = need_device(ctx))) return st;
+    if (ctx->S_nnz < 0 || ctx->S_n != Ak->n || ctx->key_cp != Ak->colptr || ctx->key_ri != Ak->rowind ||
+        ctx->key_val != Ak->val || memcmp(&ctx->key_spec, spec, sizeof *spec) != 0)
+        return fail(ctx, SAM_ERR_ARG, "sam_pattern_fill must follow sam_pattern_count with the same Ak and spec");
+    hipStream_t s = S(stream);
+    HIP_TRY(ctx, hipMemcpyAsync(S_colptr, ctx->S_cp.p, (size_t)(Ak->n + 1) * 4, hipMemcpyDeviceToDevice, s));
+    if (ctx->S_nnz > 0)
+        HIP_TRY(ctx, hipMemcpyAsync(S_rowind, ctx->S_ri.p, (size_t)ctx->S_nnz * 4, hipMemcpyDeviceToDevice, s));
+    return SAM_OK;
+}
+
+sam_status sam_plan_create(sam_ctx* ctx, const sam_csc* Ak, const sam_csc* A0, const int32_t* S_colptr,
+                           const int32_t* S_rowind, int64_t nnz_S, sam_plan** plan, sam_stream_t stream) {
+    if (check_ctx(ctx)) return SAM_ERR_ARG;
+    sam_status st;
+    if (!plan) return fail(ctx, SAM_ERR_ARG, "plan is NULL");
+    *plan = nullptr;
+    if ((st = check_csc_args(ctx, Ak, "Ak", false))) return st;
+    if ((st = check_csc_args(ctx, A0, "A0", false))) return st;
+    if (Ak->n != A0->n) return fail(ctx, SAM_ERR_SHAPE, "Ak is %d x %d but A0 is %d x %d", Ak->n, Ak->n, A0->n, A0->n);
+    if (nnz_S < 0) return fail(ctx, SAM_ERR_ARG, "nnz_S < 0");
+    if (nnz_S > INT_MAX) return fail(ctx, SAM_ERR_OVERFLOW, "nnz_S = %lld does not fit in int32", (long long)nnz_S);
+    if (!S_colptr || (nnz_S > 0 && !S_rowind)) return fail(ctx, SAM_ERR_ARG, "pattern array is NULL");
+    if ((st = need_device(ctx))) return st;
+    hipStream_t s = S(stream);
+    const int n = Ak->n;
+
+    sam_plan* pl = new (std::nothrow) sam_plan();
+    if (!pl) return fail(ctx, SAM_ERR_NOMEM, "host allocation failed");
+    pl->ctx = ctx;
+    pl->n = n;
+    pl->nnzA = Ak->nnz;
+    pl->nnzA0 = A0->nnz;
+    pl->nnzS = nnz_S;
+    pl->Ak_cp = Ak->colptr;
+    pl->Ak_ri = Ak->rowind;
+    pl->A0_cp = A0->colptr;
+    pl->A0_ri = A0->rowind;
+    pl->S_cp = S_colptr;
+    pl->S_ri = S_rowind;
+    auto bail = [&](sam_status code) {
+        release(pl->mem);
+        delete pl;
+        return code;
+    };
+
+    // pass 1: gathered entries per column -> eoff (host needs E)
+    size_t tmp_need = align256((size_t)n * 4) + align256((size_t)(n + 1) * 8) + align256(samk::scan_temp_bytes(n)) +
+                      align256(samk::bucket_temp_bytes(n)) + 1024;
+    hipError_t he = grow(ctx->ws, tmp_need);
+    if (he != hipSuccess) return bail(fail(ctx, SAM_ERR_NOMEM, "workspace: %s", hipGetErrorString(he)));
+    Carve tw(ctx->ws.p);
+    int* counts = tw.take<int>(n);
+    int64_t* off = tw.take<int64_t>(n + 1);
+    void* stemp = tw.take<char>(samk::scan_temp_bytes(n));
+    void* btemp = tw.take<char>(samk::bucket_temp_bytes(n));
+    int* flags = tw.take<int>(4);
+
+    int64_t E = 0;
+    if (n > 0) {
+        if ((he = samk::plan_gather_count(n, S_colptr, S_rowind, Ak->colptr, counts, s)) != hipSuccess ||
+            (he = samk::scan_counts(counts, n, off, nullptr, nullptr, stemp, s)) != hipSuccess ||
+            (he = read_back(off + n, &E, s)) != hipSuccess)
+            return bail(fail(ctx, SAM_ERR_HIP, "plan count: %s", hipGetErrorString(he)));
+    }
+    pl->E = E;
+    size_t mem = align256((size_t)n * 4) + align256((size_t)(n + 1) * 8) + align256((size_t)std::max<int64_t>(E, 1)) +
+                 align256((size_t)std::max(A0->nnz, 1)) + 4 * (align256((size_t)n * 4) + align256(64 * 4)) +
+                 align256((size_t)n * 8) + align256(samk::reduce_temp_bytes(n)) + 1024;
+    if ((he = grow(pl->mem, mem)) != hipSuccess)
+        return bail(fail(ctx, SAM_ERR_NOMEM, "plan memory (%zu bytes): %s", mem, hipGetErrorString(he)));
+    Carve cv(pl->mem.p);
+    pl->nI = cv.take<int>(n);
+    pl->eoff = cv.take<int64_t>(n + 1);
+    pl->posA = cv.take<unsigned char>((size_t)std::max<int64_t>(E, 1));
+    pl->posB = cv.take<unsigned char>((size_t)std::max(A0->nnz, 1));
+    for (int p = 0; p < 2; ++p)
+        for (int w = 0; w < 2; ++w) {
+            pl->combo[p][w].queue = cv.take<int>(n);
+            pl->combo[p][w].bstart = cv.take<int>(64);
+        }
+    pl->colbuf = cv.take<double>(n);
+    pl->rtemp = cv.take<char>(samk::reduce_temp_bytes(n));
+
+    if (n > 0) {
+        if ((he = hipMemcpyAsync(pl->eoff, off, (size_t)(n + 1) * 8, hipMemcpyDeviceToDevice, s)) != hipSuccess ||
+            (he = samk::plan_positions(n, S_colptr, S_rowind, Ak->colptr, Ak->rowind, A0->colptr, A0->rowind,
+                                       pl->eoff, pl->nI, pl->posA, pl->posB, s)) != hipSuccess)
+            return bail(fail(ctx, SAM_ERR_HIP, "plan positions: %s", hipGetErrorString(he)));
+        // shape statistics (host)
+        std::vector<int> hnI(n), hcp(n + 1);
+        if ((he = hipMemcpyAsync(hnI.data(), pl->nI, (size_t)n * 4, hipMemcpyDeviceToHost, s)) != hipSuccess ||
+            (he = hipMemcpyAsync(hcp.data(), S_colptr, (size_t)(n + 1) * 4, hipMemcpyDeviceToHost, s)) != hipSuccess ||
+            (he = hipStreamSynchronize(s)) != hipSuccess)
+            return bail(fail(ctx, SAM_ERR_HIP, "plan stats: %s", hipGetErrorString(he)));
+        if (hcp[0] != 0 || hcp[n] != nnz_S)
+            return bail(fail(ctx, SAM_ERR_SHAPE, "S_colptr[0] = %d, S_colptr[n] = %d but nnz_S = %lld", hcp[0], hcp[n],
+                             (long long)nnz_S));
+        for (int j = 0; j < n; ++j) {
+            if (hcp[j + 1] < hcp[j])
+                return bail(fail(ctx, SAM_ERR_UNSORTED, "S_colptr decreases at column %d", j));
+            pl->max_rows = std::max(pl->max_rows, hnI[j]);
+            pl->max_cols = std::max(pl->max_cols, hcp[j + 1] - hcp[j]);
+        }
+        for (int p = 0; p < 2; ++p)
+            for (int w = 0; w < 2; ++w)
+                if ((st = plan_combo(pl, p, w, btemp, flags, s))) return bail(st);
+    }
+    *plan = pl;
+    return SAM_OK;
+}
+
+sam_status sam_plan_destroy(sam_plan* plan) {
+    if (!plan) return SAM_OK;
+    if (plan->ctx && plan->ctx->device != SAM_NO_DEVICE) (void)hipSetDevice(plan->ctx->device);
+    release(plan->mem);
+    release(plan->bwd);
+    delete plan;
+    return SAM_OK;
+}
+
+sam_status sam_plan_info(const sam_plan* plan, int32_t* n, int32_t* max_rows, int32_t* max_cols, int64_t* gathered,
+                         int32_t* nbuckets, int32_t* bucket_cols) {
+    if (!plan) return SAM_ERR_ARG;
+    if (n) *n = plan->n;
+    if (max_rows) *max_rows = plan->max_rows;
+    if (max_cols) *max_cols = plan->max_cols;
+    if (gathered) *gathered = plan->E;
+    const Combo& cb = plan->combo[1][0];
+    if (nbuckets) *nbuckets = (int)cb.counts.size();
+    if (bucket_cols)
+        for (size_t b = 0; b < cb.counts.size() && b < 16; ++b) bucket_cols[b] = cb.counts[b];
+    return SAM_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Launch every non-empty bucket of a combination, then the column-residual sum.
+sam_status run_numeric(sam_plan* pl, const double* Ak_val, const double* A0_val, const double* w, double mu, int prec,
+                       int weighted, void* M_val, double* col_res2, double* res2, hipStream_t s) {
+    sam_ctx* ctx = pl->ctx;
+    Combo& cb = pl->combo[prec][weighted];
+    if (!cb.ok) return fail(ctx, SAM_ERR_UNSUPPORTED, "%s", cb.why.c_str());
+    NumericArgs a{};
+    a.n = pl->n;
+    a.Ak_cp = pl->Ak_cp;
+    a.Ak_v = Ak_val;
+    a.A0_cp = pl->A0_cp;
+    a.A0_v = A0_val;
+    a.S_cp = pl->S_cp;
+    a.S_ri = pl->S_ri;
+    a.nI = pl->nI;
+    a.eoff = pl->eoff;
+    a.posA = pl->posA;
+    a.posB = pl->posB;
+    a.queue = cb.queue;
+    a.bstart = cb.bstart;
+    a.M = M_val;
+    double* cols = col_res2 ? col_res2 : pl->colbuf;
+    a.col_res2 = cols;
+    a.status = ctx->d_status;
+    a.w = w;
+    a.mu = mu;
+    for (size_t b = 0; b < cb.variants.size(); ++b) {
+        const int cnt = cb.counts[b];
+        if (cnt <= 0) continue;
+        const NumericVariant* v = cb.variants[b];
+        a.bucket = (int)b;
+        int groups = (cnt + v->per_wave() - 1) / v->per_wave();
+        int cap = ctx->CUs * 16;
+        int grid = std::min(groups, cap);
+        if (grid >= 64) grid = grid / 8 * 8;
+        HIP_TRY(ctx, v->launch(a, grid, s));
+    }
+    if (res2 && pl->n > 0) HIP_TRY(ctx, samk::reduce_sum(cols, pl->n, res2, pl->rtemp, s));
+    if (res2 && pl->n == 0) HIP_TRY(ctx, hipMemsetAsync(res2, 0, sizeof(double), s));
+    return SAM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+sam_status sam_build_planned(sam_plan* plan, const double* Ak_val, const double* A0_val, sam_precision prec,
+                             void* M_val, double* col_res2, double* res2, sam_stream_t stream) {
+    if (!plan || !plan->ctx) return SAM_ERR_ARG;
+    sam_ctx* ctx = plan->ctx;
+    check_ctx(ctx);
+    if (!prec_ok(prec)) return fail(ctx, SAM_ERR_ARG, "unknown precision %d", (int)prec);
+    if ((plan->nnzA > 0 && !Ak_val) || (plan->nnzA0 > 0 && !A0_val)) return fail(ctx, SAM_ERR_ARG, "value array is NULL");
+    if (plan->nnzS > 0 && !M_val) return fail(ctx, SAM_ERR_ARG, "M_val is NULL");
+    sam_status st = need_device(ctx);
+    if (st) return st;
+    return run_numeric(plan, Ak_val, A0_val, nullptr, 0.0, prec == SAM_PREC_F32_REFINE ? 1 : 0, 0, M_val, col_res2,
+                       res2, S(stream));
+}
+
+sam_status sam_build(sam_ctx* ctx, const sam_csc* Ak, const sam_csc* A0, const int32_t* S_colptr,
+                     const int32_t* S_rowind, int64_t nnz_S, sam_precision prec, void* M_val, double* col_res2,
+                     double* res2, sam_stream_t stream) {
+    if (check_ctx(ctx)) return SAM_ERR_ARG;
+    sam_status st;
+    if ((st = check_csc_args(ctx, Ak, "Ak", true))) return st;
+    if ((st = check_csc_args(ctx, A0, "A0", true))) return st;
+    if (!prec_ok(prec)) return fail(ctx, SAM_ERR_ARG, "unknown precision %d", (int)prec);
+    if (nnz_S > 0 && !M_val) return fail(ctx, SAM_ERR_ARG, "M_val is NULL");
+    sam_plan* pl = nullptr;
+    if ((st = sam_plan_create(ctx, Ak, A0, S_colptr, S_rowind, nnz_S, &pl, stream))) return st;
+    st = sam_build_planned(pl, Ak->val, A0->val, prec, M_val, col_res2, res2, stream);
+    hipError_t e = hipStreamSynchronize(S(stream));
+    sam_plan_destroy(pl);
+    if (st) return st;
+    if (e != hipSuccess) return fail(ctx, SAM_ERR_HIP, "sam_build: %s", hipGetErrorString(e));
+    return SAM_OK;
+}
+
+sam_status sam_residual(sam_ctx* ctx, const sam_csc* Ak, const sam_csc* A0, const int32_t* M_colptr,
+                        const int32_t* M_rowind, int64_t nnz_M, const void* M_val, sam_precision prec, double* res2,
+                        double* a02, sam_stream_t stream) {
+    if (check_ctx(ctx)) return SAM_ERR_ARG;
+    sam_status st;
+    if ((st = check_csc_args(ctx, Ak, "Ak", true))) return st;
+    if ((st = check_csc_args(ctx, A0, "A0", true))) return st;
+    if (Ak->n != A0->n) return fail(ctx, SAM_ERR_SHAPE, "Ak and A0 differ in order");
+    if (!prec_ok(prec)) return fail(ctx, SAM_ERR_ARG, "unknown precision %d", (int)prec);
+    if (!M_colptr || (nnz_M > 0 && (!M_rowind || !M_val)) || !res2) return fail(ctx, SAM_ERR_ARG, "NULL argument");
+    if (nnz_M < 0 || nnz_M > INT_MAX) return fail(ctx, SAM_ERR_OVERFLOW, "nnz_M out of range");
+    if ((st = need_device(ctx))) return st;
+    hipStream_t s = S(stream);
+    const int n = Ak->n;
+    const size_t need = align256((size_t)std::max(n, 1) * 8) + align256(samk::reduce_temp_bytes(std::max<int64_t>(n, A0->nnz))) + 512;
+    HIP_TRY(ctx, grow(ctx->ws, need));
+    Carve cv(ctx->ws.p);
+    double* cols = cv.take<double>(std::max(n, 1));
+    void* rt = cv.take<char>(samk::reduce_temp_bytes(std::max<int64_t>(n, A0->nnz)));
+    if (n == 0) {
+        HIP_TRY(ctx, hipMemsetAsync(res2, 0, sizeof(double), s));
+        if (a02) HIP_TRY(ctx, hipMemsetAsync(a02, 0, sizeof(double), s));
+        return SAM_OK;
+    }
+    HIP_TRY(ctx, samk::residual_columns(n, Ak->colptr, Ak->rowind, Ak->val, A0->colptr, A0->rowind, A0->val, M_colptr,
+                                        M_rowind, M_val, prec == SAM_PREC_F32_REFINE, cols, ctx->d_status, s));
+    HIP_TRY(ctx, samk::reduce_sum(cols, n, res2, rt, s));
+    if (a02) HIP_TRY(ctx, samk::reduce_sumsq(A0->val, A0->nnz, a02, rt, s));
+    return SAM_OK;
+}
+
+sam_status sam_apply_prepare(sam_ctx* ctx, int32_t n, const int32_t* M_colptr, const int32_t* M_rowind, int64_t nnz,
+                             int32_t* T_rowptr, int32_t* T_colind, int32_t* T_perm, sam_stream_t stream) {
+    if (check_ctx(ctx)) return SAM_ERR_ARG;
+    if (n < 0 || nnz < 0) return fail(ctx, SAM_ERR_ARG, "negative size");
+    if (nnz > INT_MAX) return fail(ctx, SAM_ERR_OVERFLOW, "nnz does not fit in int32");
+    if (!M_colptr || !T_rowptr || (nnz > 0 && (!M_rowind || !T_colind || !T_perm)))
+        return fail(ctx, SAM_ERR_ARG, "NULL argument");
+    sam_status st = need_device(ctx);
+    if (st) return st;
+    hipStream_t s = S(stream);
+    const size_t need = 2 * align256((size_t)std::max(n, 1) * 4) + align256((size_t)(n + 1) * 8) +
+                        align256(samk::scan_temp_bytes(n)) + 512;
+    HIP_TRY(ctx, grow(ctx->ws, need));
+    Carve cv(ctx->ws.p);
+    int* rowcount = cv.take<int>(std::max(n, 1));
+    int* cursor = cv.take<int>(std::max(n, 1));
+    int64_t* off = cv.take<int64_t>(n + 1);
+    void* stemp = cv.take<char>(samk::scan_temp_bytes(n));
+    HIP_TRY(ctx, hipMemsetAsync(rowcount, 0, (size_t)std::max(n, 1) * 4, s));
+    HIP_TRY(ctx, hipMemsetAsync(cursor, 0, (size_t)std::max(n, 1) * 4, s));
+    HIP_TRY(ctx, samk::transpose_count(n, M_colptr, M_rowind, nnz, rowcount, s));
+    HIP_TRY(ctx, samk::scan_counts(rowcount, n, off, T_rowptr, nullptr, stemp, s));
+    HIP_TRY(ctx, samk::transpose_fill(n, M_colptr, M_rowind, T_rowptr, cursor, T_colind, T_perm, s));
+    HIP_TRY(ctx, samk::transpose_sort_rows(n, T_rowptr, T_colind, T_perm, s));
+    HIP_TRY(ctx, hipStreamSynchronize(s));
+    return SAM_OK;
+}
+
+sam_status sam_apply(sam_ctx* ctx, int32_t n, const int32_t* T_rowptr, const int32_t* T_colind, const int32_t* T_perm,
+                     const void* M_val, sam_precision prec, const double* x, double* y, sam_stream_t stream) {
+    if (check_ctx(ctx)) return SAM_ERR_ARG;
+    if (n < 0) return fail(ctx, SAM_ERR_ARG, "negative size");
+    if (!prec_ok(prec)) return fail(ctx, SAM_ERR_ARG, "unknown precision %d", (int)prec);
+    if (n > 0 && (!T_rowptr || !T_colind || !T_perm || !M_val || !x || !y)) return fail(ctx, SAM_ERR_ARG, "NULL argument");
+    sam_status st = need_device(ctx);
+    if (st) return st;
+    HIP_TRY(ctx, samk::spmv_rows(n, T_rowptr, T_colind, T_perm, M_val, prec == SAM_PREC_F32_REFINE, x, y, S(stream)));
+    return SAM_OK;
+}
+
+}  // extern "C"
+
+extern "C" {
+
+sam_status sam_build_weighted(sam_plan* plan, const double* Ak_val, const double* A0_val, const double* w, double mu,
+                              sam_precision prec, void* M_val, double* col_res2, double* res2, sam_stream_t stream) {
+    if (!plan || !plan->ctx) return SAM_ERR_ARG;
+    sam_ctx* ctx = plan->ctx;
+    check_ctx(ctx);
+    if (!prec_ok(prec)) return fail(ctx, SAM_ERR_ARG, "unknown precision %d", (int)prec);
+    if ((plan->nnzA > 0 && !Ak_val) || (plan->nnzA0 > 0 && !A0_val)) return fail(ctx, SAM_ERR_ARG, "value array is NULL");
+    if (plan->nnzS > 0 && (!M_val || !w)) return fail(ctx, SAM_ERR_ARG, "M_val or w is NULL");
+    if (!(mu >= 0.0)) return fail(ctx, SAM_ERR_ARG, "mu must be >= 0 (got %g)", mu);
+    sam_status st = need_device(ctx);
+    if (st) return st;
+    return run_numeric(plan, Ak_val, A0_val, w, mu, prec == SAM_PREC_F32_REFINE ? 1 : 0, 1, M_val, col_res2, res2,
+                       S(stream));
+}
+
+}  // extern "C"

@@ -1,0 +1,155 @@
+// sam_kernels.hpp -- host-side launchers of the gfx950 kernels (internal to
+// the library; the public interface is include/sam.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace samk {
+
+// ----------------------------------------------------------------- scans
+// Exclusive prefix sum of n int32 counts into int64 offsets (n+1 entries,
+// off[n] = total).  Optionally also writes the int32 copy (n+1) and raises
+// *overflow (device int) when the total does not fit in int32.  Needs
+// scan_temp_bytes(n) bytes of temporary device memory.
+size_t scan_temp_bytes(int64_t n);
+hipError_t scan_counts(const int* counts, int64_t n, int64_t* off, int* off32, int* overflow,
+                       void* temp, hipStream_t s);
+
+// ------------------------------------------------------------- structure
+// Checks of a CSC structure; writes the earliest bad column to *bad
+// (device int, must be preset to n by the caller; stays n when valid).
+hipError_t check_csc(int n, int nnz, const int* cp, const int* ri, int* bad, hipStream_t s);
+
+// ------------------------------------------------------------- patterns
+struct SparsifySpec {
+    int kind;
+    double thresh;
+    int global_scale;
+    double tau;
+    int lfil;
+};
+// B = S(A~) with the diagonal: count (counts[n]) then fill.
+hipError_t sparsify_count(int n, const int* cp, const int* ri, const double* v,
+                          SparsifySpec sp, double* dscratch, int* counts, hipStream_t s);
+hipError_t sparsify_fill(int n, const int* cp, const int* ri, const double* v,
+                         SparsifySpec sp, const double* dscratch, const int* out_cp,
+                         int* out_ri, hipStream_t s);
+// out(:,j) = union of rows(Q(:,l)) over l in P(:,j); count then fill.
+hipError_t expand_count(int n, const int* P_cp, const int* P_ri, const int* Q_cp, const int* Q_ri,
+                        int* counts, int* bad, hipStream_t s);
+hipError_t expand_fill(int n, const int* P_cp, const int* P_ri, const int* Q_cp, const int* Q_ri,
+                       const int* out_cp, int* out_ri, hipStream_t s);
+
+// ------------------------------------------------------------------ plan
+// Per column j: E_j = sum_{l in J_j} nnz(A_k(:,l)).
+hipError_t plan_gather_count(int n, const int* S_cp, const int* S_ri, const int* Ak_cp,
+                             int* counts, hipStream_t s);
+// Per column j: nI[j] = |I_j|, positions of the gathered A_k entries (posA,
+// at eoff[j]) and of the A_0(:,j) entries (posB aligned with A_0's entries,
+// 0xFF outside I_j).  Columns with |I_j| > 255 get nI = |I_j| and no
+// positions (they are rejected by the bucket classifier).
+hipError_t plan_positions(int n, const int* S_cp, const int* S_ri, const int* Ak_cp,
+                          const int* Ak_ri, const int* A0_cp, const int* A0_ri,
+                          const int64_t* eoff, int* nI, unsigned char* posA,
+                          unsigned char* posB, hipStream_t s);
+
+constexpr int kMaxBuckets = 16;
+struct BucketTable {
+    int nb;
+    int rows_plus_cols;   // 1: a column needs |I_j| + |J_j| rows (penalty rows)
+    int max_rows[kMaxBuckets];
+    int max_cols[kMaxBuckets];
+};
+// Stable counting sort of the columns by bucket: queue[] lists the columns
+// of bucket 0, then bucket 1, ...; bstart[b] (device, nb+1) are the bucket
+// offsets.  Columns that fit no bucket raise *unfit (device int, = count).
+size_t bucket_temp_bytes(int n);
+hipError_t bucket_sort(int n, const int* S_cp, const int* nI, BucketTable tab, int* queue,
+                       int* bstart, int* unfit, void* temp, hipStream_t s);
+
+// --------------------------------------------------------------- numeric
+struct NumericArgs {
+    int n;
+    const int* Ak_cp;
+    const double* Ak_v;
+    const int* A0_cp;
+    const double* A0_v;
+    const int* S_cp;
+    const int* S_ri;
+    const int* nI;
+    const int64_t* eoff;
+    const unsigned char* posA;
+    const unsigned char* posB;
+    const int* queue;     // all buckets' columns
+    const int* bstart;    // device, bucket offsets
+    int bucket;           // which bucket this launch serves
+    void* M;
+    double* col_res2;     // n or nullptr
+    unsigned long long* status;
+    // soft weights (nullptr for the plain map)
+    const double* w;
+    double mu;
+};
+
+// One kernel variant of the menu: solves every column of one bucket whose
+// block fits max_rows x max_cols.
+struct NumericVariant {
+    int prec;        // 0 = FP64, 1 = FP32 + refinement
+    int G;           // lanes per column problem
+    int R;           // rows per lane
+    int NC;          // max columns
+    int weighted;    // 1: stacked penalty rows
+    hipError_t (*launch)(const NumericArgs&, int grid, hipStream_t);
+    int max_rows() const { return G * R; }
+    int per_wave() const { return 64 / G; }
+};
+// The compiled menu, ordered from the cheapest per column to the most
+// general for each precision.
+const NumericVariant* numeric_menu(int* count);
+
+// Deterministic sums: out[0] = sum_i x[i] (fixed tree order).  Needs
+// reduce_temp_bytes(n).
+size_t reduce_temp_bytes(int64_t n);
+hipError_t reduce_sum(const double* x, int64_t n, double* out, void* temp, hipStream_t s);
+// out[0] = sum of squares of x (fixed order)
+hipError_t reduce_sumsq(const double* x, int64_t n, double* out, void* temp, hipStream_t s);
+
+// -------------------------------------------------------------- residual
+// Per column: rho_j = ||A_k(:,J_j) m_j - A_0(:,j)||^2 computed explicitly.
+hipError_t residual_columns(int n, const int* Ak_cp, const int* Ak_ri, const double* Ak_v,
+                            const int* A0_cp, const int* A0_ri, const double* A0_v,
+                            const int* M_cp, const int* M_ri, const void* M_v, int m_is_f32,
+                            double* col_out, unsigned long long* status, hipStream_t s);
+
+// ----------------------------------------------------------------- apply
+hipError_t transpose_count(int n, const int* cp, const int* ri, int64_t nnz, int* rowcount,
+                           hipStream_t s);
+hipError_t transpose_fill(int n, const int* cp, const int* ri, const int* rowptr, int* cursor,
+                          int* colind, int* perm, hipStream_t s);
+hipError_t transpose_sort_rows(int n, const int* rowptr, int* colind, int* perm, hipStream_t s);
+hipError_t spmv_rows(int n, const int* rowptr, const int* colind, const int* perm,
+                     const void* val, int val_f32, const double* x, double* y, hipStream_t s);
+
+// ---------------------------------------------------------------- adjoint
+struct BackwardArgs {
+    NumericArgs fw;        // forward arguments (w, mu set)
+    double dL;
+    double* contrib;       // staging: per gathered entry (eoff order)
+    double* gA0;           // nnz(A_0)
+    double* gw;            // nnz_S or nullptr
+};
+struct BackwardVariant {
+    int G, R, NC;
+    hipError_t (*launch)(const BackwardArgs&, int grid, hipStream_t);
+    int max_rows() const { return G * R; }
+    int per_wave() const { return 64 / G; }
+};
+const BackwardVariant* backward_menu(int* count);
+// gAk[e] = sum over the S entries (l, j) with l = column of e of the staged
+// contribution of column j to entry e, in ascending j (uses the row view of S).
+hipError_t backward_scatter(int n, const int* Ak_cp, const int* ST_rowptr, const int* ST_colind,
+                            const int* ST_perm, const int* S_cp, const int64_t* eoff,
+                            const double* contrib, double* gAk, hipStream_t s);
+
+}  // namespace samk

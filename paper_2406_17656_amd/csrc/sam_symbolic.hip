@@ -1,0 +1,585 @@
+// sam_symbolic.hip -- integer (symbolic) kernels of the SAM library for
+// gfx950: prefix sums, CSC structure checks, the sparsification rules and
+// level expansion that form the pattern S (Sections 3-4 of the paper), and
+// the plan of the column problems (row sets, gather positions, buckets).
+//
+// Row-set construction uses a per-wave LDS bitmap over the window of
+// candidate rows: every candidate sets its bit (ds_or), and the ascending
+// union, its size and the rank of any row inside it follow from popcounts,
+// with no sort.  Windows wider than the bitmap are processed in chunks.
+#include "sam_device.hpp"
+#include "sam_kernels.hpp"
+
+#include <algorithm>
+#include <climits>
+
+namespace samk {
+
+namespace {
+
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 4;
+constexpr int kScanTile = kScanThreads * kScanItems;
+
+__device__ inline int64_t block_exclusive_scan(int64_t v, int64_t* sh, int64_t* total) {
+    // Hillis-Steele over kScanThreads values in LDS
+    const int t = threadIdx.x;
+    sh[t] = v;
+    __syncthreads();
+    for (int d = 1; d < kScanThreads; d <<= 1) {
+        int64_t add = t >= d ? sh[t - d] : 0;
+        __syncthreads();
+        sh[t] += add;
+        __syncthreads();
+    }
+    int64_t incl = sh[t];
+    *total = sh[kScanThreads - 1];
+    __syncthreads();
+    return incl - v;
+}
+
+// Scans in[0..N) where in[i] = i < n_in ? src[i] : 0 (the last virtual zero
+// gives the total at off[n_in]).
+template <typename Tin>
+__global__ void __launch_bounds__(kScanThreads)
+k_scan_local(const Tin* src, int64_t n_in, int64_t N, int64_t* out, int64_t* block_tot) {
+    __shared__ int64_t sh[kScanThreads];
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    int64_t v[kScanItems];
+    int64_t s = 0;
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) {
+        int64_t idx = base + i;
+        v[i] = (idx < n_in) ? (int64_t)src[idx] : 0;
+        s += v[i];
+    }
+    int64_t tot;
+    int64_t pre = block_exclusive_scan(s, sh, &tot);
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) {
+        int64_t idx = base + i;
+        if (idx < N) out[idx] = pre;
+        pre += v[i];
+    }
+    if (threadIdx.x == 0) block_tot[blockIdx.x] = tot;
+}
+
+__global__ void k_scan_add(int64_t* out, int64_t N, const int64_t* block_off) {
+    const int64_t i = (int64_t)blockIdx.x * kScanTile + threadIdx.x;
+    const int64_t add = block_off[blockIdx.x];
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        int64_t idx = i + (int64_t)k * kScanThreads;
+        if (idx < N) out[idx] += add;
+    }
+}
+
+__global__ void k_to_i32(const int64_t* off, int64_t N, int* off32, int* overflow) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < N) {
+        int64_t v = off[i];
+        if (off32) off32[i] = (int)v;
+        if (v > INT_MAX && overflow) atomicOr(overflow, 1);
+    }
+}
+
+int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+}  // namespace
+
+size_t scan_temp_bytes(int64_t n) {
+    int64_t N = n + 1;
+    size_t bytes = 0;
+    while (true) {
+        int64_t nb = ceil_div(N, kScanTile);
+        bytes += (size_t)(2 * nb + 1) * sizeof(int64_t);
+        if (nb <= 1) break;
+        N = nb;
+    }
+    return bytes + 256;
+}
+
+// Recursive three-phase scan.  Level buffers live in `temp`.
+static hipError_t scan_i64_levels(int64_t* out, int64_t N, int64_t* temp, hipStream_t s);
+
+template <typename Tin>
+static hipError_t scan_any(const Tin* src, int64_t n_in, int64_t N, int64_t* out, int64_t* temp,
+                           hipStream_t s) {
+    const int64_t nb = ceil_div(N, kScanTile);
+    int64_t* tot = temp;
+    int64_t* totoff = temp + nb;
+    hipLaunchKernelGGL(k_scan_local<Tin>, dim3((unsigned)nb), dim3(kScanThreads), 0, s, src, n_in, N,
+                       out, tot);
+    if (nb > 1) {
+        // exclusive scan of the block totals (nb values, one virtual zero not needed)
+        hipError_t e = scan_any<int64_t>(tot, nb, nb, totoff, temp + 2 * nb + 1, s);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_scan_add, dim3((unsigned)nb), dim3(kScanThreads), 0, s, out, N, totoff);
+    }
+    return hipGetLastError();
+}
+
+static hipError_t scan_i64_levels(int64_t* out, int64_t N, int64_t* temp, hipStream_t s) {
+    return scan_any<int64_t>(out, N, N, out, temp, s);
+}
+
+hipError_t scan_counts(const int* counts, int64_t n, int64_t* off, int* off32, int* overflow,
+                       void* temp, hipStream_t s) {
+    const int64_t N = n + 1;
+    hipError_t e = scan_any<int>(counts, n, N, off, (int64_t*)temp, s);
+    if (e != hipSuccess) return e;
+    if (off32 || overflow) {
+        hipLaunchKernelGGL(k_to_i32, dim3((unsigned)ceil_div(N, 256)), dim3(256), 0, s, off, N, off32,
+                           overflow);
+    }
+    return hipGetLastError();
+}
+
+// ----------------------------------------------------------------- checks
+
+__global__ void k_check_csc(int n, int nnz, const int* cp, const int* ri, int* bad) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    const int a = cp[j], b = cp[j + 1];
+    bool ok = a >= 0 && a <= b && b <= nnz;
+    if (j == 0 && a != 0) ok = false;
+    if (j == n - 1 && b != nnz) ok = false;
+    if (ok) {
+        int prev = -1;
+        for (int e = a; e < b; ++e) {
+            int r = ri[e];
+            if (r <= prev || r >= n) { ok = false; break; }
+            prev = r;
+        }
+    }
+    if (!ok) atomicMin(bad, j);
+}
+
+hipError_t check_csc(int n, int nnz, const int* cp, const int* ri, int* bad, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_check_csc, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s, n, nnz, cp, ri,
+                       bad);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------ sparsify
+
+// D_jj = |a_jj| if nonzero, else 1 (Section 4, definition of D).
+__global__ void k_diag_scale(int n, const int* cp, const int* ri, const double* v, double* D) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    double d = 0.0;
+    for (int e = cp[j]; e < cp[j + 1]; ++e)
+        if (ri[e] == j) d = fabs(v[e]);
+    D[j] = d > 0.0 ? d : 1.0;
+}
+
+// Decision for entry e of column j (the diagonal is handled by the caller).
+__device__ inline bool keep_entry(int j, int i, double a, const SparsifySpec& sp, const double* D,
+                                  double colmax, int rank_lfil) {
+    switch (sp.kind) {
+        case 0:
+            return true;
+        case 1: {
+            double s = sp.global_scale > 0 ? sqrt(D[i] * D[j]) : 1.0 / sqrt(D[i] * D[j]);
+            return fabs(a) * s > sp.thresh;
+        }
+        case 2:
+            return fabs(a) > (1.0 - sp.tau) * colmax;
+        default:
+            return rank_lfil < sp.lfil - 1;
+    }
+}
+
+// rank of off-diagonal entry e among the column's off-diagonals by
+// (magnitude descending, row ascending)
+__device__ inline int lfil_rank(int j, int a, int b, int e, const int* ri, const double* v) {
+    const double me = fabs(v[e]);
+    const int re = ri[e];
+    int rank = 0;
+    for (int f = a; f < b; ++f) {
+        int rf = ri[f];
+        if (rf == j || f == e) continue;
+        double mf = fabs(v[f]);
+        if (mf > me || (mf == me && rf < re)) ++rank;
+    }
+    return rank;
+}
+
+template <bool FILL>
+__global__ void k_sparsify(int n, const int* cp, const int* ri, const double* v, SparsifySpec sp,
+                           const double* D, int* counts, const int* out_cp, int* out_ri) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    const int a = cp[j], b = cp[j + 1];
+    double colmax = 0.0;
+    if (sp.kind == 2)
+        for (int e = a; e < b; ++e) colmax = fmax(colmax, fabs(v[e]));
+    int cnt = 0;
+    bool diag_done = false;
+    int o = FILL ? out_cp[j] : 0;
+    for (int e = a; e < b; ++e) {
+        const int i = ri[e];
+        bool keep;
+        if (i == j) {
+            keep = true;
+        } else {
+            int rk = sp.kind == 3 ? lfil_rank(j, a, b, e, ri, v) : 0;
+            keep = keep_entry(j, i, v ? v[e] : 0.0, sp, D, colmax, rk);
+        }
+        if (!diag_done && i > j) {  // diagonal not stored: insert before
+            if (FILL) out_ri[o + cnt] = j;
+            ++cnt;
+            diag_done = true;
+        }
+        if (i == j) diag_done = true;
+        if (keep) {
+            if (FILL) out_ri[o + cnt] = i;
+            ++cnt;
+        }
+    }
+    if (!diag_done) {
+        if (FILL) out_ri[o + cnt] = j;
+        ++cnt;
+    }
+    if (!FILL) counts[j] = cnt;
+}
+
+hipError_t sparsify_count(int n, const int* cp, const int* ri, const double* v, SparsifySpec sp,
+                          double* dscratch, int* counts, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const unsigned nb = (unsigned)ceil_div(n, 256);
+    if (sp.kind == 1) hipLaunchKernelGGL(k_diag_scale, dim3(nb), dim3(256), 0, s, n, cp, ri, v, dscratch);
+    hipLaunchKernelGGL(k_sparsify<false>, dim3(nb), dim3(256), 0, s, n, cp, ri, v, sp, dscratch, counts,
+                       nullptr, nullptr);
+    return hipGetLastError();
+}
+
+hipError_t sparsify_fill(int n, const int* cp, const int* ri, const double* v, SparsifySpec sp,
+                         const double* dscratch, const int* out_cp, int* out_ri, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const unsigned nb = (unsigned)ceil_div(n, 256);
+    hipLaunchKernelGGL(k_sparsify<true>, dim3(nb), dim3(256), 0, s, n, cp, ri, v, sp, dscratch, nullptr,
+                       out_cp, out_ri);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------- row-set bitmaps
+
+constexpr int kBmWords = 1024;              // 32768 rows per chunk
+constexpr int kBmBits = kBmWords * 32;
+constexpr int kWavesPerBlock = 4;
+
+__device__ inline int wave_min_i(int v) {
+    for (int d = 32; d >= 1; d >>= 1) v = min(v, __shfl_xor(v, d));
+    return v;
+}
+__device__ inline int wave_max_i(int v) {
+    for (int d = 32; d >= 1; d >>= 1) v = max(v, __shfl_xor(v, d));
+    return v;
+}
+__device__ inline int wave_sum_i(int v) {
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d);
+    return v;
+}
+__device__ inline int wave_excl_scan_i(int v) {
+    const int lane = wave_lane();
+    int x = v;
+    for (int d = 1; d < 64; d <<= 1) {
+        int y = __shfl_up(x, d);
+        if (lane >= d) x += y;
+    }
+    return x - v;
+}
+
+// Candidates of column j: rows of Q(:, l) for l in P(:, j).  Lane t handles
+// P entries t, t+64, ...  Returns the candidate row range through lo/hi
+// (lo > hi when empty) and flags out-of-range column indices.
+__device__ inline void candidate_range(int j, int n, const int* P_cp, const int* P_ri, const int* Q_cp,
+                                       const int* Q_ri, int* lo, int* hi, int* bad) {
+    const int lane = wave_lane();
+    const int pa = P_cp[j], pb = P_cp[j + 1];
+    int mn = INT_MAX, mx = -1;
+    for (int t = pa + lane; t < pb; t += 64) {
+        int l = P_ri[t];
+        if (l < 0 || l >= n) {
+            if (bad) atomicMin(bad, j);
+            continue;
+        }
+        int qa = Q_cp[l], qb = Q_cp[l + 1];
+        if (qb > qa) {
+            mn = min(mn, Q_ri[qa]);
+            mx = max(mx, Q_ri[qb - 1]);
+        }
+    }
+    *lo = wave_min_i(mn);
+    *hi = wave_max_i(mx);
+}
+
+__device__ inline void set_chunk_bits(unsigned* bm, int j, int n, int base, const int* P_cp,
+                                      const int* P_ri, const int* Q_cp, const int* Q_ri) {
+    const int lane = wave_lane();
+    const int pa = P_cp[j], pb = P_cp[j + 1];
+    for (int t = pa + lane; t < pb; t += 64) {
+        int l = P_ri[t];
+        if (l < 0 || l >= n) continue;
+        for (int f = Q_cp[l]; f < Q_cp[l + 1]; ++f) {
+            int r = Q_ri[f] - base;
+            if (r >= 0 && r < kBmBits) atomicOr(&bm[r >> 5], 1u << (r & 31));
+        }
+    }
+}
+
+// Count (counts != nullptr) or fill (out_ri != nullptr) the sorted union.
+__global__ void __launch_bounds__(64 * kWavesPerBlock)
+k_expand(int n, const int* P_cp, const int* P_ri, const int* Q_cp, const int* Q_ri, int* counts,
+         const int* out_cp, int* out_ri, int* bad) {
+    __shared__ unsigned bm_all[kWavesPerBlock][kBmWords];
+    unsigned* bm = bm_all[threadIdx.x >> 6];
+    const int lane = wave_lane();
+    const int wave = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+    const int nwaves = gridDim.x * kWavesPerBlock;
+    for (int j = wave; j < n; j += nwaves) {
+        int lo, hi;
+        candidate_range(j, n, P_cp, P_ri, Q_cp, Q_ri, &lo, &hi, bad);
+        int total = 0;
+        for (int base = lo; base <= hi; base += kBmBits) {
+            const int nbits = min(kBmBits, hi - base + 1);
+            const int nw = (nbits + 31) >> 5;
+            for (int w = lane; w < nw; w += 64) bm[w] = 0u;
+            wave_sync();
+            set_chunk_bits(bm, j, n, base, P_cp, P_ri, Q_cp, Q_ri);
+            wave_sync();
+            const int wpl = (nw + 63) >> 6;   // words per lane, contiguous
+            const int w0 = lane * wpl;
+            int c = 0;
+            for (int w = w0; w < min(nw, w0 + wpl); ++w) c += __popc(bm[w]);
+            const int pre = wave_excl_scan_i(c);
+            if (out_ri) {
+                int o = out_cp[j] + total + pre;
+                for (int w = w0; w < min(nw, w0 + wpl); ++w) {
+                    unsigned x = bm[w];
+                    while (x) {
+                        int b = __ffs(x) - 1;
+                        x &= x - 1;
+                        out_ri[o++] = base + (w << 5) + b;
+                    }
+                }
+            }
+            total += wave_sum_i(c);
+            wave_sync();
+        }
+        if (counts && lane == 0) counts[j] = total;
+    }
+}
+
+static unsigned expand_grid(int n) {
+    int64_t waves = n;
+    int64_t blocks = ceil_div(waves, kWavesPerBlock);
+    return (unsigned)std::min<int64_t>(blocks, 256 * 16);
+}
+
+hipError_t expand_count(int n, const int* P_cp, const int* P_ri, const int* Q_cp, const int* Q_ri,
+                        int* counts, int* bad, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_expand, dim3(expand_grid(n)), dim3(64 * kWavesPerBlock), 0, s, n, P_cp, P_ri,
+                       Q_cp, Q_ri, counts, nullptr, nullptr, bad);
+    return hipGetLastError();
+}
+
+hipError_t expand_fill(int n, const int* P_cp, const int* P_ri, const int* Q_cp, const int* Q_ri,
+                       const int* out_cp, int* out_ri, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_expand, dim3(expand_grid(n)), dim3(64 * kWavesPerBlock), 0, s, n, P_cp, P_ri,
+                       Q_cp, Q_ri, nullptr, out_cp, out_ri, nullptr);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ plan
+
+__global__ void k_gather_count(int n, const int* S_cp, const int* S_ri, const int* Ak_cp, int* counts) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    int s = 0;
+    for (int e = S_cp[j]; e < S_cp[j + 1]; ++e) {
+        int l = S_ri[e];
+        if (l >= 0 && l < n) s += Ak_cp[l + 1] - Ak_cp[l];
+    }
+    counts[j] = s;
+}
+
+hipError_t plan_gather_count(int n, const int* S_cp, const int* S_ri, const int* Ak_cp, int* counts,
+                             hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gather_count, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s, n, S_cp, S_ri,
+                       Ak_cp, counts);
+    return hipGetLastError();
+}
+
+// Row set I_j as a bitmap; every gathered A_k entry (in the order: entries of
+// A_k(:, J_j[0]), then of A_k(:, J_j[1]), ...) gets its rank inside I_j, and
+// so does every entry of A_0(:, j) (0xFF when its row is not in I_j).
+__global__ void __launch_bounds__(64 * kWavesPerBlock)
+k_plan_positions(int n, const int* S_cp, const int* S_ri, const int* Ak_cp, const int* Ak_ri,
+                 const int* A0_cp, const int* A0_ri, const int64_t* eoff, int* nI, unsigned char* posA,
+                 unsigned char* posB) {
+    __shared__ unsigned bm_all[kWavesPerBlock][kBmWords];
+    __shared__ int pre_all[kWavesPerBlock][kBmWords];
+    unsigned* bm = bm_all[threadIdx.x >> 6];
+    int* wpre = pre_all[threadIdx.x >> 6];
+    const int lane = wave_lane();
+    const int wave = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+    const int nwaves = gridDim.x * kWavesPerBlock;
+    for (int j = wave; j < n; j += nwaves) {
+        int lo, hi;
+        candidate_range(j, n, S_cp, S_ri, Ak_cp, Ak_ri, &lo, &hi, nullptr);
+        // A_0(:,j) rows start as "outside"
+        for (int e = A0_cp[j] + lane; e < A0_cp[j + 1]; e += 64) posB[e] = 0xFF;
+        const int sa = S_cp[j], sb = S_cp[j + 1];
+        int total = 0;
+        for (int base = lo; base <= hi; base += kBmBits) {
+            const int nbits = min(kBmBits, hi - base + 1);
+            const int nw = (nbits + 31) >> 5;
+            for (int w = lane; w < nw; w += 64) bm[w] = 0u;
+            wave_sync();
+            set_chunk_bits(bm, j, n, base, S_cp, S_ri, Ak_cp, Ak_ri);
+            wave_sync();
+            const int wpl = (nw + 63) >> 6;
+            const int w0 = lane * wpl;
+            int c = 0;
+            for (int w = w0; w < min(nw, w0 + wpl); ++w) c += __popc(bm[w]);
+            int run = total + wave_excl_scan_i(c);
+            for (int w = w0; w < min(nw, w0 + wpl); ++w) {
+                wpre[w] = run;
+                run += __popc(bm[w]);
+            }
+            wave_sync();
+            // ranks of the gathered A_k entries whose rows fall in this chunk
+            int off = 0;  // flat offset of the first entry of S entry t in this round
+            for (int t0 = sa; t0 < sb; t0 += 64) {
+                const int t = t0 + lane;
+                int l = -1, len = 0;
+                if (t < sb) {
+                    l = S_ri[t];
+                    if (l >= 0 && l < n) len = Ak_cp[l + 1] - Ak_cp[l];
+                }
+                const int my = off + wave_excl_scan_i(len);
+                if (len > 0) {
+                    const int qa = Ak_cp[l];
+                    for (int f = 0; f < len; ++f) {
+                        int r = Ak_ri[qa + f] - base;
+                        if (r >= 0 && r < kBmBits) {
+                            int w = r >> 5;
+                            int rank = wpre[w] + __popc(bm[w] & ((1u << (r & 31)) - 1u));
+                            posA[eoff[j] + my + f] = (unsigned char)min(rank, 255);
+                        }
+                    }
+                }
+                off += wave_sum_i(len);
+            }
+            for (int e = A0_cp[j] + lane; e < A0_cp[j + 1]; e += 64) {
+                int r = A0_ri[e] - base;
+                if (r >= 0 && r < kBmBits && (bm[r >> 5] >> (r & 31)) & 1u) {
+                    int w = r >> 5;
+                    int rank = wpre[w] + __popc(bm[w] & ((1u << (r & 31)) - 1u));
+                    posB[e] = (unsigned char)min(rank, 254);
+                }
+            }
+            total += wave_sum_i(c);
+            wave_sync();
+        }
+        if (lane == 0) nI[j] = total;
+    }
+}
+
+hipError_t plan_positions(int n, const int* S_cp, const int* S_ri, const int* Ak_cp, const int* Ak_ri,
+                          const int* A0_cp, const int* A0_ri, const int64_t* eoff, int* nI,
+                          unsigned char* posA, unsigned char* posB, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_plan_positions, dim3(expand_grid(n)), dim3(64 * kWavesPerBlock), 0, s, n, S_cp,
+                       S_ri, Ak_cp, Ak_ri, A0_cp, A0_ri, eoff, nI, posA, posB);
+    return hipGetLastError();
+}
+
+// --------------------------------------------------------------- buckets
+
+constexpr int kBucketThreads = 256;
+
+__device__ inline int bucket_of(int nI, int nJ, const BucketTable& tab) {
+    const int rows = tab.rows_plus_cols ? nI + nJ : nI;
+    for (int b = 0; b < tab.nb; ++b)
+        if (rows <= tab.max_rows[b] && nJ <= tab.max_cols[b]) return b;
+    return -1;
+}
+
+// hist is bucket-major: hist[b * nblocks + block]
+__global__ void __launch_bounds__(kBucketThreads)
+k_bucket_hist(int n, const int* S_cp, const int* nI, BucketTable tab, int* hist, int* unfit) {
+    __shared__ int h[kMaxBuckets];
+    if (threadIdx.x < kMaxBuckets) h[threadIdx.x] = 0;
+    __syncthreads();
+    const int j = blockIdx.x * kBucketThreads + threadIdx.x;
+    if (j < n) {
+        int b = bucket_of(nI[j], S_cp[j + 1] - S_cp[j], tab);
+        if (b >= 0) atomicAdd(&h[b], 1);
+        else atomicAdd(unfit, 1);
+    }
+    __syncthreads();
+    if (threadIdx.x < tab.nb) hist[threadIdx.x * gridDim.x + blockIdx.x] = h[threadIdx.x];
+}
+
+__global__ void __launch_bounds__(kBucketThreads)
+k_bucket_scatter(int n, const int* S_cp, const int* nI, BucketTable tab, const int64_t* off,
+                 int* queue) {
+    __shared__ int wcount[kBucketThreads / 64][kMaxBuckets];
+    const int j = blockIdx.x * kBucketThreads + threadIdx.x;
+    const int wv = threadIdx.x >> 6;
+    const int lane = wave_lane();
+    int b = -1;
+    if (j < n) b = bucket_of(nI[j], S_cp[j + 1] - S_cp[j], tab);
+    int my_rank = 0;
+    for (int k = 0; k < tab.nb; ++k) {
+        unsigned long long m = __ballot(b == k);
+        if (b == k) my_rank = __popcll(m & ((1ull << lane) - 1ull));
+        if (lane == 0) wcount[wv][k] = __popcll(m);
+    }
+    __syncthreads();
+    if (b >= 0) {
+        int r = my_rank;
+        for (int w = 0; w < wv; ++w) r += wcount[w][b];
+        queue[off[(int64_t)b * gridDim.x + blockIdx.x] + r] = j;
+    }
+}
+
+__global__ void k_bucket_starts(int nb, int nblocks, const int64_t* off, int* bstart) {
+    const int b = threadIdx.x;
+    if (b <= nb) bstart[b] = (int)off[(int64_t)b * nblocks];
+}
+
+size_t bucket_temp_bytes(int n) {
+    int64_t nblocks = ceil_div(std::max(n, 1), kBucketThreads);
+    int64_t cells = nblocks * kMaxBuckets;
+    return (size_t)cells * sizeof(int) + (size_t)(cells + 1) * sizeof(int64_t) + scan_temp_bytes(cells) + 512;
+}
+
+hipError_t bucket_sort(int n, const int* S_cp, const int* nI, BucketTable tab, int* queue, int* bstart,
+                       int* unfit, void* temp, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const int nblocks = (int)ceil_div(n, kBucketThreads);
+    const int64_t cells = (int64_t)nblocks * tab.nb;
+    char* p = (char*)temp;
+    int* hist = (int*)p;
+    p += (((size_t)nblocks * kMaxBuckets * sizeof(int)) + 255) / 256 * 256;
+    int64_t* off = (int64_t*)p;
+    p += (((size_t)(nblocks * kMaxBuckets + 1) * sizeof(int64_t)) + 255) / 256 * 256;
+    hipLaunchKernelGGL(k_bucket_hist, dim3(nblocks), dim3(kBucketThreads), 0, s, n, S_cp, nI, tab, hist,
+                       unfit);
+    hipError_t e = scan_counts(hist, cells, off, nullptr, nullptr, p, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_bucket_scatter, dim3(nblocks), dim3(kBucketThreads), 0, s, n, S_cp, nI, tab, off,
+                       queue);
+    hipLaunchKernelGGL(k_bucket_starts, dim3(1), dim3(kMaxBuckets + 1), 0, s, tab.nb, nblocks, off, bstart);
+    return hipGetLastError();
+}
+
+}  // namespace samk

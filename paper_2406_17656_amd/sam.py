@@ -1,0 +1,309 @@
+"""Python binding of the SAM C ABI over torch tensors (device memory and
+streams only; every step runs in the HIP library).
+
+Names follow include/sam.h: ``Context.pattern`` wraps sam_pattern_count +
+sam_pattern_fill, ``Context.plan`` sam_plan_create, ``Plan.build``
+sam_build_planned, ``Context.build`` sam_build, ``Context.residual``
+sam_residual, ``Context.apply_prepare`` / ``Context.apply`` the y = M x calls,
+``Context.sequence`` the sequence calls, ``Plan.build_weighted`` /
+``Plan.backward`` the soft-weighted map and its adjoint.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import _capi as C
+
+PREC = {"f64": C.SAM_PREC_F64, "f32": C.SAM_PREC_F32_REFINE, "f32_refine": C.SAM_PREC_F32_REFINE}
+
+
+class SamError(RuntimeError):
+    def __init__(self, status: int, message: str, column: int = -1):
+        name = C.STATUS_NAMES.get(status, str(status))
+        super().__init__(f"{name}: {message}" if message else name)
+        self.status = status
+        self.name = name
+        self.column = column
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _prec(p) -> int:
+    if isinstance(p, str):
+        return PREC[p]
+    return int(p)
+
+
+def _mdtype(prec: int):
+    return torch.float32 if prec == C.SAM_PREC_F32_REFINE else torch.float64
+
+
+@dataclass
+class DeviceCSC:
+    """Square CSC matrix held in device tensors."""
+    n: int
+    colptr: torch.Tensor   # int32 n+1
+    rowind: torch.Tensor   # int32 nnz
+    val: torch.Tensor | None = None  # float64 nnz
+
+    @property
+    def nnz(self) -> int:
+        return int(self.rowind.numel())
+
+    @staticmethod
+    def from_host(A, device="cuda") -> "DeviceCSC":
+        """From any object with n, colptr, rowind, val numpy arrays."""
+        return DeviceCSC(int(A.n),
+                         torch.as_tensor(np.ascontiguousarray(A.colptr, dtype=np.int32)).to(device),
+                         torch.as_tensor(np.ascontiguousarray(A.rowind, dtype=np.int32)).to(device),
+                         None if getattr(A, "val", None) is None else
+                         torch.as_tensor(np.ascontiguousarray(A.val, dtype=np.float64)).to(device))
+
+    def struct(self) -> C.sam_csc:
+        return C.sam_csc(self.n, self.nnz, self.colptr.data_ptr(), self.rowind.data_ptr(),
+                         None if self.val is None else self.val.data_ptr())
+
+
+def _spec(kind="none", power=1, thresh=0.0, global_scale=-1, tau=0.0, lfil=1) -> C.sam_pattern_spec:
+    return C.sam_pattern_spec(C.SPARSIFY[kind] if isinstance(kind, str) else int(kind), int(power),
+                              float(thresh), int(global_scale), float(tau), int(lfil))
+
+
+class Context:
+    """A sam_ctx bound to one HIP device."""
+
+    def __init__(self, device: int = 0):
+        self.lib = C.load()
+        self.device = device
+        h = ctypes.c_void_p()
+        st = self.lib.sam_create(ctypes.byref(h), device)
+        if st != C.SAM_OK:
+            raise SamError(st, f"sam_create(device={device}) failed")
+        self.h = h
+
+    # -- plumbing
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            self.lib.sam_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def stream(self):
+        if self.device == C.SAM_NO_DEVICE:
+            return None
+        return ctypes.c_void_p(torch.cuda.current_stream(self.device).cuda_stream)
+
+    def check(self, st: int):
+        if st != C.SAM_OK:
+            msg = self.lib.sam_last_error(self.h)
+            raise SamError(st, msg.decode() if msg else "")
+
+    def sync_status(self):
+        col = ctypes.c_int32(-1)
+        st = self.lib.sam_sync_status(self.h, self.stream(), ctypes.byref(col))
+        if st != C.SAM_OK:
+            msg = self.lib.sam_last_error(self.h)
+            raise SamError(st, msg.decode() if msg else "", col.value)
+
+    def check_csc(self, A: DeviceCSC):
+        s = A.struct()
+        self.check(self.lib.sam_check_csc(self.h, ctypes.byref(s), self.stream()))
+
+    # -- pattern (Sections 3-4)
+    def pattern(self, Ak: DeviceCSC, power=1, kind="none", **kw):
+        s = Ak.struct()
+        sp = _spec(kind, power, **kw)
+        nnz = ctypes.c_int64()
+        self.check(self.lib.sam_pattern_count(self.h, ctypes.byref(s), ctypes.byref(sp),
+                                              ctypes.byref(nnz), self.stream()))
+        dev = Ak.colptr.device
+        cp = torch.empty(Ak.n + 1, dtype=torch.int32, device=dev)
+        ri = torch.empty(max(nnz.value, 1), dtype=torch.int32, device=dev)
+        self.check(self.lib.sam_pattern_fill(self.h, ctypes.byref(s), ctypes.byref(sp), _ptr(cp),
+                                             _ptr(ri), self.stream()))
+        return cp, ri[:nnz.value]
+
+    # -- build (Section 2)
+    def plan(self, Ak: DeviceCSC, A0: DeviceCSC, S_colptr, S_rowind) -> "Plan":
+        return Plan(self, Ak, A0, S_colptr, S_rowind)
+
+    def build(self, Ak: DeviceCSC, A0: DeviceCSC, S_colptr, S_rowind, prec="f64", want_cols=True):
+        p = _prec(prec)
+        nnz = int(S_rowind.numel())
+        dev = Ak.colptr.device
+        M = torch.empty(max(nnz, 1), dtype=_mdtype(p), device=dev)
+        cols = torch.empty(max(Ak.n, 1), dtype=torch.float64, device=dev) if want_cols else None
+        res2 = torch.empty(1, dtype=torch.float64, device=dev)
+        a, b = Ak.struct(), A0.struct()
+        self.check(self.lib.sam_build(self.h, ctypes.byref(a), ctypes.byref(b), _ptr(S_colptr),
+                                      _ptr(S_rowind), nnz, p, _ptr(M), _ptr(cols), _ptr(res2),
+                                      self.stream()))
+        return M[:nnz], (cols[:Ak.n] if cols is not None else None), res2
+
+    # -- residual (Section 2 eq. res)
+    def residual(self, Ak: DeviceCSC, A0: DeviceCSC, M_colptr, M_rowind, M_val, prec="f64"):
+        p = _prec(prec)
+        dev = Ak.colptr.device
+        res2 = torch.empty(1, dtype=torch.float64, device=dev)
+        a02 = torch.empty(1, dtype=torch.float64, device=dev)
+        a, b = Ak.struct(), A0.struct()
+        self.check(self.lib.sam_residual(self.h, ctypes.byref(a), ctypes.byref(b), _ptr(M_colptr),
+                                         _ptr(M_rowind), int(M_rowind.numel()), _ptr(M_val), p,
+                                         _ptr(res2), _ptr(a02), self.stream()))
+        return res2, a02
+
+    # -- y = M x
+    def apply_prepare(self, n, M_colptr, M_rowind):
+        nnz = int(M_rowind.numel())
+        dev = M_colptr.device
+        rp = torch.empty(n + 1, dtype=torch.int32, device=dev)
+        ci = torch.empty(max(nnz, 1), dtype=torch.int32, device=dev)
+        pm = torch.empty(max(nnz, 1), dtype=torch.int32, device=dev)
+        self.check(self.lib.sam_apply_prepare(self.h, n, _ptr(M_colptr), _ptr(M_rowind), nnz, _ptr(rp),
+                                              _ptr(ci), _ptr(pm), self.stream()))
+        return rp, ci, pm
+
+    def apply(self, T, M_val, x, prec="f64", y=None):
+        rp, ci, pm = T
+        n = rp.numel() - 1
+        if y is None:
+            y = torch.empty(n, dtype=torch.float64, device=x.device)
+        self.check(self.lib.sam_apply(self.h, n, _ptr(rp), _ptr(ci), _ptr(pm), _ptr(M_val), _prec(prec),
+                                      _ptr(x), _ptr(y), self.stream()))
+        return y
+
+    # -- sequence
+    def sequence(self, A0: DeviceCSC, Ak_struct: DeviceCSC, n_src: int, prec="f32", power=1,
+                 kind="none", replan_each_run=False, **kw) -> "Sequence":
+        return Sequence(self, A0, Ak_struct, n_src, _prec(prec), _spec(kind, power, **kw),
+                        replan_each_run)
+
+
+class Plan:
+    """sam_plan: symbolic analysis of the column problems."""
+
+    def __init__(self, ctx: Context, Ak: DeviceCSC, A0: DeviceCSC, S_colptr, S_rowind):
+        self.ctx = ctx
+        self.Ak, self.A0 = Ak, A0          # keep the structure arrays alive
+        self.S_colptr, self.S_rowind = S_colptr, S_rowind
+        self.n = Ak.n
+        self.nnz_S = int(S_rowind.numel())
+        h = ctypes.c_void_p()
+        a, b = Ak.struct(), A0.struct()
+        ctx.check(ctx.lib.sam_plan_create(ctx.h, ctypes.byref(a), ctypes.byref(b), _ptr(S_colptr),
+                                          _ptr(S_rowind), self.nnz_S, ctypes.byref(h), ctx.stream()))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            torch.cuda.synchronize(self.ctx.device)
+            self.ctx.lib.sam_plan_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self) -> dict:
+        n = ctypes.c_int32(); mr = ctypes.c_int32(); mc = ctypes.c_int32()
+        ga = ctypes.c_int64(); nb = ctypes.c_int32(); bc = (ctypes.c_int32 * 16)()
+        self.ctx.check(self.ctx.lib.sam_plan_info(self.h, ctypes.byref(n), ctypes.byref(mr),
+                                                  ctypes.byref(mc), ctypes.byref(ga), ctypes.byref(nb), bc))
+        return {"n": n.value, "max_rows": mr.value, "max_cols": mc.value, "gathered": ga.value,
+                "bucket_cols": list(bc[:nb.value])}
+
+    def _outs(self, prec, M, cols, res2):
+        dev = self.S_colptr.device
+        if M is None:
+            M = torch.empty(max(self.nnz_S, 1), dtype=_mdtype(prec), device=dev)
+        if res2 is None:
+            res2 = torch.empty(1, dtype=torch.float64, device=dev)
+        return M, cols, res2
+
+    def build(self, Ak_val, A0_val, prec="f64", M=None, col_res2=None, res2=None):
+        p = _prec(prec)
+        M, col_res2, res2 = self._outs(p, M, col_res2, res2)
+        self.ctx.check(self.ctx.lib.sam_build_planned(self.h, _ptr(Ak_val), _ptr(A0_val), p, _ptr(M),
+                                                      _ptr(col_res2), _ptr(res2), self.ctx.stream()))
+        return M[:self.nnz_S], col_res2, res2
+
+    def build_weighted(self, Ak_val, A0_val, w, mu, prec="f32", M=None, col_res2=None, res2=None):
+        p = _prec(prec)
+        M, col_res2, res2 = self._outs(p, M, col_res2, res2)
+        self.ctx.check(self.ctx.lib.sam_build_weighted(self.h, _ptr(Ak_val), _ptr(A0_val), _ptr(w),
+                                                       float(mu), p, _ptr(M), _ptr(col_res2), _ptr(res2),
+                                                       self.ctx.stream()))
+        return M[:self.nnz_S], col_res2, res2
+
+    def backward(self, Ak_val, A0_val, w, mu, dL=1.0, prec="f32", want_gw=True):
+        p = _prec(prec)
+        dev = Ak_val.device
+        gAk = torch.empty_like(Ak_val)
+        gA0 = torch.empty_like(A0_val)
+        gw = torch.empty(max(self.nnz_S, 1), dtype=torch.float64, device=dev) if want_gw else None
+        loss = torch.empty(1, dtype=torch.float64, device=dev)
+        self.ctx.check(self.ctx.lib.sam_backward(self.h, _ptr(Ak_val), _ptr(A0_val), _ptr(w), float(mu),
+                                                 float(dL), p, _ptr(gAk), _ptr(gA0), _ptr(gw), _ptr(loss),
+                                                 self.ctx.stream()))
+        return gAk, gA0, (gw[:self.nnz_S] if gw is not None else None), loss
+
+
+class Sequence:
+    """sam_seq: maps A_1..A_N to A_0 with one graph launch per run."""
+
+    def __init__(self, ctx: Context, A0: DeviceCSC, Ak_struct: DeviceCSC, n_src: int, prec: int,
+                 spec: C.sam_pattern_spec, replan_each_run: bool):
+        self.ctx = ctx
+        self.A0, self.Ak_struct = A0, Ak_struct
+        self.n_src = n_src
+        self.prec = prec
+        self.spec = spec
+        h = ctypes.c_void_p()
+        a, b = A0.struct(), Ak_struct.struct()
+        ctx.check(ctx.lib.sam_sequence_create(ctx.h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(spec),
+                                              n_src, prec, 1 if replan_each_run else 0, ctypes.byref(h),
+                                              ctx.stream()))
+        self.h = h
+        nb = ctypes.c_int64()
+        ctx.check(ctx.lib.sam_sequence_info(self.h, ctypes.byref(nb)))
+        self.nnz_bound = nb.value
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            torch.cuda.synchronize(self.ctx.device)
+            self.ctx.lib.sam_sequence_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def alloc_maps(self):
+        dev = self.A0.colptr.device
+        return [torch.empty(max(self.nnz_bound, 1), dtype=_mdtype(self.prec), device=dev)
+                for _ in range(self.n_src)]
+
+    def run(self, Ak_vals, M_vals, res2):
+        arr_a = (ctypes.c_void_p * self.n_src)(*[t.data_ptr() for t in Ak_vals])
+        arr_m = (ctypes.c_void_p * self.n_src)(*[t.data_ptr() for t in M_vals])
+        self.ctx.check(self.ctx.lib.sam_sequence_run(self.h, arr_a, arr_m, _ptr(res2), self.ctx.stream()))
+
+    def pattern(self, k: int):
+        cp = ctypes.c_void_p(); ri = ctypes.c_void_p()
+        self.ctx.check(self.ctx.lib.sam_sequence_pattern(self.h, k, ctypes.byref(cp), ctypes.byref(ri)))
+        return cp.value, ri.value
