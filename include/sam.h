@@ -187,6 +187,16 @@ sam_status sam_plan_destroy(sam_plan* plan);
 sam_status sam_plan_info(const sam_plan* plan, int32_t* n, int32_t* max_rows, int32_t* max_cols,
                          int64_t* gathered, int32_t* nbuckets, int32_t* bucket_cols);
 
+/* Algorithmic cost of one sam_build_planned on this plan (host outputs, any
+ * may be NULL): flops of the dense column blocks, split into FP32 work
+ * (Householder QR 2 r c^2 - 2/3 c^3, Q^T b, triangular solves) and FP64 work
+ * (refinement residuals; everything for SAM_PREC_F64), with r = |I_j|,
+ * c = |J_j| summed over columns; and compulsory HBM bytes
+ * 12 nnz(A_k) + 12 nnz(A_0) + 4 nnz(S) + 12 (n+1) + v nnz(S) + 8 n, with
+ * v = 4 (FP32 map) or 8 (FP64 map). */
+sam_status sam_plan_cost(const sam_plan* plan, sam_precision prec, double* flops32, double* flops64,
+                         double* bytes);
+
 /* Numeric SAM build on a plan (Section 2): for every column j solve
  * min ||A_k(I_j,J_j) m - A_0(I_j,j)||_2 by Householder QR and back
  * substitution (prec selects FP64 or FP32 + FP64-residual refinement), write

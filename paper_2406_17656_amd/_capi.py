@@ -59,6 +59,8 @@ SIGNATURES = {
     "sam_plan_info": (c_int32, [P, ctypes.POINTER(c_int32), ctypes.POINTER(c_int32),
                                 ctypes.POINTER(c_int32), ctypes.POINTER(c_int64),
                                 ctypes.POINTER(c_int32), ctypes.POINTER(c_int32)]),
+    "sam_plan_cost": (c_int32, [P, c_int32, ctypes.POINTER(c_double), ctypes.POINTER(c_double),
+                                ctypes.POINTER(c_double)]),
     "sam_build_planned": (c_int32, [P, P, P, c_int32, P, P, P, P]),
     "sam_build": (c_int32, [P, CSCP, CSCP, P, P, c_int64, c_int32, P, P, P, P]),
     "sam_residual": (c_int32, [P, CSCP, CSCP, P, P, c_int64, P, c_int32, P, P, P]),

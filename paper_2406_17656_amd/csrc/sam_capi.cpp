@@ -280,6 +280,8 @@ struct sam_plan {
     void* rtemp = nullptr;
     int64_t E = 0;
     int max_rows = 0, max_cols = 0;
+    // algorithmic flop counts of one build (dense column blocks)
+    double fl_qr32 = 0.0, fl_ref64 = 0.0, fl_f64 = 0.0;
     Combo combo[2][2];  // [prec][weighted]
     // backward staging (lazily allocated)
     DevBuf bwd;
@@ -564,6 +566,12 @@ sam_status sam_plan_create(sam_ctx* ctx, const sam_csc* Ak, const sam_csc* A0, c
                 return bail(fail(ctx, SAM_ERR_UNSORTED, "S_colptr decreases at column %d", j));
             pl->max_rows = std::max(pl->max_rows, hnI[j]);
             pl->max_cols = std::max(pl->max_cols, hcp[j + 1] - hcp[j]);
+            const double r = hnI[j], c = hcp[j + 1] - hcp[j];
+            // Householder QR of the r x c block, Q^T b and back substitution
+            const double qr = 2.0 * r * c * c - 2.0 / 3.0 * c * c * c + 4.0 * r * c - 2.0 * c * c + c * c;
+            pl->fl_qr32 += qr + 2.0 * c * c;              // + two triangular solves of the refinement
+            pl->fl_ref64 += 6.0 * r * c + 2.0 * r;         // r = b - Am, A^T r, final residual
+            pl->fl_f64 += qr + 2.0 * r * c + 2.0 * r;      // FP64 mode: explicit residual
         }
         for (int p = 0; p < 2; ++p)
             for (int w = 0; w < 2; ++w)
@@ -579,6 +587,20 @@ sam_status sam_plan_destroy(sam_plan* plan) {
     release(plan->mem);
     release(plan->bwd);
     delete plan;
+    return SAM_OK;
+}
+
+sam_status sam_plan_cost(const sam_plan* plan, sam_precision prec, double* flops32, double* flops64,
+                         double* bytes) {
+    if (!plan || !prec_ok(prec)) return SAM_ERR_ARG;
+    const bool f32 = prec == SAM_PREC_F32_REFINE;
+    if (flops32) *flops32 = f32 ? plan->fl_qr32 : 0.0;
+    if (flops64) *flops64 = f32 ? plan->fl_ref64 : plan->fl_f64;
+    if (bytes) {
+        const double vb = f32 ? 4.0 : 8.0;
+        *bytes = 12.0 * plan->nnzA + 12.0 * plan->nnzA0 + 4.0 * (double)plan->nnzS + 12.0 * (plan->n + 1.0) +
+                 vb * (double)plan->nnzS + 8.0 * plan->n;
+    }
     return SAM_OK;
 }
 

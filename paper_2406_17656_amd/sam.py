@@ -225,6 +225,12 @@ class Plan:
         return {"n": n.value, "max_rows": mr.value, "max_cols": mc.value, "gathered": ga.value,
                 "bucket_cols": list(bc[:nb.value])}
 
+    def cost(self, prec="f32") -> dict:
+        f32 = ctypes.c_double(); f64 = ctypes.c_double(); by = ctypes.c_double()
+        self.ctx.check(self.ctx.lib.sam_plan_cost(self.h, _prec(prec), ctypes.byref(f32), ctypes.byref(f64),
+                                                  ctypes.byref(by)))
+        return {"flops32": f32.value, "flops64": f64.value, "bytes": by.value}
+
     def _outs(self, prec, M, cols, res2):
         dev = self.S_colptr.device
         if M is None:
