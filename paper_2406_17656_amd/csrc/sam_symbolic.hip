@@ -265,133 +265,188 @@ hipError_t sparsify_fill(int n, const int* cp, const int* ri, const double* v, S
 }
 
 // ------------------------------------------------------- row-set bitmaps
+//
+// One 16-lane DPP row per column (four columns per wave).  The candidates of
+// column j are the rows of Q(:, l) for l in P(:, j); lane g of the group owns
+// the lists l = P(:, j)[g], P(:, j)[g+16], ...  The window of candidate rows
+// is swept in chunks of kChunk rows: each chunk gets an LDS bitmap (four
+// 32-bit words per lane), set with ds_or, counted with popcount and a row
+// prefix scan.  After a chunk the sweep jumps to the smallest candidate
+// beyond it, so only occupied chunks cost anything, whatever the bandwidth.
 
-constexpr int kBmWords = 1024;              // 32768 rows per chunk
-constexpr int kBmBits = kBmWords * 32;
-constexpr int kWavesPerBlock = 4;
+constexpr int kGS = 16;                   // lanes per column
+constexpr int kChunkWords = 64;           // 4 words per lane
+constexpr int kChunk = kChunkWords * 32;  // 2048 rows
+constexpr int kSymThreads = 256;
+constexpr int kGroupsPerBlock = kSymThreads / kGS;
 
-__device__ inline int wave_min_i(int v) {
-    for (int d = 32; d >= 1; d >>= 1) v = min(v, __shfl_xor(v, d));
+template <int CTRL>
+__device__ inline int dppi(int v) { return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false); }
+
+// sums / minima over the 16 lanes of a row (all lanes get the result)
+__device__ inline int row_sum_i(int v) {
+    v += __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, true);
+    v += __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, true);
+    v += __builtin_amdgcn_update_dpp(0, v, 0x141, 0xF, 0xF, true);
+    v += __builtin_amdgcn_update_dpp(0, v, 0x140, 0xF, 0xF, true);
     return v;
 }
-__device__ inline int wave_max_i(int v) {
-    for (int d = 32; d >= 1; d >>= 1) v = max(v, __shfl_xor(v, d));
+__device__ inline int row_min_i(int v) {
+    v = min(v, __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, true));
+    v = min(v, __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, true));
+    v = min(v, __builtin_amdgcn_update_dpp(0, v, 0x141, 0xF, 0xF, true));
+    v = min(v, __builtin_amdgcn_update_dpp(0, v, 0x140, 0xF, 0xF, true));
     return v;
 }
-__device__ inline int wave_sum_i(int v) {
-    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d);
-    return v;
-}
-__device__ inline int wave_excl_scan_i(int v) {
-    const int lane = wave_lane();
+// exclusive prefix sum inside the row (Kogge-Stone with row_shr; lanes whose
+// source lies before the row start add 0)
+__device__ inline int row_excl_scan_i(int v) {
     int x = v;
-    for (int d = 1; d < 64; d <<= 1) {
-        int y = __shfl_up(x, d);
-        if (lane >= d) x += y;
-    }
+    x += dppi<0x111>(x);
+    x += dppi<0x112>(x);
+    x += dppi<0x114>(x);
+    x += dppi<0x118>(x);
     return x - v;
 }
 
-// Candidates of column j: rows of Q(:, l) for l in P(:, j).  Lane t handles
-// P entries t, t+64, ...  Returns the candidate row range through lo/hi
-// (lo > hi when empty) and flags out-of-range column indices.
-__device__ inline void candidate_range(int j, int n, const int* P_cp, const int* P_ri, const int* Q_cp,
-                                       const int* Q_ri, int* lo, int* hi, int* bad) {
-    const int lane = wave_lane();
-    const int pa = P_cp[j], pb = P_cp[j + 1];
-    int mn = INT_MAX, mx = -1;
-    for (int t = pa + lane; t < pb; t += 64) {
-        int l = P_ri[t];
-        if (l < 0 || l >= n) {
-            if (bad) atomicMin(bad, j);
-            continue;
-        }
-        int qa = Q_cp[l], qb = Q_cp[l + 1];
-        if (qb > qa) {
-            mn = min(mn, Q_ri[qa]);
-            mx = max(mx, Q_ri[qb - 1]);
-        }
-    }
-    *lo = wave_min_i(mn);
-    *hi = wave_max_i(mx);
-}
+enum { kModeCount = 0, kModeFill = 1, kModePositions = 2 };
 
-__device__ inline void set_chunk_bits(unsigned* bm, int j, int n, int base, const int* P_cp,
-                                      const int* P_ri, const int* Q_cp, const int* Q_ri) {
-    const int lane = wave_lane();
-    const int pa = P_cp[j], pb = P_cp[j + 1];
-    for (int t = pa + lane; t < pb; t += 64) {
-        int l = P_ri[t];
-        if (l < 0 || l >= n) continue;
-        for (int f = Q_cp[l]; f < Q_cp[l + 1]; ++f) {
-            int r = Q_ri[f] - base;
-            if (r >= 0 && r < kBmBits) atomicOr(&bm[r >> 5], 1u << (r & 31));
+template <int MODE>
+__global__ void __launch_bounds__(kSymThreads)
+k_union(int n, const int* P_cp, const int* P_ri, const int* Q_cp, const int* Q_ri, int* counts,
+        const int* out_cp, int* out_ri, const int64_t* eoff, unsigned char* posA, const int* A0_cp,
+        const int* A0_ri, unsigned char* posB, int* bad) {
+    __shared__ unsigned bm_all[kGroupsPerBlock][kChunkWords];
+    __shared__ int pre_all[kGroupsPerBlock][kChunkWords];
+    const int grp = threadIdx.x / kGS;
+    const int g = threadIdx.x % kGS;
+    unsigned* bm = bm_all[grp];
+    int* wpre = pre_all[grp];
+    const int stride = gridDim.x * kGroupsPerBlock;
+    for (int j = blockIdx.x * kGroupsPerBlock + grp; j < n; j += stride) {
+        const int pa = P_cp[j], pb = P_cp[j + 1];
+        // first candidate row: lists are sorted, so their heads bound it
+        int lo = INT_MAX;
+        for (int t = pa + g; t < pb; t += kGS) {
+            const int l = P_ri[t];
+            if (l < 0 || l >= n) {
+                if (bad) atomicMin(bad, j);
+                continue;
+            }
+            if (Q_cp[l + 1] > Q_cp[l]) lo = min(lo, Q_ri[Q_cp[l]]);
         }
-    }
-}
-
-// Count (counts != nullptr) or fill (out_ri != nullptr) the sorted union.
-__global__ void __launch_bounds__(64 * kWavesPerBlock)
-k_expand(int n, const int* P_cp, const int* P_ri, const int* Q_cp, const int* Q_ri, int* counts,
-         const int* out_cp, int* out_ri, int* bad) {
-    __shared__ unsigned bm_all[kWavesPerBlock][kBmWords];
-    unsigned* bm = bm_all[threadIdx.x >> 6];
-    const int lane = wave_lane();
-    const int wave = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
-    const int nwaves = gridDim.x * kWavesPerBlock;
-    for (int j = wave; j < n; j += nwaves) {
-        int lo, hi;
-        candidate_range(j, n, P_cp, P_ri, Q_cp, Q_ri, &lo, &hi, bad);
-        int total = 0;
-        for (int base = lo; base <= hi; base += kBmBits) {
-            const int nbits = min(kBmBits, hi - base + 1);
-            const int nw = (nbits + 31) >> 5;
-            for (int w = lane; w < nw; w += 64) bm[w] = 0u;
+        lo = row_min_i(lo);
+        if (MODE == kModePositions)
+            for (int e = A0_cp[j] + g; e < A0_cp[j + 1]; e += kGS) posB[e] = 0xFF;
+        int running = 0;
+        int base = lo;
+        while (base != INT_MAX) {
+#pragma unroll
+            for (int w = 0; w < 4; ++w) bm[g * 4 + w] = 0u;
             wave_sync();
-            set_chunk_bits(bm, j, n, base, P_cp, P_ri, Q_cp, Q_ri);
+            int next = INT_MAX;
+            for (int t = pa + g; t < pb; t += kGS) {
+                const int l = P_ri[t];
+                if (l < 0 || l >= n) continue;
+                for (int f = Q_cp[l]; f < Q_cp[l + 1]; ++f) {
+                    const int d = Q_ri[f] - base;
+                    if (d >= kChunk) {
+                        next = min(next, d + base);
+                        break;
+                    }
+                    if (d >= 0) atomicOr(&bm[d >> 5], 1u << (d & 31));
+                }
+            }
             wave_sync();
-            const int wpl = (nw + 63) >> 6;   // words per lane, contiguous
-            const int w0 = lane * wpl;
             int c = 0;
-            for (int w = w0; w < min(nw, w0 + wpl); ++w) c += __popc(bm[w]);
-            const int pre = wave_excl_scan_i(c);
-            if (out_ri) {
-                int o = out_cp[j] + total + pre;
-                for (int w = w0; w < min(nw, w0 + wpl); ++w) {
-                    unsigned x = bm[w];
+#pragma unroll
+            for (int w = 0; w < 4; ++w) c += __popc(bm[g * 4 + w]);
+            const int pre = row_excl_scan_i(c);
+            const int tot = row_sum_i(c);
+            if (MODE != kModeCount) {
+                int run = running + pre;
+#pragma unroll
+                for (int w = 0; w < 4; ++w) {
+                    wpre[g * 4 + w] = run;
+                    run += __popc(bm[g * 4 + w]);
+                }
+            }
+            wave_sync();
+            if (MODE == kModeFill) {
+                int o = out_cp[j] + running + pre;
+#pragma unroll
+                for (int w = 0; w < 4; ++w) {
+                    unsigned x = bm[g * 4 + w];
                     while (x) {
-                        int b = __ffs(x) - 1;
+                        const int b = __ffs(x) - 1;
                         x &= x - 1;
-                        out_ri[o++] = base + (w << 5) + b;
+                        out_ri[o++] = base + ((g * 4 + w) << 5) + b;
                     }
                 }
             }
-            total += wave_sum_i(c);
+            if (MODE == kModePositions) {
+                // ranks of the gathered A_k entries, in the order of the lists
+                int carry = 0;
+                for (int t0 = pa; t0 < pb; t0 += kGS) {
+                    const int t = t0 + g;
+                    int l = -1, len = 0;
+                    if (t < pb) {
+                        l = P_ri[t];
+                        if (l >= 0 && l < n) len = Q_cp[l + 1] - Q_cp[l];
+                    }
+                    const int off = carry + row_excl_scan_i(len);
+                    if (len > 0) {
+                        const int qa = Q_cp[l];
+                        for (int f = 0; f < len; ++f) {
+                            const int d = Q_ri[qa + f] - base;
+                            if (d >= kChunk) break;
+                            if (d >= 0) {
+                                const int w = d >> 5;
+                                const int rank = wpre[w] + __popc(bm[w] & ((1u << (d & 31)) - 1u));
+                                posA[eoff[j] + off + f] = (unsigned char)min(rank, 255);
+                            }
+                        }
+                    }
+                    carry += row_sum_i(len);
+                }
+                for (int e = A0_cp[j] + g; e < A0_cp[j + 1]; e += kGS) {
+                    const int d = A0_ri[e] - base;
+                    if (d >= 0 && d < kChunk && ((bm[d >> 5] >> (d & 31)) & 1u)) {
+                        const int w = d >> 5;
+                        const int rank = wpre[w] + __popc(bm[w] & ((1u << (d & 31)) - 1u));
+                        posB[e] = (unsigned char)min(rank, 254);
+                    }
+                }
+            }
+            running += tot;
+            base = row_min_i(next);
             wave_sync();
         }
-        if (counts && lane == 0) counts[j] = total;
+        if (g == 0) {
+            if (MODE == kModeCount) counts[j] = running;
+            if (MODE == kModePositions) counts[j] = running;  // |I_j|
+        }
     }
 }
 
-static unsigned expand_grid(int n) {
-    int64_t waves = n;
-    int64_t blocks = ceil_div(waves, kWavesPerBlock);
-    return (unsigned)std::min<int64_t>(blocks, 256 * 16);
+static unsigned union_grid(int n) {
+    int64_t blocks = ceil_div(n, kGroupsPerBlock);
+    return (unsigned)std::min<int64_t>(blocks, 256 * 32);
 }
 
 hipError_t expand_count(int n, const int* P_cp, const int* P_ri, const int* Q_cp, const int* Q_ri,
                         int* counts, int* bad, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_expand, dim3(expand_grid(n)), dim3(64 * kWavesPerBlock), 0, s, n, P_cp, P_ri,
-                       Q_cp, Q_ri, counts, nullptr, nullptr, bad);
+    hipLaunchKernelGGL(k_union<kModeCount>, dim3(union_grid(n)), dim3(kSymThreads), 0, s, n, P_cp, P_ri, Q_cp,
+                       Q_ri, counts, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, bad);
     return hipGetLastError();
 }
 
 hipError_t expand_fill(int n, const int* P_cp, const int* P_ri, const int* Q_cp, const int* Q_ri,
                        const int* out_cp, int* out_ri, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_expand, dim3(expand_grid(n)), dim3(64 * kWavesPerBlock), 0, s, n, P_cp, P_ri,
-                       Q_cp, Q_ri, nullptr, out_cp, out_ri, nullptr);
+    hipLaunchKernelGGL(k_union<kModeFill>, dim3(union_grid(n)), dim3(kSymThreads), 0, s, n, P_cp, P_ri, Q_cp,
+                       Q_ri, nullptr, out_cp, out_ri, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr);
     return hipGetLastError();
 }
 
@@ -416,88 +471,16 @@ hipError_t plan_gather_count(int n, const int* S_cp, const int* S_ri, const int*
     return hipGetLastError();
 }
 
-// Row set I_j as a bitmap; every gathered A_k entry (in the order: entries of
-// A_k(:, J_j[0]), then of A_k(:, J_j[1]), ...) gets its rank inside I_j, and
-// so does every entry of A_0(:, j) (0xFF when its row is not in I_j).
-__global__ void __launch_bounds__(64 * kWavesPerBlock)
-k_plan_positions(int n, const int* S_cp, const int* S_ri, const int* Ak_cp, const int* Ak_ri,
-                 const int* A0_cp, const int* A0_ri, const int64_t* eoff, int* nI, unsigned char* posA,
-                 unsigned char* posB) {
-    __shared__ unsigned bm_all[kWavesPerBlock][kBmWords];
-    __shared__ int pre_all[kWavesPerBlock][kBmWords];
-    unsigned* bm = bm_all[threadIdx.x >> 6];
-    int* wpre = pre_all[threadIdx.x >> 6];
-    const int lane = wave_lane();
-    const int wave = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
-    const int nwaves = gridDim.x * kWavesPerBlock;
-    for (int j = wave; j < n; j += nwaves) {
-        int lo, hi;
-        candidate_range(j, n, S_cp, S_ri, Ak_cp, Ak_ri, &lo, &hi, nullptr);
-        // A_0(:,j) rows start as "outside"
-        for (int e = A0_cp[j] + lane; e < A0_cp[j + 1]; e += 64) posB[e] = 0xFF;
-        const int sa = S_cp[j], sb = S_cp[j + 1];
-        int total = 0;
-        for (int base = lo; base <= hi; base += kBmBits) {
-            const int nbits = min(kBmBits, hi - base + 1);
-            const int nw = (nbits + 31) >> 5;
-            for (int w = lane; w < nw; w += 64) bm[w] = 0u;
-            wave_sync();
-            set_chunk_bits(bm, j, n, base, S_cp, S_ri, Ak_cp, Ak_ri);
-            wave_sync();
-            const int wpl = (nw + 63) >> 6;
-            const int w0 = lane * wpl;
-            int c = 0;
-            for (int w = w0; w < min(nw, w0 + wpl); ++w) c += __popc(bm[w]);
-            int run = total + wave_excl_scan_i(c);
-            for (int w = w0; w < min(nw, w0 + wpl); ++w) {
-                wpre[w] = run;
-                run += __popc(bm[w]);
-            }
-            wave_sync();
-            // ranks of the gathered A_k entries whose rows fall in this chunk
-            int off = 0;  // flat offset of the first entry of S entry t in this round
-            for (int t0 = sa; t0 < sb; t0 += 64) {
-                const int t = t0 + lane;
-                int l = -1, len = 0;
-                if (t < sb) {
-                    l = S_ri[t];
-                    if (l >= 0 && l < n) len = Ak_cp[l + 1] - Ak_cp[l];
-                }
-                const int my = off + wave_excl_scan_i(len);
-                if (len > 0) {
-                    const int qa = Ak_cp[l];
-                    for (int f = 0; f < len; ++f) {
-                        int r = Ak_ri[qa + f] - base;
-                        if (r >= 0 && r < kBmBits) {
-                            int w = r >> 5;
-                            int rank = wpre[w] + __popc(bm[w] & ((1u << (r & 31)) - 1u));
-                            posA[eoff[j] + my + f] = (unsigned char)min(rank, 255);
-                        }
-                    }
-                }
-                off += wave_sum_i(len);
-            }
-            for (int e = A0_cp[j] + lane; e < A0_cp[j + 1]; e += 64) {
-                int r = A0_ri[e] - base;
-                if (r >= 0 && r < kBmBits && (bm[r >> 5] >> (r & 31)) & 1u) {
-                    int w = r >> 5;
-                    int rank = wpre[w] + __popc(bm[w] & ((1u << (r & 31)) - 1u));
-                    posB[e] = (unsigned char)min(rank, 254);
-                }
-            }
-            total += wave_sum_i(c);
-            wave_sync();
-        }
-        if (lane == 0) nI[j] = total;
-    }
-}
-
+// Row set I_j of every column as a bitmap sweep; every gathered A_k entry (in
+// the order: entries of A_k(:, J_j[0]), then of A_k(:, J_j[1]), ...) gets its
+// rank inside I_j, and so does every entry of A_0(:, j) (0xFF when its row is
+// not in I_j).  nI[j] = |I_j|.
 hipError_t plan_positions(int n, const int* S_cp, const int* S_ri, const int* Ak_cp, const int* Ak_ri,
                           const int* A0_cp, const int* A0_ri, const int64_t* eoff, int* nI,
                           unsigned char* posA, unsigned char* posB, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_plan_positions, dim3(expand_grid(n)), dim3(64 * kWavesPerBlock), 0, s, n, S_cp,
-                       S_ri, Ak_cp, Ak_ri, A0_cp, A0_ri, eoff, nI, posA, posB);
+    hipLaunchKernelGGL(k_union<kModePositions>, dim3(union_grid(n)), dim3(kSymThreads), 0, s, n, S_cp, S_ri,
+                       Ak_cp, Ak_ri, nI, nullptr, nullptr, eoff, posA, A0_cp, A0_ri, posB, nullptr);
     return hipGetLastError();
 }
 
