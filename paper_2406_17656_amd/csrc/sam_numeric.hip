@@ -48,21 +48,42 @@ __device__ inline int logical_block() {
     return (b & 7) * (nb >> 3) + (b >> 3);
 }
 
-template <typename TQ, int G, int R, int NC, int TC, bool WEIGHTED>
+template <typename T>
+__device__ inline T recip(T x);
+template <>
+__device__ inline float recip<float>(float x) { return __builtin_amdgcn_rcpf(x); }
+template <>
+__device__ inline double recip<double>(double x) { return 1.0 / x; }
+
+template <typename T>
+__device__ inline T root(T x);
+template <>
+__device__ inline float root<float>(float x) { return __builtin_amdgcn_sqrtf(x); }
+template <>
+__device__ inline double root<double>(double x) { return sqrt(x); }
+
+// One kernel variant serves one bucket: every column problem with
+// |I_j| (+ |J_j| when weighted) <= G*R rows and |J_j| <= NC columns.  The
+// code is straight-line in NC and R (no runtime column guards): columns past
+// |J_j| are zero and pass through the Householder steps as identities.
+template <typename TQ, int G, int R, int NC, int TC, int LPL, bool WEIGHTED>
 __global__ void __launch_bounds__(64)
 k_numeric(NumericArgs a) {
     constexpr int P = 64 / G;        // problems per wave
     constexpr int RM = G * R;        // rows per problem (padded)
+    constexpr int RX = RM + G;       // plus one scratch row per lane
     constexpr bool REFINE = std::is_same<TQ, float>::value;
     static_assert(TC >= 1, "tile chunk");
-    __shared__ double tile[P * RM * TC];  // gather staging, reused for r
-    __shared__ double bsh[P * RM];        // b = A_0(I_j, j)
+    __shared__ double tile[P * RX * TC];  // gather staging, later the residual vector
+    __shared__ double bsh[P * RX];        // b = A_0(I_j, j)
     __shared__ int cst[P][NC + 1];        // entry offset of column c in the block
     __shared__ int vbs[P][NC];            // start of A_k(:, J_j[c]) in the value array
+    __shared__ int cln[P][NC];            // nnz of A_k(:, J_j[c])
 
     const int lane = threadIdx.x;
     const int g = lane % G;
     const int q = lane / G;
+    const int trash = RM + g;             // this lane's scratch row: absorbs masked writes
     const int b0 = a.bstart[a.bucket];
     const int count = a.bstart[a.bucket + 1] - b0;
     const int ngroups = (count + P - 1) / P;
@@ -83,78 +104,116 @@ k_numeric(NumericArgs a) {
             nIj = a.nI[j];
             eo = a.eoff[j];
         }
-        // rows the QR sees: I_j, plus the penalty rows in the weighted form
         const int nrows = WEIGHTED ? nIj + nJ : nIj;
-        const int ncw = __builtin_amdgcn_readfirstlane((int)group_max<64>((float)nJ));
 
-        // ---- column metadata
+        // ---- column metadata: lane g resolves columns g, g+G, ... of J_j
+#pragma unroll
+        for (int c = g; c < NC; c += G) {
+            int vb = 0, len = 0;
+            if (c < nJ) {
+                const int l = a.S_ri[scol + c];
+                vb = a.Ak_cp[l];
+                len = a.Ak_cp[l + 1] - vb;
+            }
+            vbs[q][c] = vb;
+            cln[q][c] = len;
+        }
+        // ---- b = A_0(I_j, j) and out_j (rows outside I_j)
+#pragma unroll
+        for (int t = 0; t < R; ++t) bsh[q * RX + t * G + g] = 0.0;
+        bsh[q * RX + trash] = 0.0;
+        const int a0 = valid ? a.A0_cp[j] : 0;
+        const int a1 = valid ? a.A0_cp[j + 1] : 0;
+        int bp[LPL];
+        double bv[LPL];
+#pragma unroll
+        for (int s = 0; s < LPL; ++s) {
+            const int e = a0 + g + s * G;
+            const bool ok = e < a1;
+            const int ec = ok ? e : 0;
+            const int p = a.posB[ec];
+            const double v = a.A0_v[ec];
+            bp[s] = ok ? p : -1;
+            bv[s] = ok ? v : 0.0;
+        }
+        wave_sync();
         if (g == 0) {
             int acc = 0;
+#pragma unroll
             for (int c = 0; c < NC; ++c) {
-                int vb = 0, len = 0;
-                if (c < nJ) {
-                    const int l = a.S_ri[scol + c];
-                    vb = a.Ak_cp[l];
-                    len = a.Ak_cp[l + 1] - vb;
-                }
                 cst[q][c] = acc;
-                vbs[q][c] = vb;
-                acc += len;
+                acc += cln[q][c];
             }
             cst[q][NC] = acc;
         }
-        // ---- b = A_0(I_j, j), out_j
-#pragma unroll
-        for (int t = 0; t < R; ++t) bsh[q * RM + t * G + g] = 0.0;
-        wave_sync();
         double outj = 0.0;
-        if (valid) {
-            for (int e = a.A0_cp[j] + g; e < a.A0_cp[j + 1]; e += G) {
-                const int p = a.posB[e];
-                const double v = a.A0_v[e];
-                if (p != 0xFF) bsh[q * RM + p] = v;
-                else outj += v * v;
-            }
+#pragma unroll
+        for (int s = 0; s < LPL; ++s) {
+            outj += bp[s] == 0xFF ? bv[s] * bv[s] : 0.0;
+            bsh[q * RX + ((bp[s] >= 0 && bp[s] != 0xFF) ? bp[s] : trash)] = bv[s];
+        }
+        for (int e = a0 + g + LPL * G; e < a1; e += G) {  // long columns
+            const int p = a.posB[e];
+            const double v = a.A0_v[e];
+            if (p != 0xFF) bsh[q * RX + p] = v;
+            else outj += v * v;
         }
         outj = group_sum<G>(outj);
         wave_sync();
 
-        // ---- gather the block, TC columns at a time
+        // ---- gather: every A_k value this lane moves is loaded first (static
+        //      indices), then staged TC columns at a time through the LDS
+        //      tile and read back row-wise; masked entries go to the lane's
+        //      scratch row.
+        double pv[NC][LPL];
+        int pp[NC][LPL];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            const int len = cln[q][c];
+            const int e0 = cst[q][c];
+            const int vb = vbs[q][c];
+#pragma unroll
+            for (int s = 0; s < LPL; ++s) {
+                const int e = g + s * G;
+                const bool ok = e < len;
+                const int ec = ok ? e : 0;  // clamped: the load is always in bounds
+                const int p = a.posA[eo + e0 + ec];
+                const double v = a.Ak_v[vb + ec];
+                pp[c][s] = ok ? p : trash;
+                pv[c][s] = ok ? v : 0.0;
+            }
+        }
         TQ A[R][NC];
 #pragma unroll
         for (int c0 = 0; c0 < NC; c0 += TC) {
-            if (c0 < ncw) {
 #pragma unroll
-                for (int t = 0; t < R; ++t)
+            for (int t = 0; t <= R; ++t) {
+                const int row = t < R ? t * G + g : trash;
 #pragma unroll
-                    for (int cc = 0; cc < TC; ++cc) tile[(q * RM + t * G + g) * TC + cc] = 0.0;
-                wave_sync();
+                for (int cc = 0; cc < TC; ++cc) tile[(q * RX + row) * TC + cc] = 0.0;
+            }
+            wave_sync();
 #pragma unroll
-                for (int cc = 0; cc < TC; ++cc) {
-                    const int c = c0 + cc;
-                    if (c < NC && c < nJ) {
-                        const int e0 = cst[q][c], e1 = cst[q][c + 1];
-                        const int vb = vbs[q][c];
-                        for (int e = g; e < e1 - e0; e += G) {
-                            const int p = a.posA[eo + e0 + e];
-                            tile[(q * RM + p) * TC + cc] = a.Ak_v[vb + e];
-                        }
+            for (int cc = 0; cc < TC; ++cc) {
+                const int c = c0 + cc;
+                if (c < NC) {
+#pragma unroll
+                    for (int s = 0; s < LPL; ++s) tile[(q * RX + pp[c][s]) * TC + cc] = pv[c][s];
+                    const int len = cln[q][c];
+                    if (len > LPL * G) {  // long columns: the rest straight from memory
+                        const int e0 = cst[q][c], vb = vbs[q][c];
+                        for (int e = g + LPL * G; e < len; e += G)
+                            tile[(q * RX + a.posA[eo + e0 + e]) * TC + cc] = a.Ak_v[vb + e];
                     }
                 }
-                wave_sync();
-#pragma unroll
-                for (int t = 0; t < R; ++t)
-#pragma unroll
-                    for (int cc = 0; cc < TC; ++cc)
-                        if (c0 + cc < NC) A[t][c0 + cc] = (TQ)tile[(q * RM + t * G + g) * TC + cc];
-                wave_sync();
-            } else {
-#pragma unroll
-                for (int t = 0; t < R; ++t)
-#pragma unroll
-                    for (int cc = 0; cc < TC; ++cc)
-                        if (c0 + cc < NC) A[t][c0 + cc] = (TQ)0;
             }
+            wave_sync();
+#pragma unroll
+            for (int t = 0; t < R; ++t)
+#pragma unroll
+                for (int cc = 0; cc < TC; ++cc)
+                    if (c0 + cc < NC) A[t][c0 + cc] = (TQ)tile[(q * RX + t * G + g) * TC + cc];
+            wave_sync();
         }
         // penalty rows: row nIj + c holds sqrt(p_c) in column c
         if constexpr (WEIGHTED) {
@@ -172,67 +231,61 @@ k_numeric(NumericArgs a) {
         }
         TQ bq[R];
 #pragma unroll
-        for (int t = 0; t < R; ++t) bq[t] = (TQ)bsh[q * RM + t * G + g];
+        for (int t = 0; t < R; ++t) bq[t] = (TQ)bsh[q * RX + t * G + g];
 
         // ---- Householder QR (dgeqr2 conventions), applied to b as well
-        TQ rdiag[NC];
+        TQ rdiag[NC], rinv[NC];
 #pragma unroll
         for (int k = 0; k < NC; ++k) {
-            rdiag[k] = (TQ)0;
-            if (k < ncw) {
-                constexpr int dummy = 0;
-                (void)dummy;
-                const int tk = k / G, gk = k % G;
-                TQ sig = 0, alp = 0;
+            constexpr int dummy = 0;
+            (void)dummy;
+            const int tk = k / G, gk = k % G;
+            TQ sig = 0, alp = 0;
 #pragma unroll
-                for (int t = 0; t < R; ++t) {
-                    if (t < tk) continue;
-                    const TQ x = A[t][k];
-                    const bool below = (t > tk) || (g > gk);
-                    sig += below ? x * x : (TQ)0;
-                    if (t == tk) alp = (g == gk) ? x : (TQ)0;
-                }
-                sig = group_sum<G>(sig);
-                alp = group_sum<G>(alp);
-                const bool zero = !(sig > (TQ)0);
-                const TQ nrm = sqrt(alp * alp + sig);
-                const TQ beta = zero ? alp : -sgn_copy(nrm, alp);
-                const TQ tau = zero ? (TQ)0 : (beta - alp) / beta;
-                const TQ scal = zero ? (TQ)0 : (TQ)1 / (alp - beta);
-                rdiag[k] = beta;
-                TQ v[R];
-#pragma unroll
-                for (int t = 0; t < R; ++t) {
-                    if (t < tk) { v[t] = 0; continue; }
-                    const bool below = (t > tk) || (g > gk);
-                    const bool diag = (t == tk) && (g == gk);
-                    v[t] = below ? A[t][k] * scal : (diag ? (TQ)1 : (TQ)0);
-                    if (below) A[t][k] = v[t];
-                    if (diag) A[t][k] = beta;
-                }
-                TQ w[NC];
-#pragma unroll
-                for (int c = k + 1; c < NC; ++c) {
-                    TQ s = 0;
-#pragma unroll
-                    for (int t = tk; t < R; ++t) s += v[t] * A[t][c];
-                    w[c] = s;
-                }
-                TQ wb = 0;
-#pragma unroll
-                for (int t = tk; t < R; ++t) wb += v[t] * bq[t];
-#pragma unroll
-                for (int c = k + 1; c < NC; ++c)
-                    if (c < ncw) w[c] = group_sum<G>(w[c]) * tau;
-                wb = group_sum<G>(wb) * tau;
-#pragma unroll
-                for (int c = k + 1; c < NC; ++c)
-                    if (c < ncw)
-#pragma unroll
-                        for (int t = tk; t < R; ++t) A[t][c] -= w[c] * v[t];
-#pragma unroll
-                for (int t = tk; t < R; ++t) bq[t] -= wb * v[t];
+            for (int t = tk; t < R; ++t) {
+                const TQ x = A[t][k];
+                const bool below = (t > tk) || (g > gk);
+                sig += below ? x * x : (TQ)0;
+                if (t == tk) alp = (g == gk) ? x : (TQ)0;
             }
+            sig = group_sum<G>(sig);
+            alp = group_sum<G>(alp);
+            const bool zero = !(sig > (TQ)0);
+            const TQ nrm = root<TQ>(alp * alp + sig);
+            const TQ beta = zero ? alp : -copysign(nrm, alp);
+            const TQ ib = recip<TQ>(beta);
+            const TQ tau = zero ? (TQ)0 : (beta - alp) * ib;
+            const TQ scal = zero ? (TQ)0 : recip<TQ>(alp - beta);
+            rdiag[k] = beta;
+            rinv[k] = ib;
+            TQ v[R];
+#pragma unroll
+            for (int t = tk; t < R; ++t) {
+                const bool below = (t > tk) || (g > gk);
+                const bool diag = (t == tk) && (g == gk);
+                v[t] = below ? A[t][k] * scal : (diag ? (TQ)1 : (TQ)0);
+                A[t][k] = below ? v[t] : (diag ? beta : A[t][k]);
+            }
+            TQ w[NC + 1];
+#pragma unroll
+            for (int c = k + 1; c < NC; ++c) {
+                TQ s = 0;
+#pragma unroll
+                for (int t = tk; t < R; ++t) s += v[t] * A[t][c];
+                w[c] = s;
+            }
+            TQ wb = 0;
+#pragma unroll
+            for (int t = tk; t < R; ++t) wb += v[t] * bq[t];
+#pragma unroll
+            for (int c = k + 1; c < NC; ++c) w[c] = group_sum<G>(w[c]) * tau;
+            wb = group_sum<G>(wb) * tau;
+#pragma unroll
+            for (int c = k + 1; c < NC; ++c)
+#pragma unroll
+                for (int t = tk; t < R; ++t) A[t][c] -= w[c] * v[t];
+#pragma unroll
+            for (int t = tk; t < R; ++t) bq[t] -= wb * v[t];
         }
 
         // ---- rank test: |R_kk| <= 10 * rows * eps * max |R_ii|
@@ -240,88 +293,111 @@ k_numeric(NumericArgs a) {
         {
             TQ mx = 0;
 #pragma unroll
-            for (int k = 0; k < NC; ++k)
-                if (k < nJ) mx = fmax(mx, fabs(rdiag[k]));
+            for (int k = 0; k < NC; ++k) mx = fmax(mx, k < nJ ? fabs(rdiag[k]) : (TQ)0);
             const TQ eps = std::is_same<TQ, float>::value ? (TQ)1.1920928955078125e-07
                                                           : (TQ)2.220446049250313e-16;
             const TQ tol = (TQ)10 * (TQ)nrows * eps * mx;
             if (nJ > 0 && !(mx > (TQ)0)) bad_rank = true;
 #pragma unroll
-            for (int k = 0; k < NC; ++k)
-                if (k < nJ && !(fabs(rdiag[k]) > tol)) bad_rank = true;
+            for (int k = 0; k < NC; ++k) bad_rank |= (k < nJ) && !(fabs(rdiag[k]) > tol);
         }
 
-        // ---- back substitution R m = c1 (owner lane of row k computes,
-        //      then broadcasts inside the group)
+        // ---- back substitution R m = c1: the lane owning row k computes, then
+        //      the value is broadcast inside the group
         TQ m[NC];
 #pragma unroll
         for (int k = NC - 1; k >= 0; --k) {
-            m[k] = 0;
-            if (k < ncw) {
-                const int tk = k / G, gk = k % G;
-                TQ s = bq[tk];
+            const int tk = k / G, gk = k % G;
+            TQ s = bq[tk];
 #pragma unroll
-                for (int c = k + 1; c < NC; ++c) s -= A[tk][c] * m[c];
-                TQ mk = s / rdiag[k];
-                mk = group_bcast<G>(mk, g, gk);
-                m[k] = (k < nJ) ? mk : (TQ)0;
-            }
+            for (int c = k + 1; c < NC; ++c) s -= A[tk][c] * m[c];
+            const TQ mk = group_bcast<G>(s * rinv[k], g, gk);
+            m[k] = (k < nJ) ? mk : (TQ)0;
         }
 
-        double* rsh = tile + q * RM;  // residual vector (tile is free now)
-        // r = b - A mm over the gathered entries, in FP64; rows beyond nIj
-        // (penalty rows) are not part of the residual.
-        auto residual_pass = [&](const double (&mm)[NC]) {
-#pragma unroll
-            for (int t = 0; t < R; ++t) rsh[t * G + g] = bsh[q * RM + t * G + g];
-            wave_sync();
-#pragma unroll
-            for (int c = 0; c < NC; ++c) {
-                if (c < ncw) {
-                    if (c < nJ) {
-                        const int e0 = cst[q][c], e1 = cst[q][c + 1];
-                        const int vb = vbs[q][c];
-                        const double mc = mm[c];
-                        for (int e = g; e < e1 - e0; e += G) {
-                            const int p = a.posA[eo + e0 + e];
-                            rsh[p] -= a.Ak_v[vb + e] * mc;
-                        }
-                    }
-                    wave_sync();
-                }
-            }
-        };
-
+        double* rsh = tile + q * RX;  // residual vector (the tile is free now)
         double mfin[NC];
+        double rr;
         if constexpr (REFINE) {
+            // One FP64 pass r = b - A m over the gathered entries into rsh.
+            // Rows are distinct inside one column, so the lanes of a group
+            // never update one slot in the same instruction, and the wave's
+            // LDS operations complete in program order from column to column.
+            // The values are reloaded (L2-resident), all loads issued first.
             double m64[NC];
 #pragma unroll
             for (int c = 0; c < NC; ++c) m64[c] = (double)m[c];
+            double rr_it = 0.0;
 #pragma unroll
             for (int it = 0; it < (WEIGHTED ? 2 : 1); ++it) {
-                residual_pass(m64);
-                // g = A^T r (FP64) minus the penalty term p .* m
-                double gc[NC];
+#pragma unroll
+                for (int t = 0; t < R; ++t) rsh[t * G + g] = bsh[q * RX + t * G + g];
+                rsh[trash] = 0.0;
 #pragma unroll
                 for (int c = 0; c < NC; ++c) {
-                    double s = 0.0;
-                    if (c < ncw && c < nJ) {
-                        const int e0 = cst[q][c], e1 = cst[q][c + 1];
-                        const int vb = vbs[q][c];
-                        for (int e = g; e < e1 - e0; e += G) {
-                            const int p = a.posA[eo + e0 + e];
-                            s += a.Ak_v[vb + e] * rsh[p];
-                        }
+                    const int len = cln[q][c];
+                    const int e0 = cst[q][c];
+                    const int vb = vbs[q][c];
+#pragma unroll
+                    for (int u = 0; u < LPL; ++u) {
+                        const int e = g + u * G;
+                        const bool ok = e < len;
+                        const int ec = ok ? e : 0;
+                        const int p = a.posA[eo + e0 + ec];
+                        const double v = a.Ak_v[vb + ec];
+                        pp[c][u] = ok ? p : trash;
+                        pv[c][u] = ok ? v : 0.0;
                     }
-                    gc[c] = s;
+                }
+                wave_sync();
+#pragma unroll
+                for (int c = 0; c < NC; ++c) {
+                    const double mc = m64[c];
+#pragma unroll
+                    for (int u = 0; u < LPL; ++u) rsh[pp[c][u]] -= pv[c][u] * mc;
+                    const int len = cln[q][c];
+                    if (len > LPL * G) {  // long columns
+                        const int e0 = cst[q][c], vb = vbs[q][c];
+                        for (int e = g + LPL * G; e < len; e += G) rsh[a.posA[eo + e0 + e]] -= a.Ak_v[vb + e] * mc;
+                    }
+                }
+                wave_sync();
+                // ||r||^2 over the rows of I_j and gA = A^T r (FP64)
+                double r2 = 0.0;
+#pragma unroll
+                for (int t = 0; t < R; ++t) {
+                    const double x = rsh[t * G + g];
+                    r2 += (t * G + g < nIj) ? x * x : 0.0;
+                }
+                rr_it = group_sum<G>(r2);
+                double gA[NC], gc[NC];
+#pragma unroll
+                for (int c = 0; c < NC; ++c) {
+                    double sacc = 0.0;
+#pragma unroll
+                    for (int u = 0; u < LPL; ++u) sacc += pv[c][u] * rsh[pp[c][u]];
+                    const int len = cln[q][c];
+                    if (len > LPL * G) {
+                        const int e0 = cst[q][c], vb = vbs[q][c];
+                        for (int e = g + LPL * G; e < len; e += G) sacc += a.Ak_v[vb + e] * rsh[a.posA[eo + e0 + e]];
+                    }
+                    gA[c] = sacc;
                 }
 #pragma unroll
-                for (int c = 0; c < NC; ++c)
-                    if (c < ncw) gc[c] = group_sum<G>(gc[c]);
+                for (int c = 0; c < NC; ++c) {
+                    gA[c] = group_sum<G>(gA[c]);
+                    gc[c] = gA[c];
+                }
+                // normal-equation residual of the penalised problem: g - P m
+                double pen[NC];
+#pragma unroll
+                for (int c = 0; c < NC; ++c) pen[c] = 0.0;
                 if constexpr (WEIGHTED) {
 #pragma unroll
-                    for (int c = 0; c < NC; ++c)
-                        if (valid && c < nJ) gc[c] -= a.mu * (1.0 / a.w[scol + c] - 1.0) * m64[c];
+                    for (int c = 0; c < NC; ++c) {
+                        if (valid && c < nJ) pen[c] = a.mu * (1.0 / a.w[scol + c] - 1.0);
+                        gc[c] -= pen[c] * m64[c];
+                    }
                 }
                 // y = R^{-T} g (FP32): y_c = (g_c - sum_{k<c} R_kc y_k) / R_cc
                 TQ ydist[R];
@@ -330,56 +406,63 @@ k_numeric(NumericArgs a) {
                 for (int t = 0; t < R; ++t) ydist[t] = 0;
 #pragma unroll
                 for (int c = 0; c < NC; ++c) {
-                    yrep[c] = 0;
-                    if (c < ncw) {
-                        TQ part = 0;
+                    TQ part = 0;
 #pragma unroll
-                        for (int t = 0; t < R; ++t) {
-                            const int row = t * G + g;
-                            if (t * G < c) part += (row < c) ? A[t][c] * ydist[t] : (TQ)0;
-                        }
-                        part = group_sum<G>(part);
-                        TQ yc = ((TQ)gc[c] - part) / rdiag[c];
-                        yc = (c < nJ) ? yc : (TQ)0;
-                        yrep[c] = yc;
-                        if (g == c % G) ydist[c / G] = yc;
+                    for (int t = 0; t < R; ++t) {
+                        const int row = t * G + g;
+                        if (t * G < c) part += (row < c) ? A[t][c] * ydist[t] : (TQ)0;
                     }
+                    part = group_sum<G>(part);
+                    TQ yc = ((TQ)gc[c] - part) * rinv[c];
+                    yc = (c < nJ) ? yc : (TQ)0;
+                    yrep[c] = yc;
+                    if (g == c % G) ydist[c / G] = yc;
                 }
                 // delta = R^{-1} y
                 TQ dl[NC];
 #pragma unroll
                 for (int k = NC - 1; k >= 0; --k) {
-                    dl[k] = 0;
-                    if (k < ncw) {
-                        const int tk = k / G, gk = k % G;
-                        TQ s = yrep[k];
+                    const int tk = k / G, gk = k % G;
+                    TQ sacc = yrep[k];
 #pragma unroll
-                        for (int c = k + 1; c < NC; ++c) s -= A[tk][c] * dl[c];
-                        TQ dk = s / rdiag[k];
-                        dk = group_bcast<G>(dk, g, gk);
-                        dl[k] = (k < nJ) ? dk : (TQ)0;
-                    }
+                    for (int c = k + 1; c < NC; ++c) sacc -= A[tk][c] * dl[c];
+                    const TQ dk = group_bcast<G>(sacc * rinv[k], g, gk);
+                    dl[k] = (k < nJ) ? dk : (TQ)0;
                 }
+                // ||b - A(m + d)||^2 = ||r||^2 - 2 d^T A^T r + ||A d||^2, and
+                // ||A d||^2 = ||R d||^2 - d^T P d with R d = y (second order in d)
+                double dg = 0.0, yy = 0.0, pdd = 0.0;
 #pragma unroll
-                for (int c = 0; c < NC; ++c) m64[c] += (double)dl[c];
+                for (int c = 0; c < NC; ++c) {
+                    const double d = (double)dl[c];
+                    dg += d * gA[c];
+                    yy += (double)yrep[c] * (double)yrep[c];
+                    pdd += pen[c] * d * d;
+                    m64[c] += d;
+                }
+                rr_it = rr_it - 2.0 * dg + (yy - pdd);
             }
 #pragma unroll
             for (int c = 0; c < NC; ++c) mfin[c] = m64[c];
+            rr = rr_it + outj;
         } else {
 #pragma unroll
             for (int c = 0; c < NC; ++c) mfin[c] = (double)m[c];
-        }
-
-        // ---- column residual rho_j = ||b - A m||^2 + out_j (FP64)
-        residual_pass(mfin);
-        double rr = 0.0;
+            // ||c2||^2: rows nJ.. of Q^T b (the stacked form adds m^T P m)
+            double r2 = 0.0;
 #pragma unroll
-        for (int t = 0; t < R; ++t) {
-            const double x = rsh[t * G + g];
-            rr += (t * G + g < nIj) ? x * x : 0.0;
+            for (int t = 0; t < R; ++t) {
+                const double x = (double)bq[t];
+                r2 += (t * G + g >= nJ) ? x * x : 0.0;
+            }
+            rr = group_sum<G>(r2);
+            if constexpr (WEIGHTED) {
+#pragma unroll
+                for (int c = 0; c < NC; ++c)
+                    if (valid && c < nJ) rr -= a.mu * (1.0 / a.w[scol + c] - 1.0) * mfin[c] * mfin[c];
+            }
+            rr += outj;
         }
-        rr = group_sum<G>(rr) + outj;
-        wave_sync();
 
         // ---- outputs
         bool nonfinite = !isfinite(rr);
@@ -402,40 +485,42 @@ k_numeric(NumericArgs a) {
     }
 }
 
-template <typename TQ, int G, int R, int NC, int TC, bool W>
+template <typename TQ, int G, int R, int NC, int TC, int LPL, bool W>
 hipError_t launch_numeric(const NumericArgs& args, int grid, hipStream_t s) {
-    hipLaunchKernelGGL((k_numeric<TQ, G, R, NC, TC, W>), dim3(grid), dim3(64), 0, s, args);
+    hipLaunchKernelGGL((k_numeric<TQ, G, R, NC, TC, LPL, W>), dim3(grid), dim3(64), 0, s, args);
     return hipGetLastError();
 }
 
-#define SAM_VARIANT(TQ, PREC, G, R, NC, TC, W) \
-    NumericVariant{PREC, G, R, NC, W, &launch_numeric<TQ, G, R, NC, TC, W>}
+// LPL: entries of one A_k column a lane moves with static indices (longer
+// columns fall back to a loop over memory), sized for 5- to 9-point stencils.
+#define SAM_VARIANT(TQ, PREC, G, R, NC, TC, LPL, W) \
+    NumericVariant{PREC, G, R, NC, W, &launch_numeric<TQ, G, R, NC, TC, LPL, W>}
 
 // Menu per precision, cheapest first.  Shapes of the workloads: 2D 5-point
 // level 1 (13 x 5), level 2 (25 x 13); 3D 7-point level 2 (63 x 25); 2D
 // 9-point level 2 with thresholds (<= 49 x 24); weighted 3D (88 x 25).
 const NumericVariant kMenu[] = {
     // FP32 + refinement
-    SAM_VARIANT(float, 1, 2, 8, 8, 4, false),
-    SAM_VARIANT(float, 1, 4, 7, 13, 2, false),
-    SAM_VARIANT(float, 1, 4, 8, 16, 2, false),
-    SAM_VARIANT(float, 1, 16, 4, 25, 1, false),
-    SAM_VARIANT(float, 1, 16, 4, 32, 1, false),
-    SAM_VARIANT(float, 1, 32, 4, 32, 1, false),
+    SAM_VARIANT(float, 1, 2, 8, 5, 4, 3, false),
+    SAM_VARIANT(float, 1, 2, 8, 8, 4, 3, false),
+    SAM_VARIANT(float, 1, 4, 7, 13, 2, 2, false),
+    SAM_VARIANT(float, 1, 4, 8, 16, 2, 2, false),
+    SAM_VARIANT(float, 1, 16, 4, 25, 1, 1, false),
+    SAM_VARIANT(float, 1, 32, 4, 32, 1, 1, false),
     // FP64
-    SAM_VARIANT(double, 0, 2, 8, 8, 4, false),
-    SAM_VARIANT(double, 0, 4, 7, 13, 2, false),
-    SAM_VARIANT(double, 0, 8, 4, 16, 2, false),
-    SAM_VARIANT(double, 0, 32, 2, 25, 1, false),
-    SAM_VARIANT(double, 0, 32, 2, 32, 1, false),
-    SAM_VARIANT(double, 0, 64, 2, 32, 1, false),
+    SAM_VARIANT(double, 0, 2, 8, 5, 4, 3, false),
+    SAM_VARIANT(double, 0, 2, 8, 8, 4, 3, false),
+    SAM_VARIANT(double, 0, 4, 7, 13, 2, 2, false),
+    SAM_VARIANT(double, 0, 8, 4, 16, 2, 1, false),
+    SAM_VARIANT(double, 0, 32, 2, 25, 1, 1, false),
+    SAM_VARIANT(double, 0, 64, 2, 32, 1, 1, false),
     // soft-weighted (stacked penalty rows)
-    SAM_VARIANT(float, 1, 4, 8, 13, 2, true),
-    SAM_VARIANT(float, 1, 32, 3, 25, 1, true),
-    SAM_VARIANT(float, 1, 64, 2, 32, 1, true),
-    SAM_VARIANT(double, 0, 4, 8, 13, 2, true),
-    SAM_VARIANT(double, 0, 64, 2, 25, 1, true),
-    SAM_VARIANT(double, 0, 64, 2, 32, 1, true),
+    SAM_VARIANT(float, 1, 4, 8, 13, 2, 2, true),
+    SAM_VARIANT(float, 1, 32, 3, 25, 1, 1, true),
+    SAM_VARIANT(float, 1, 64, 2, 32, 1, 1, true),
+    SAM_VARIANT(double, 0, 4, 8, 13, 2, 2, true),
+    SAM_VARIANT(double, 0, 64, 2, 25, 1, 1, true),
+    SAM_VARIANT(double, 0, 64, 2, 32, 1, 1, true),
 };
 
 }  // namespace
