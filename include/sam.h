@@ -266,11 +266,14 @@ sam_status sam_sequence_create(sam_ctx* ctx, const sam_csc* A0, const sam_csc* A
 
 sam_status sam_sequence_destroy(sam_seq* seq);
 
-/* nnz bound per map (host) and, for source k, the device arrays holding its
- * pattern after a run (valid until the next run). */
+/* nnz bound per map (host): the size M_vals[k] must have. */
 sam_status sam_sequence_info(const sam_seq* seq, int64_t* nnz_bound);
-sam_status sam_sequence_pattern(const sam_seq* seq, int32_t k, const int32_t** S_colptr,
-                                const int32_t** S_rowind);
+
+/* Copy the pattern of source k as computed by the last run (static mode:
+ * the shared pattern) into caller arrays S_colptr (n+1) and S_rowind (at most
+ * nnz_bound entries); *nnz_S (host) receives its size.  Synchronising. */
+sam_status sam_sequence_pattern(sam_seq* seq, int32_t k, int32_t* S_colptr, int32_t* S_rowind, int64_t* nnz_S,
+                                sam_stream_t stream);
 
 /* Build every map of the sequence: Ak_vals (host array of n_src device
  * pointers), M_vals (host array of n_src device pointers), res2 (device,

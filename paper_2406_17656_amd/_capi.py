@@ -70,7 +70,7 @@ SIGNATURES = {
                                       ctypes.POINTER(c_void_p), P]),
     "sam_sequence_destroy": (c_int32, [P]),
     "sam_sequence_info": (c_int32, [P, ctypes.POINTER(c_int64)]),
-    "sam_sequence_pattern": (c_int32, [P, c_int32, ctypes.POINTER(c_void_p), ctypes.POINTER(c_void_p)]),
+    "sam_sequence_pattern": (c_int32, [P, c_int32, P, P, ctypes.POINTER(c_int64), P]),
     "sam_sequence_run": (c_int32, [P, P, P, P, P]),
     "sam_build_weighted": (c_int32, [P, P, P, P, c_double, c_int32, P, P, P, P]),
     "sam_backward": (c_int32, [P, P, P, P, c_double, c_double, c_int32, P, P, P, P, P]),

@@ -1,53 +1,21 @@
 // sam_capi.cpp -- host implementation of the C ABI declared in include/sam.h:
-// argument validation, context / plan / sequence objects, device memory
+// argument validation, context / pattern / plan objects, device memory
 // management and the launch sequence of the gfx950 kernels.
-#include "sam.h"
-#include "sam_kernels.hpp"
+#include "sam_host.hpp"
 
-#include <hip/hip_runtime.h>
-
-#include <algorithm>
 #include <climits>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
-#include <string>
-#include <vector>
 
 using samk::BucketTable;
 using samk::NumericArgs;
 using samk::NumericVariant;
+using namespace samh;
 
-namespace {
+namespace samh {
 
-struct DevBuf {
-    void* p = nullptr;
-    size_t bytes = 0;
-};
 
-}  // namespace
-
-struct sam_ctx {
-    int device = SAM_NO_DEVICE;
-    std::string err;
-    unsigned long long* d_status = nullptr;
-    DevBuf ws;  // scratch for synchronising calls
-    // last pattern from sam_pattern_count
-    DevBuf S_cp, S_ri;
-    int64_t S_nnz = -1;
-    int S_n = -1;
-    const int32_t* key_cp = nullptr;
-    const int32_t* key_ri = nullptr;
-    const double* key_val = nullptr;
-    sam_pattern_spec key_spec{};
-    int CUs = 256;
-};
-
-namespace {
-
-constexpr unsigned long long kStatusClear = 0x7fffffffffffffffull;
-
-sam_status fail(sam_ctx* ctx, sam_status st, const char* fmt, ...) __attribute__((format(printf, 3, 4)));
 sam_status fail(sam_ctx* ctx, sam_status st, const char* fmt, ...) {
     if (ctx) {
         char buf[512];
@@ -60,17 +28,8 @@ sam_status fail(sam_ctx* ctx, sam_status st, const char* fmt, ...) {
     return st;
 }
 
-#define HIP_TRY(ctx, expr)                                                                       \
-    do {                                                                                         \
-        hipError_t e_ = (expr);                                                                  \
-        if (e_ != hipSuccess)                                                                    \
-            return fail((ctx), e_ == hipErrorOutOfMemory ? SAM_ERR_NOMEM : SAM_ERR_HIP,          \
-                        "%s: %s (%s:%d)", #expr, hipGetErrorString(e_), __FILE__, __LINE__);     \
-    } while (0)
 
-hipStream_t S(sam_stream_t s) { return reinterpret_cast<hipStream_t>(s); }
 
-size_t align256(size_t b) { return (b + 255) / 256 * 256; }
 
 hipError_t grow(DevBuf& b, size_t bytes) {
     if (b.bytes >= bytes && b.p) return hipSuccess;
@@ -96,18 +55,6 @@ void release(DevBuf& b) {
     b.bytes = 0;
 }
 
-// bump allocator over a DevBuf
-struct Carve {
-    char* base;
-    size_t off = 0;
-    explicit Carve(void* p) : base((char*)p) {}
-    template <typename T>
-    T* take(size_t count) {
-        T* r = (T*)(base + off);
-        off += align256(count * sizeof(T));
-        return r;
-    }
-};
 
 sam_status check_ctx(sam_ctx* ctx) {
     if (!ctx) return SAM_ERR_ARG;
@@ -156,21 +103,13 @@ samk::SparsifySpec to_sp(const sam_pattern_spec* spec) {
     return sp;
 }
 
-bool prec_ok(sam_precision p) { return p == SAM_PREC_F64 || p == SAM_PREC_F32_REFINE; }
 
-// read one device int64 value (synchronising)
-template <typename T>
-hipError_t read_back(const T* dptr, T* host, hipStream_t s) {
-    hipError_t e = hipMemcpyAsync(host, dptr, sizeof(T), hipMemcpyDeviceToHost, s);
-    if (e != hipSuccess) return e;
-    return hipStreamSynchronize(s);
-}
 
 // Pattern pipeline: B = sparsify(A_k) (diagonal added), then S = B, and
 // p-1 times S <- expand(S, B).  Produces device arrays into out_cp/out_ri
 // (grown as needed) and the host nnz.
 sam_status compute_pattern(sam_ctx* ctx, const sam_csc* Ak, const sam_pattern_spec* spec, DevBuf& out_cp,
-                           DevBuf& out_ri, int64_t* nnz_out, hipStream_t s) {
+                           DevBuf& out_ri, int64_t* nnz_out, hipStream_t s, std::vector<int64_t>* level_nnz) {
     const int n = Ak->n;
     samk::SparsifySpec sp = to_sp(spec);
     // workspace: counts (n int), scan out (n+1 int64), scan temp, D (n double),
@@ -202,6 +141,7 @@ sam_status compute_pattern(sam_ctx* ctx, const sam_csc* Ak, const sam_pattern_sp
     HIP_TRY(ctx, samk::sparsify_fill(n, Ak->colptr, Ak->rowind, Ak->val, sp, D, B_cp, B_ri, s));
     int64_t nnzB = 0;
     HIP_TRY(ctx, read_back(off + n, &nnzB, s));
+    if (level_nnz) level_nnz->assign(1, nnzB);
     const int* cur_cp = B_cp;
     const int* cur_ri = B_ri;
     int64_t cur_nnz = nnzB;
@@ -225,6 +165,7 @@ sam_status compute_pattern(sam_ctx* ctx, const sam_csc* Ak, const sam_pattern_sp
         cur_cp = (int*)ncp.p;
         cur_ri = (int*)nri.p;
         cur_nnz = tot;
+        if (level_nnz) level_nnz->push_back(tot);
     }
     int hflags[2] = {0, n};
     HIP_TRY(ctx, hipMemcpyAsync(hflags, flags, sizeof hflags, hipMemcpyDeviceToHost, s));
@@ -245,67 +186,31 @@ sam_status compute_pattern(sam_ctx* ctx, const sam_csc* Ak, const sam_pattern_sp
     return st;
 }
 
-}  // namespace
 
-// ------------------------------------------------------------------ plan
-
-namespace {
-
-// One (precision, weighted) combination of a plan: the bucket order of the
-// columns and the kernel variant per bucket.
-struct Combo {
-    bool ok = false;
-    std::string why;
-    std::vector<const NumericVariant*> variants;
-    int* queue = nullptr;   // device n
-    int* bstart = nullptr;  // device nb+1
-    std::vector<int> counts;
-};
-
-}  // namespace
-
-struct sam_plan {
-    sam_ctx* ctx = nullptr;
-    int n = 0;
-    int nnzA = 0, nnzA0 = 0;
-    int64_t nnzS = 0;
-    const int *Ak_cp = nullptr, *Ak_ri = nullptr, *A0_cp = nullptr, *A0_ri = nullptr;
-    const int *S_cp = nullptr, *S_ri = nullptr;
-    DevBuf mem;          // nI, eoff, posA, posB, queues, colbuf, reduce temp
-    int* nI = nullptr;
-    int64_t* eoff = nullptr;
-    unsigned char* posA = nullptr;
-    unsigned char* posB = nullptr;
-    double* colbuf = nullptr;
-    void* rtemp = nullptr;
-    int64_t E = 0;
-    int max_rows = 0, max_cols = 0;
-    // algorithmic flop counts of one build (dense column blocks)
-    double fl_qr32 = 0.0, fl_ref64 = 0.0, fl_f64 = 0.0;
-    Combo combo[2][2];  // [prec][weighted]
-    // backward staging (lazily allocated)
-    DevBuf bwd;
-};
-
-namespace {
-
-sam_status plan_combo(sam_plan* pl, int prec, int weighted, void* temp, int* unfit_d, hipStream_t s) {
-    sam_ctx* ctx = pl->ctx;
-    Combo& cb = pl->combo[prec][weighted];
+BucketTable menu_table(int prec, int weighted, std::vector<const NumericVariant*>* variants) {
     int cnt = 0;
     const NumericVariant* menu = samk::numeric_menu(&cnt);
     BucketTable tab{};
     tab.nb = 0;
+    tab.rows_plus_cols = weighted;
     for (int i = 0; i < cnt && tab.nb < samk::kMaxBuckets; ++i) {
         if (menu[i].prec != prec || menu[i].weighted != weighted) continue;
         tab.max_rows[tab.nb] = menu[i].max_rows();
         tab.max_cols[tab.nb] = menu[i].NC;
-        tab.rows_plus_cols = weighted;
-        cb.variants.push_back(&menu[i]);
+        if (variants) variants->push_back(&menu[i]);
         tab.nb++;
     }
+    return tab;
+}
+
+sam_status plan_combo(sam_plan* pl, int prec, int weighted, void* temp, int* unfit_d, hipStream_t s) {
+    sam_ctx* ctx = pl->ctx;
+    Combo& cb = pl->combo[prec][weighted];
+    cb.variants.clear();
+    BucketTable tab = menu_table(prec, weighted, &cb.variants);
+    cb.tab = tab;
     HIP_TRY(ctx, hipMemsetAsync(unfit_d, 0, sizeof(int), s));
-    HIP_TRY(ctx, samk::bucket_sort(pl->n, pl->S_cp, pl->nI, tab, cb.queue, cb.bstart, unfit_d, temp, s));
+    HIP_TRY(ctx, samk::bucket_sort(pl->n, pl->S_cp, pl->nI, tab, cb.queue, cb.bstart, unfit_d, nullptr, temp, s));
     std::vector<int> hb(tab.nb + 1, 0);
     int unfit = 0;
     HIP_TRY(ctx, hipMemcpyAsync(hb.data(), cb.bstart, sizeof(int) * (tab.nb + 1), hipMemcpyDeviceToHost, s));
@@ -324,7 +229,52 @@ sam_status plan_combo(sam_plan* pl, int prec, int weighted, void* temp, int* unf
     return SAM_OK;
 }
 
-}  // namespace
+
+// Launch every non-empty bucket of a combination, then the column-residual sum.
+sam_status run_numeric(sam_plan* pl, const double* Ak_val, const double* A0_val, const double* w, double mu, int prec,
+                       int weighted, void* M_val, double* col_res2, double* res2, hipStream_t s) {
+    sam_ctx* ctx = pl->ctx;
+    Combo& cb = pl->combo[prec][weighted];
+    if (!cb.ok) return fail(ctx, SAM_ERR_UNSUPPORTED, "%s", cb.why.c_str());
+    NumericArgs a{};
+    a.n = pl->n;
+    a.Ak_cp = pl->Ak_cp;
+    a.Ak_v = Ak_val;
+    a.A0_cp = pl->A0_cp;
+    a.A0_v = A0_val;
+    a.S_cp = pl->S_cp;
+    a.S_ri = pl->S_ri;
+    a.nI = pl->nI;
+    a.eoff = pl->eoff;
+    a.posA = pl->posA;
+    a.posB = pl->posB;
+    a.queue = cb.queue;
+    a.bstart = cb.bstart;
+    a.M = M_val;
+    double* cols = col_res2 ? col_res2 : pl->colbuf;
+    a.col_res2 = cols;
+    a.status = ctx->d_status;
+    a.w = w;
+    a.mu = mu;
+    for (size_t b = 0; b < cb.variants.size(); ++b) {
+        // bucket sizes: exact (plan) or an upper bound (replanned sequence,
+        // where the kernel reads the actual count from bstart on the device)
+        const int cnt = cb.counts[b];
+        if (cnt <= 0) continue;
+        const NumericVariant* v = cb.variants[b];
+        a.bucket = (int)b;
+        int groups = (cnt + v->per_wave() - 1) / v->per_wave();
+        int cap = ctx->CUs * 16;
+        int grid = std::min(groups, cap);
+        if (grid >= 64) grid = grid / 8 * 8;
+        HIP_TRY(ctx, v->launch(a, grid, s));
+    }
+    if (res2 && pl->n > 0) HIP_TRY(ctx, samk::reduce_sum(cols, pl->n, res2, pl->rtemp, s));
+    if (res2 && pl->n == 0) HIP_TRY(ctx, hipMemsetAsync(res2, 0, sizeof(double), s));
+    return SAM_OK;
+}
+
+}  // namespace samh
 
 extern "C" {
 
@@ -620,51 +570,6 @@ sam_status sam_plan_info(const sam_plan* plan, int32_t* n, int32_t* max_rows, in
 
 }  // extern "C"
 
-namespace {
-
-// Launch every non-empty bucket of a combination, then the column-residual sum.
-sam_status run_numeric(sam_plan* pl, const double* Ak_val, const double* A0_val, const double* w, double mu, int prec,
-                       int weighted, void* M_val, double* col_res2, double* res2, hipStream_t s) {
-    sam_ctx* ctx = pl->ctx;
-    Combo& cb = pl->combo[prec][weighted];
-    if (!cb.ok) return fail(ctx, SAM_ERR_UNSUPPORTED, "%s", cb.why.c_str());
-    NumericArgs a{};
-    a.n = pl->n;
-    a.Ak_cp = pl->Ak_cp;
-    a.Ak_v = Ak_val;
-    a.A0_cp = pl->A0_cp;
-    a.A0_v = A0_val;
-    a.S_cp = pl->S_cp;
-    a.S_ri = pl->S_ri;
-    a.nI = pl->nI;
-    a.eoff = pl->eoff;
-    a.posA = pl->posA;
-    a.posB = pl->posB;
-    a.queue = cb.queue;
-    a.bstart = cb.bstart;
-    a.M = M_val;
-    double* cols = col_res2 ? col_res2 : pl->colbuf;
-    a.col_res2 = cols;
-    a.status = ctx->d_status;
-    a.w = w;
-    a.mu = mu;
-    for (size_t b = 0; b < cb.variants.size(); ++b) {
-        const int cnt = cb.counts[b];
-        if (cnt <= 0) continue;
-        const NumericVariant* v = cb.variants[b];
-        a.bucket = (int)b;
-        int groups = (cnt + v->per_wave() - 1) / v->per_wave();
-        int cap = ctx->CUs * 16;
-        int grid = std::min(groups, cap);
-        if (grid >= 64) grid = grid / 8 * 8;
-        HIP_TRY(ctx, v->launch(a, grid, s));
-    }
-    if (res2 && pl->n > 0) HIP_TRY(ctx, samk::reduce_sum(cols, pl->n, res2, pl->rtemp, s));
-    if (res2 && pl->n == 0) HIP_TRY(ctx, hipMemsetAsync(res2, 0, sizeof(double), s));
-    return SAM_OK;
-}
-
-}  // namespace
 
 extern "C" {
 

@@ -63,10 +63,11 @@ struct BucketTable {
 };
 // Stable counting sort of the columns by bucket: queue[] lists the columns
 // of bucket 0, then bucket 1, ...; bstart[b] (device, nb+1) are the bucket
-// offsets.  Columns that fit no bucket raise *unfit (device int, = count).
+// offsets.  Columns that fit no bucket are counted in *unfit (device int,
+// may be null) and reported in the status word (may be null).
 size_t bucket_temp_bytes(int n);
 hipError_t bucket_sort(int n, const int* S_cp, const int* nI, BucketTable tab, int* queue,
-                       int* bstart, int* unfit, void* temp, hipStream_t s);
+                       int* bstart, int* unfit, unsigned long long* status, void* temp, hipStream_t s);
 
 // --------------------------------------------------------------- numeric
 struct NumericArgs {

@@ -1,20 +1,345 @@
-// sam_sequence.cpp -- sequence and adjoint entry points (in progress).
-#include "sam.h"
+// sam_sequence.cpp -- a sequence of sources A_1..A_N mapped to the target A_0
+// (Section 2: every map goes back to A_0), run as one HIP graph.
+//
+// Static mode (structure-only pattern, replan_each_run = 0): the pattern
+// S((I + B)^p) and the plan are computed once at creation; a run is the
+// numeric build and Frobenius residual of every map.
+// Replanning mode (value-dependent sparsification, or replan_each_run = 1):
+// a run recomputes, for every source, the sparsified pattern, the row sets,
+// gather positions and buckets on the device, into buffers sized by the
+// structural bound (the pattern of the unsparsified A_k contains every
+// sparsified one), so no host synchronisation and no allocation is needed
+// and the whole run is capturable.  Bucket sizes then stay on the device and
+// every kernel variant launches with the bound grid.
+#include "sam_host.hpp"
+
+#include <climits>
+#include <cstring>
+
+using namespace samh;
+
+struct sam_seq {
+    sam_ctx* ctx = nullptr;
+    int n = 0;
+    int n_src = 0;
+    int prec = 1;  // 0 FP64, 1 FP32 + refinement
+    sam_pattern_spec spec{};
+    bool replan = false;
+    const int *A0_cp = nullptr, *A0_ri = nullptr, *Ak_cp = nullptr, *Ak_ri = nullptr;
+    const double* A0_val = nullptr;
+    int nnzA = 0, nnzA0 = 0;
+    // structural pattern (the pattern of every map in static mode, the bound
+    // otherwise) and its plan
+    DevBuf S_cp, S_ri;
+    int64_t nnzS = 0;
+    std::vector<int64_t> level_nnz;
+    sam_plan* plan = nullptr;
+    // replanning mode
+    DevBuf dyn;
+    sam_plan dplan;                // views into dyn
+    std::vector<int*> Sk_cp, Sk_ri;
+    int *counts = nullptr, *B_cp = nullptr, *B_ri = nullptr, *L_cp[2] = {nullptr, nullptr},
+        *L_ri[2] = {nullptr, nullptr}, *flags = nullptr;
+    int64_t* off = nullptr;
+    void *stemp = nullptr, *btemp = nullptr;
+    double* D = nullptr;
+    // graph
+    hipStream_t cap = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<const void*> key;
+};
+
+namespace {
+
+void drop_graph(sam_seq* q) {
+    if (q->exec) (void)hipGraphExecDestroy(q->exec);
+    if (q->graph) (void)hipGraphDestroy(q->graph);
+    q->exec = nullptr;
+    q->graph = nullptr;
+    q->key.clear();
+}
+
+// Symbolic work for source k (replanning mode), then its numeric build.
+sam_status enqueue_replanned(sam_seq* q, int k, const double* vals, void* M, double* res2, hipStream_t s) {
+    sam_ctx* ctx = q->ctx;
+    const int n = q->n;
+    const samk::SparsifySpec sp = to_sp(&q->spec);
+    const int p = q->spec.power;
+    int* Scp = q->Sk_cp[k];
+    int* Sri = q->Sk_ri[k];
+    // B = S(A~_k) plus the diagonal (written straight into S_k when p = 1)
+    int* bcp = p == 1 ? Scp : q->B_cp;
+    int* bri = p == 1 ? Sri : q->B_ri;
+    HIP_TRY(ctx, samk::sparsify_count(n, q->Ak_cp, q->Ak_ri, vals, sp, q->D, q->counts, s));
+    HIP_TRY(ctx, samk::scan_counts(q->counts, n, q->off, bcp, nullptr, q->stemp, s));
+    HIP_TRY(ctx, samk::sparsify_fill(n, q->Ak_cp, q->Ak_ri, vals, sp, q->D, bcp, bri, s));
+    const int* cur_cp = bcp;
+    const int* cur_ri = bri;
+    for (int lev = 1; lev < p; ++lev) {
+        int* dcp = lev == p - 1 ? Scp : q->L_cp[lev & 1];
+        int* dri = lev == p - 1 ? Sri : q->L_ri[lev & 1];
+        HIP_TRY(ctx, samk::expand_count(n, cur_cp, cur_ri, q->B_cp, q->B_ri, q->counts, nullptr, s));
+        HIP_TRY(ctx, samk::scan_counts(q->counts, n, q->off, dcp, nullptr, q->stemp, s));
+        HIP_TRY(ctx, samk::expand_fill(n, cur_cp, cur_ri, q->B_cp, q->B_ri, dcp, dri, s));
+        cur_cp = dcp;
+        cur_ri = dri;
+    }
+    // plan of the column problems on S_k
+    sam_plan* pl = &q->dplan;
+    pl->S_cp = Scp;
+    pl->S_ri = Sri;
+    HIP_TRY(ctx, samk::plan_gather_count(n, Scp, Sri, q->Ak_cp, q->counts, s));
+    HIP_TRY(ctx, samk::scan_counts(q->counts, n, pl->eoff, nullptr, nullptr, q->stemp, s));
+    HIP_TRY(ctx, samk::plan_positions(n, Scp, Sri, q->Ak_cp, q->Ak_ri, q->A0_cp, q->A0_ri, pl->eoff, pl->nI,
+                                      pl->posA, pl->posB, s));
+    Combo& cb = pl->combo[q->prec][0];
+    HIP_TRY(ctx, samk::bucket_sort(n, Scp, pl->nI, cb.tab, cb.queue, cb.bstart, nullptr, ctx->d_status, q->btemp, s));
+    return run_numeric(pl, vals, q->A0_val, nullptr, 0.0, q->prec, 0, M, nullptr, res2, s);
+}
+
+sam_status enqueue_run(sam_seq* q, const double* const* vals, void* const* M, double* res2, hipStream_t s) {
+    for (int k = 0; k < q->n_src; ++k) {
+        sam_status st = q->replan ? enqueue_replanned(q, k, vals[k], M[k], res2 + k, s)
+                                  : run_numeric(q->plan, vals[k], q->A0_val, nullptr, 0.0, q->prec, 0, M[k], nullptr,
+                                                res2 + k, s);
+        if (st) return st;
+    }
+    return SAM_OK;
+}
+
+}  // namespace
 
 extern "C" {
-sam_status sam_sequence_create(sam_ctx*, const sam_csc*, const sam_csc*, const sam_pattern_spec*, int32_t,
-                               sam_precision, int32_t, sam_seq** seq, sam_stream_t) {
-    if (seq) *seq = nullptr;
-    return SAM_ERR_UNSUPPORTED;
+
+sam_status sam_sequence_create(sam_ctx* ctx, const sam_csc* A0, const sam_csc* Ak_struct, const sam_pattern_spec* spec,
+                               int32_t n_src, sam_precision prec, int32_t replan_each_run, sam_seq** out,
+                               sam_stream_t stream) {
+    if (check_ctx(ctx)) return SAM_ERR_ARG;
+    if (!out) return fail(ctx, SAM_ERR_ARG, "seq is NULL");
+    *out = nullptr;
+    sam_status st;
+    if ((st = check_csc_args(ctx, A0, "A0", true))) return st;
+    if ((st = check_csc_args(ctx, Ak_struct, "Ak_struct", false))) return st;
+    if ((st = check_spec(ctx, spec))) return st;
+    if (A0->n != Ak_struct->n) return fail(ctx, SAM_ERR_SHAPE, "A0 and Ak_struct differ in order");
+    if (n_src < 1) return fail(ctx, SAM_ERR_ARG, "n_src must be >= 1 (got %d)", n_src);
+    if (!prec_ok(prec)) return fail(ctx, SAM_ERR_ARG, "unknown precision %d", (int)prec);
+    if ((st = need_device(ctx))) return st;
+    hipStream_t s = S(stream);
+    const int n = A0->n;
+
+    sam_seq* q = new (std::nothrow) sam_seq();
+    if (!q) return fail(ctx, SAM_ERR_NOMEM, "host allocation failed");
+    q->ctx = ctx;
+    q->n = n;
+    q->n_src = n_src;
+    q->prec = prec == SAM_PREC_F32_REFINE ? 1 : 0;
+    q->spec = *spec;
+    q->replan = replan_each_run != 0 || spec->kind != SAM_SPARSIFY_NONE;
+    q->A0_cp = A0->colptr;
+    q->A0_ri = A0->rowind;
+    q->A0_val = A0->val;
+    q->nnzA0 = A0->nnz;
+    q->Ak_cp = Ak_struct->colptr;
+    q->Ak_ri = Ak_struct->rowind;
+    q->nnzA = Ak_struct->nnz;
+    auto bail = [&](sam_status code) {
+        sam_sequence_destroy(q);
+        return code;
+    };
+
+    // structural pattern: S((I + S(A_k))^p), the bound of every sparsified one
+    sam_pattern_spec structural = *spec;
+    structural.kind = SAM_SPARSIFY_NONE;
+    sam_csc skel = *Ak_struct;
+    skel.val = nullptr;
+    if ((st = compute_pattern(ctx, &skel, &structural, q->S_cp, q->S_ri, &q->nnzS, s, &q->level_nnz))) return bail(st);
+    if ((st = sam_plan_create(ctx, &skel, A0, (const int*)q->S_cp.p, (const int*)q->S_ri.p, q->nnzS, &q->plan, stream)))
+        return bail(st);
+    if (!q->plan->combo[q->prec][0].ok)
+        return bail(fail(ctx, SAM_ERR_UNSUPPORTED, "%s", q->plan->combo[q->prec][0].why.c_str()));
+
+    if (q->replan) {
+        int64_t lev_max = 1;
+        for (size_t i = 0; i + 1 < q->level_nnz.size(); ++i) lev_max = std::max(lev_max, q->level_nnz[i]);
+        const int64_t nnzB = (int64_t)q->nnzA + n;
+        const int64_t E = std::max<int64_t>(q->plan->E, 1);
+        size_t need = 0;
+        auto add = [&](size_t b) { need += align256(b); };
+        add((size_t)n * 4);                      // counts
+        add((size_t)(n + 1) * 8);                // off
+        add(samk::scan_temp_bytes(n));           // stemp
+        add(samk::bucket_temp_bytes(n));         // btemp
+        add((size_t)n * 8);                      // D
+        add((size_t)(n + 1) * 4);                // B_cp
+        add((size_t)nnzB * 4);                   // B_ri
+        for (int i = 0; i < 2; ++i) {
+            add((size_t)(n + 1) * 4);
+            add((size_t)lev_max * 4);
+        }
+        for (int k = 0; k < n_src; ++k) {
+            add((size_t)(n + 1) * 4);
+            add((size_t)std::max<int64_t>(q->nnzS, 1) * 4);
+        }
+        add((size_t)n * 4);                      // nI
+        add((size_t)(n + 1) * 8);                // eoff
+        add((size_t)E);                          // posA
+        add((size_t)std::max(q->nnzA0, 1));      // posB
+        add((size_t)n * 4);                      // queue
+        add(64 * 4);                             // bstart
+        add((size_t)n * 8);                      // colbuf
+        add(samk::reduce_temp_bytes(n));
+        add(64);                                 // flags
+        hipError_t he = grow(q->dyn, need + 4096);
+        if (he != hipSuccess) return bail(fail(ctx, SAM_ERR_NOMEM, "sequence buffers (%zu bytes): %s", need,
+                                               hipGetErrorString(he)));
+        Carve cv(q->dyn.p);
+        q->counts = cv.take<int>(n);
+        q->off = cv.take<int64_t>(n + 1);
+        q->stemp = cv.take<char>(samk::scan_temp_bytes(n));
+        q->btemp = cv.take<char>(samk::bucket_temp_bytes(n));
+        q->D = cv.take<double>(n);
+        q->B_cp = cv.take<int>(n + 1);
+        q->B_ri = cv.take<int>((size_t)nnzB);
+        for (int i = 0; i < 2; ++i) {
+            q->L_cp[i] = cv.take<int>(n + 1);
+            q->L_ri[i] = cv.take<int>((size_t)lev_max);
+        }
+        for (int k = 0; k < n_src; ++k) {
+            q->Sk_cp.push_back(cv.take<int>(n + 1));
+            q->Sk_ri.push_back(cv.take<int>((size_t)std::max<int64_t>(q->nnzS, 1)));
+        }
+        sam_plan& d = q->dplan;
+        d.ctx = ctx;
+        d.n = n;
+        d.nnzA = q->nnzA;
+        d.nnzA0 = q->nnzA0;
+        d.nnzS = q->nnzS;
+        d.Ak_cp = q->Ak_cp;
+        d.Ak_ri = q->Ak_ri;
+        d.A0_cp = q->A0_cp;
+        d.A0_ri = q->A0_ri;
+        d.nI = cv.take<int>(n);
+        d.eoff = cv.take<int64_t>(n + 1);
+        d.posA = cv.take<unsigned char>((size_t)E);
+        d.posB = cv.take<unsigned char>((size_t)std::max(q->nnzA0, 1));
+        Combo& cb = d.combo[q->prec][0];
+        cb.queue = cv.take<int>(n);
+        cb.bstart = cv.take<int>(64);
+        cb.tab = menu_table(q->prec, 0, &cb.variants);
+        cb.ok = true;
+        // Grid bounds per bucket: a sparsified column only shrinks, so it
+        // lands in its structural bucket or an earlier one; the count of
+        // bucket b is at most the structural count of buckets >= b.
+        const std::vector<int>& sc = q->plan->combo[q->prec][0].counts;
+        cb.counts.assign(sc.size(), 0);
+        int suffix = 0;
+        for (int b = (int)sc.size() - 1; b >= 0; --b) {
+            suffix += sc[b];
+            cb.counts[b] = suffix;
+        }
+        d.colbuf = cv.take<double>(n);
+        d.rtemp = cv.take<char>(samk::reduce_temp_bytes(n));
+        d.device_counts = true;
+        q->flags = cv.take<int>(16);
+    }
+    if (hipStreamCreateWithFlags(&q->cap, hipStreamNonBlocking) != hipSuccess)
+        return bail(fail(ctx, SAM_ERR_HIP, "stream creation failed"));
+    *out = q;
+    return SAM_OK;
 }
-sam_status sam_sequence_destroy(sam_seq*) { return SAM_OK; }
-sam_status sam_sequence_info(const sam_seq*, int64_t*) { return SAM_ERR_UNSUPPORTED; }
-sam_status sam_sequence_pattern(const sam_seq*, int32_t, const int32_t**, const int32_t**) { return SAM_ERR_UNSUPPORTED; }
-sam_status sam_sequence_run(sam_seq*, const double* const*, void* const*, double*, sam_stream_t) {
-    return SAM_ERR_UNSUPPORTED;
+
+sam_status sam_sequence_destroy(sam_seq* q) {
+    if (!q) return SAM_OK;
+    if (q->ctx && q->ctx->device != SAM_NO_DEVICE) {
+        (void)hipSetDevice(q->ctx->device);
+        (void)hipDeviceSynchronize();
+    }
+    drop_graph(q);
+    if (q->cap) (void)hipStreamDestroy(q->cap);
+    if (q->plan) sam_plan_destroy(q->plan);
+    release(q->S_cp);
+    release(q->S_ri);
+    release(q->dyn);
+    delete q;
+    return SAM_OK;
 }
+
+sam_status sam_sequence_info(const sam_seq* q, int64_t* nnz_bound) {
+    if (!q || !nnz_bound) return SAM_ERR_ARG;
+    *nnz_bound = q->nnzS;
+    return SAM_OK;
+}
+
+sam_status sam_sequence_pattern(sam_seq* q, int32_t k, int32_t* S_colptr, int32_t* S_rowind, int64_t* nnz_S,
+                                sam_stream_t stream) {
+    if (!q || !q->ctx) return SAM_ERR_ARG;
+    sam_ctx* ctx = q->ctx;
+    check_ctx(ctx);
+    if (k < 0 || k >= q->n_src) return fail(ctx, SAM_ERR_ARG, "source index %d outside [0, %d)", k, q->n_src);
+    if (!S_colptr || !nnz_S) return fail(ctx, SAM_ERR_ARG, "NULL argument");
+    sam_status st = need_device(ctx);
+    if (st) return st;
+    hipStream_t s = S(stream);
+    const int* cp = q->replan ? q->Sk_cp[k] : (const int*)q->S_cp.p;
+    const int* ri = q->replan ? q->Sk_ri[k] : (const int*)q->S_ri.p;
+    int last = 0;
+    HIP_TRY(ctx, hipMemcpyAsync(&last, cp + q->n, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, hipStreamSynchronize(s));
+    *nnz_S = last;
+    HIP_TRY(ctx, hipMemcpyAsync(S_colptr, cp, (size_t)(q->n + 1) * 4, hipMemcpyDeviceToDevice, s));
+    if (last > 0) {
+        if (!S_rowind) return fail(ctx, SAM_ERR_ARG, "S_rowind is NULL");
+        HIP_TRY(ctx, hipMemcpyAsync(S_rowind, ri, (size_t)last * 4, hipMemcpyDeviceToDevice, s));
+    }
+    HIP_TRY(ctx, hipStreamSynchronize(s));
+    return SAM_OK;
+}
+
+sam_status sam_sequence_run(sam_seq* q, const double* const* Ak_vals, void* const* M_vals, double* res2,
+                            sam_stream_t stream) {
+    if (!q || !q->ctx) return SAM_ERR_ARG;
+    sam_ctx* ctx = q->ctx;
+    check_ctx(ctx);
+    if (!Ak_vals || !M_vals || !res2) return fail(ctx, SAM_ERR_ARG, "NULL argument");
+    for (int k = 0; k < q->n_src; ++k)
+        if (!Ak_vals[k] || !M_vals[k]) return fail(ctx, SAM_ERR_ARG, "NULL pointer for source %d", k);
+    sam_status st = need_device(ctx);
+    if (st) return st;
+    std::vector<const void*> key;
+    key.reserve(2 * q->n_src + 1);
+    for (int k = 0; k < q->n_src; ++k) {
+        key.push_back(Ak_vals[k]);
+        key.push_back(M_vals[k]);
+    }
+    key.push_back(res2);
+    if (!q->exec || key != q->key) {
+        drop_graph(q);
+        HIP_TRY(ctx, hipStreamBeginCapture(q->cap, hipStreamCaptureModeThreadLocal));
+        st = enqueue_run(q, Ak_vals, M_vals, res2, q->cap);
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(q->cap, &g);
+        if (st) {
+            if (g) (void)hipGraphDestroy(g);
+            return st;
+        }
+        if (e != hipSuccess) return fail(ctx, SAM_ERR_HIP, "graph capture: %s", hipGetErrorString(e));
+        q->graph = g;
+        e = hipGraphInstantiate(&q->exec, q->graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            drop_graph(q);
+            return fail(ctx, SAM_ERR_HIP, "graph instantiate: %s", hipGetErrorString(e));
+        }
+        q->key = key;
+    }
+    HIP_TRY(ctx, hipGraphLaunch(q->exec, S(stream)));
+    return SAM_OK;
+}
+
 sam_status sam_backward(sam_plan*, const double*, const double*, const double*, double, double, sam_precision, double*,
                         double*, double*, double*, sam_stream_t) {
     return SAM_ERR_UNSUPPORTED;
 }
-}
+
+}  // extern "C"

@@ -497,15 +497,20 @@ __device__ inline int bucket_of(int nI, int nJ, const BucketTable& tab) {
 
 // hist is bucket-major: hist[b * nblocks + block]
 __global__ void __launch_bounds__(kBucketThreads)
-k_bucket_hist(int n, const int* S_cp, const int* nI, BucketTable tab, int* hist, int* unfit) {
+k_bucket_hist(int n, const int* S_cp, const int* nI, BucketTable tab, int* hist, int* unfit,
+              unsigned long long* status) {
     __shared__ int h[kMaxBuckets];
     if (threadIdx.x < kMaxBuckets) h[threadIdx.x] = 0;
     __syncthreads();
     const int j = blockIdx.x * kBucketThreads + threadIdx.x;
     if (j < n) {
         int b = bucket_of(nI[j], S_cp[j + 1] - S_cp[j], tab);
-        if (b >= 0) atomicAdd(&h[b], 1);
-        else atomicAdd(unfit, 1);
+        if (b >= 0) {
+            atomicAdd(&h[b], 1);
+        } else {
+            if (unfit) atomicAdd(unfit, 1);
+            if (status) report(status, j, kStUnsupported);
+        }
     }
     __syncthreads();
     if (threadIdx.x < tab.nb) hist[threadIdx.x * gridDim.x + blockIdx.x] = h[threadIdx.x];
@@ -546,7 +551,7 @@ size_t bucket_temp_bytes(int n) {
 }
 
 hipError_t bucket_sort(int n, const int* S_cp, const int* nI, BucketTable tab, int* queue, int* bstart,
-                       int* unfit, void* temp, hipStream_t s) {
+                       int* unfit, unsigned long long* status, void* temp, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     const int nblocks = (int)ceil_div(n, kBucketThreads);
     const int64_t cells = (int64_t)nblocks * tab.nb;
@@ -556,7 +561,7 @@ hipError_t bucket_sort(int n, const int* S_cp, const int* nI, BucketTable tab, i
     int64_t* off = (int64_t*)p;
     p += (((size_t)(nblocks * kMaxBuckets + 1) * sizeof(int64_t)) + 255) / 256 * 256;
     hipLaunchKernelGGL(k_bucket_hist, dim3(nblocks), dim3(kBucketThreads), 0, s, n, S_cp, nI, tab, hist,
-                       unfit);
+                       unfit, status);
     hipError_t e = scan_counts(hist, cells, off, nullptr, nullptr, p, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_bucket_scatter, dim3(nblocks), dim3(kBucketThreads), 0, s, n, S_cp, nI, tab, off,

@@ -310,6 +310,11 @@ class Sequence:
         self.ctx.check(self.ctx.lib.sam_sequence_run(self.h, arr_a, arr_m, _ptr(res2), self.ctx.stream()))
 
     def pattern(self, k: int):
-        cp = ctypes.c_void_p(); ri = ctypes.c_void_p()
-        self.ctx.check(self.ctx.lib.sam_sequence_pattern(self.h, k, ctypes.byref(cp), ctypes.byref(ri)))
-        return cp.value, ri.value
+        """Pattern of source k from the last run (colptr, rowind tensors)."""
+        dev = self.A0.colptr.device
+        cp = torch.empty(self.A0.n + 1, dtype=torch.int32, device=dev)
+        ri = torch.empty(max(self.nnz_bound, 1), dtype=torch.int32, device=dev)
+        nnz = ctypes.c_int64()
+        self.ctx.check(self.ctx.lib.sam_sequence_pattern(self.h, k, _ptr(cp), _ptr(ri), ctypes.byref(nnz),
+                                                         self.ctx.stream()))
+        return cp, ri[:nnz.value]

@@ -1,0 +1,123 @@
+"""GPU tests of the sequence path: every source of a matrix sequence mapped to
+A_0 in one HIP graph (static pattern, per-run replanning, value-dependent
+sparsification), checked against the CPU oracle per map, and graph replays
+checked against the first (eager-captured) run with other GPU work and
+synchronisations in between."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import pde_inputs as P
+from parity_util import TOL, colmax_rel
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2406_17656_amd import Context
+    c = Context(0)
+    yield c
+    torch.cuda.synchronize()
+    c.close()
+
+
+def dev(A):
+    from paper_2406_17656_amd import DeviceCSC
+    return DeviceCSC.from_host(A)
+
+
+def run_seq(ctx, A0, As, prec, replan=False, power=2, kind="none", **kw):
+    dA0 = dev(A0)
+    dAs = [dev(A) for A in As]
+    seq = ctx.sequence(dA0, dAs[0], len(As), prec=prec, power=power, kind=kind, replan_each_run=replan, **kw)
+    Ms = seq.alloc_maps()
+    res2 = torch.zeros(len(As), dtype=torch.float64, device="cuda")
+    seq.run([d.val for d in dAs], Ms, res2)
+    ctx.sync_status()
+    return seq, dAs, Ms, res2
+
+
+def check_maps(ctx, seq, A0, As, Ms, res2, prec, power, kind="none", **kw):
+    for k, Ak in enumerate(As):
+        Sp = O.pattern(Ak, power, kind, **kw)
+        cp, ri = seq.pattern(k)
+        assert np.array_equal(cp.cpu().numpy(), Sp.colptr)
+        assert np.array_equal(ri.cpu().numpy(), Sp.rowind)
+        Mo, rho, _, _ = O.sam_build(Ak, A0, Sp)
+        Mg = Ms[k][:Sp.nnz].cpu().numpy().astype(np.float64)
+        wc, we = colmax_rel(Mg, Mo, Sp.colptr)
+        assert wc <= TOL[prec], (k, wc, we)
+        assert np.isclose(float(res2[k].cpu()), rho.sum(), rtol=1e-9)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("replan", [False, True])
+def test_sequence_structural(ctx, prec, replan):
+    A0, As = P.config2(m=40, nmat=4)
+    seq, dAs, Ms, res2 = run_seq(ctx, A0, As, prec, replan=replan)
+    check_maps(ctx, seq, A0, As, Ms, res2, prec, 2)
+    seq.close()
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_sequence_thresholded(ctx, prec):
+    """Value-dependent patterns: global threshold then level 2, replanned on
+    the device for every source inside the graph."""
+    A0, As = P.config4(m=40, nmat=4)
+    kw = dict(kind="global", thresh=0.1)
+    seq, dAs, Ms, res2 = run_seq(ctx, A0, As, prec, power=2, **kw)
+    check_maps(ctx, seq, A0, As, Ms, res2, prec, 2, **kw)
+    seq.close()
+
+
+def test_sequence_column_tau_3d(ctx):
+    A0, As = P.config3(m=8)
+    kw = dict(kind="column", tau=0.85)
+    seq, dAs, Ms, res2 = run_seq(ctx, A0, As, "f32", power=2, **kw)
+    check_maps(ctx, seq, A0, As, Ms, res2, "f32", 2, **kw)
+    seq.close()
+
+
+@pytest.mark.parametrize("replan", [False, True])
+def test_graph_replays_bitwise(ctx, replan):
+    """Replays of the captured graph, with eager torch work and
+    synchronisations between them, reproduce the first run bit for bit, and
+    equal a fresh one-shot build of each map."""
+    A0, As = P.config2(m=32, nmat=3)
+    seq, dAs, Ms, res2 = run_seq(ctx, A0, As, "f32", replan=replan)
+    first = [m.clone() for m in Ms]
+    r_first = res2.clone()
+    junk = torch.randn(1 << 20, device="cuda")
+    for rep in range(4):
+        for m in Ms:
+            m.fill_(float("nan"))
+        res2.fill_(float("nan"))
+        junk = junk * 1.0001 + 1.0   # unrelated eager work on the same stream
+        torch.cuda.synchronize()
+        seq.run([d.val for d in dAs], Ms, res2)
+        torch.cuda.synchronize()
+        for a, b in zip(first, Ms):
+            assert torch.equal(a, b), rep
+        assert torch.equal(r_first, res2), rep
+    # same numbers as the one-shot path
+    for k, d in enumerate(dAs):
+        cp, ri = seq.pattern(k)
+        M1, _, r1 = ctx.build(d, dev(A0), cp, ri, "f32")
+        assert torch.equal(M1, Ms[k][:ri.numel()])
+        assert torch.equal(r1[0], res2[k])
+    seq.close()
+
+
+def test_pointer_change_recaptures(ctx):
+    A0, As = P.config2(m=24, nmat=3)
+    seq, dAs, Ms, res2 = run_seq(ctx, A0, As, "f64", replan=False)
+    Ms2 = seq.alloc_maps()
+    res2b = torch.zeros_like(res2)
+    seq.run([d.val for d in dAs], Ms2, res2b)
+    torch.cuda.synchronize()
+    for a, b in zip(Ms, Ms2):
+        assert torch.equal(a, b)
+    assert torch.equal(res2, res2b)
+    seq.close()
