@@ -3,14 +3,16 @@
 
 Workload (one step): the 2D variable-coefficient diffusion sequence on a
 512 x 512 grid (n = 262144), target A_0 and sources A_1..A_7 with
-a_k = 1 + 0.5 sin(2 pi x + 0.1 k) cos(2 pi y) + 0.05 N(0,1); for every source
-the whole path runs: level-2 pattern S(A_k^2) (Sections 3-4), the plan of the
-column problems (row sets, gather positions, size buckets), the batched
-least-squares build in FP32 + one FP64 refinement step, and the Frobenius
-residual ||A_k M_k - A_0||_F (Section 2).  Inputs are resident in HBM before
-the timed region.  Prints one JSON line; progress goes to stderr.
+a_k = 1 + 0.5 sin(2 pi x + 0.1 k) cos(2 pi y) + 0.05 N(0,1).  For every
+source the whole path runs inside one HIP graph: the level-2 pattern
+S(A_k^2) (Sections 3-4), the plan of the column problems (row sets, gather
+positions, size buckets), the batched least-squares build in FP32 with one
+FP64 refinement step, and the Frobenius residual ||A_k M_k - A_0||_F
+(Section 2).  Inputs are resident in HBM before the timed region.  Prints
+one JSON line; progress goes to stderr.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+    python bench.py --copy-calibration   # plain copy of known size, for PMC scaling
 """
 import argparse
 import json
@@ -28,12 +30,28 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
+def copy_calibration():
+    """One device-to-device copy of 1 GiB (read 1 GiB, write 1 GiB): the
+    reference the FETCH_SIZE / WRITE_SIZE counters are scaled by."""
+    import torch
+    n = (1 << 30) // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8, "launches": 3}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--grid", type=int, default=512)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -41,6 +59,9 @@ def main():
               "would shard across GPUs by contiguous column ranges with one halo exchange, which "
               "this build does not run.", file=sys.stderr)
         sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration()
+        return
 
     import numpy as np
     import torch
@@ -51,74 +72,102 @@ def main():
     m = args.grid
     A0h, Ash = P.config2(m=m, nmat=8)
     n = A0h.n
-    log(f"inputs: n={n}, {len(Ash)} sources, nnz(A)={A0h.nnz}")
+    nmaps = len(Ash)
+    cols = n * nmaps
+    log(f"inputs: n={n}, {nmaps} sources, nnz(A)={A0h.nnz}")
     ctx = Context(0)
     dA0 = DeviceCSC.from_host(A0h)
     dAk = [DeviceCSC.from_host(A) for A in Ash]
+    vals = [d.val for d in dAk]
     torch.cuda.synchronize()
     a02 = float((A0h.val ** 2).sum())
 
-    def run_sequence(prec, power, events=None, keep=None):
-        res = []
-        for k, A in enumerate(dAk):
-            Scp, Sri = ctx.pattern(A, power)
-            plan = ctx.plan(A, dA0, Scp, Sri)
-            if events is not None:
-                e0 = torch.cuda.Event(enable_timing=True)
-                e1 = torch.cuda.Event(enable_timing=True)
-                e0.record()
-            M, _, r2 = plan.build(A.val, dA0.val, prec)
-            if events is not None:
-                e1.record()
-                events.append((e0, e1))
-            res.append(r2)
-            if keep is not None and k == 0:
-                keep.update(plan.cost(prec))
-                keep["info"] = plan.info()
-            plan.close()
-        return res
-
-    def timed(prec, power, steps, warmup):
+    def time_sequence(prec, power, replan, steps, warmup):
+        seq = ctx.sequence(dA0, dAk[0], nmaps, prec=prec, power=power, replan_each_run=replan)
+        Ms = seq.alloc_maps()
+        res2 = torch.zeros(nmaps, dtype=torch.float64, device="cuda")
         for _ in range(warmup):
-            run_sequence(prec, power)
+            seq.run(vals, Ms, res2)
+        ctx.sync_status()
         torch.cuda.synchronize()
-        events = []
-        cost = {}
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
         t0 = time.perf_counter()
+        e0.record()
         for _ in range(steps):
-            res = run_sequence(prec, power, events, cost)
+            seq.run(vals, Ms, res2)
+        e1.record()
         torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        build_ms = float(np.mean([a.elapsed_time(b) for a, b in events]))
-        r2 = [float(r.item()) for r in res]
-        return dt / steps, build_ms, cost, r2
+        wall = (time.perf_counter() - t0) / steps
+        ev = e0.elapsed_time(e1) / steps * 1e-3
+        ctx.sync_status()
+        r2 = res2.cpu().numpy().copy()
+        seq.close()
+        return wall, ev, r2
 
-    log("timing FP32+refine, S(A_k^2)")
-    ms_step, build_ms, cost, r2_f32 = timed("f32", 2, args.steps, args.warmup)
-    cols = n * len(dAk)
-    value = cols / ms_step
-    log(f"step {ms_step * 1e3:.2f} ms, numeric build {build_ms:.3f} ms/map")
+    log("timing: replanned sequence, FP32+refine, S(A_k^2) (the step)")
+    wall, ev, r2_f32 = time_sequence("f32", 2, True, args.steps, args.warmup)
+    value = cols / wall
+    log(f"step {wall * 1e3:.3f} ms (events {ev * 1e3:.3f} ms), {value / 1e6:.1f} M columns/s")
 
-    # roofline of the dominant kernel (the numeric build of one map)
+    # dominant kernel: the numeric build of one map, timed with events on the
+    # stream it is launched on, same kernel variant and grid as in the graph
+    Scp, Sri = ctx.pattern(dAk[0], 2)
+    plan = ctx.plan(dAk[0], dA0, Scp, Sri)
+    cost = plan.cost("f32")
+    info = plan.info()
+
+    def time_build(prec, reps=20):
+        M = torch.empty(max(Sri.numel(), 1), dtype=torch.float32 if prec == "f32" else torch.float64,
+                        device="cuda")
+        r = torch.empty(1, dtype=torch.float64, device="cuda")
+        for _ in range(3):
+            plan.build(dAk[0].val, dA0.val, prec, M=M, res2=r)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            plan.build(dAk[0].val, dA0.val, prec, M=M, res2=r)
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    build_ms = time_build("f32")
     flops = cost["flops32"] + cost["flops64"]
     achieved_tf = flops / (build_ms * 1e-3) / 1e12
     achieved_gbs = cost["bytes"] / (build_ms * 1e-3) / 1e9
+    log(f"numeric build {build_ms * 1e3:.1f} us/map, {achieved_tf:.2f} TFLOP/s, {achieved_gbs:.0f} GB/s")
 
-    variants = {}
-    log("timing FP64, S(A_k^2)")
-    ms64, b64, cost64, r2_f64 = timed("f64", 2, max(2, args.steps // 2), 1)
-    variants["f64_level2"] = {"cols_per_s": cols / ms64, "numeric_ms_per_map": b64}
-    for prec in ("f32", "f64"):
-        log(f"timing {prec}, S(A_k)")
-        ms1, b1, c1, _ = timed(prec, 1, max(2, args.steps // 2), 1)
-        variants[f"{prec}_level1"] = {
-            "cols_per_s": cols / ms1, "numeric_ms_per_map": b1,
-            "numeric_GBs": c1["bytes"] / (b1 * 1e-3) / 1e9,
-            "numeric_hbm_frac": c1["bytes"] / (b1 * 1e-3) / 1e9 / PEAK["hbm_GBs"]}
-    variants["f32_level2"] = {"cols_per_s": value, "numeric_ms_per_map": build_ms,
-                              "numeric_cols_per_s": n / (build_ms * 1e-3)}
-    variants["f64_level2"]["numeric_cols_per_s"] = n / (b64 * 1e-3)
-    eq = max(abs(a - b) / b for a, b in zip(r2_f32, r2_f64))
+    variants = {"f32_level2_replanned": {"cols_per_s": value, "ms_per_step": wall * 1e3},
+                "f32_level2_numeric_build_us": build_ms * 1e3}
+    eq = None
+    if not args.no_variants:
+        b64 = time_build("f64")
+        variants["f64_level2_numeric_build_us"] = b64 * 1e3
+        plan.close()
+        for prec in ("f32", "f64"):
+            for power in (1, 2):
+                log(f"timing: static sequence {prec} level {power}")
+                w, e, r2 = time_sequence(prec, power, False, max(5, args.steps // 2), 2)
+                variants[f"{prec}_level{power}_static"] = {"cols_per_s": cols / w, "ms_per_step": w * 1e3}
+                if prec == "f64" and power == 2:
+                    r2_f64 = r2
+        w, e, _ = time_sequence("f64", 2, True, max(5, args.steps // 2), 2)
+        variants["f64_level2_replanned"] = {"cols_per_s": cols / w, "ms_per_step": w * 1e3}
+        eq = float(max(abs(a - b) / b for a, b in zip(r2_f32, r2_f64)))
+        # the one-shot API (pattern, plan with host syncs and allocation, build) per map
+        log("timing: one-shot API per map")
+        t0 = time.perf_counter()
+        for k, A in enumerate(dAk):
+            cp, ri = ctx.pattern(A, 2)
+            pl = ctx.plan(A, dA0, cp, ri)
+            pl.build(A.val, dA0.val, "f32")
+            pl.close()
+        torch.cuda.synchronize()
+        variants["f32_level2_oneshot_api"] = {"cols_per_s": cols / (time.perf_counter() - t0)}
+    else:
+        plan.close()
     rel_res = [float(np.sqrt(r / a02)) for r in r2_f32]
 
     cpu = None
@@ -137,30 +186,30 @@ def main():
                 break
         tc = time.perf_counter() - t0
         cpu = {"value": done / tc, "unit": "columns/s", "cores": nthreads, "kind": "oracle",
-               "sample": f"the full workload ({len(Ash)} maps, pattern + FP64 build) repeated "
-                         f"{done // cols}x, {tc:.1f} s"}
+               "sample": f"the full workload ({nmaps} maps: level-2 pattern + FP64 Householder build) "
+                         f"repeated {done // cols}x, {tc:.1f} s"}
 
     out = {
-        "metric": "SAM columns/sec (FP32+refine, level-2 pattern, whole path incl. pattern and plan)",
+        "metric": "SAM columns/sec (whole path per map: level-2 pattern, plan, FP32+FP64-refine build, residual)",
         "value": value,
         "unit": "columns/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_step * 1e3,
+        "ms_per_step": wall * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32+f64refine",
         "data": "synthetic",
-        "config": {"workload": f"2D var-coeff diffusion {m}x{m} (n={n}), 7 sources mapped to A_0, "
-                               "pattern S(A_k^2), FP32 QR + FP64 refinement",
-                   "n": n, "maps": len(dAk), "pattern": "S(A_k^2)",
-                   "max_rows": cost["info"]["max_rows"], "max_cols": cost["info"]["max_cols"]},
+        "config": {"workload": f"2D var-coeff diffusion {m}x{m} (n={n}), {nmaps} sources mapped to A_0, "
+                               "pattern S(A_k^2) recomputed per source, FP32 QR + FP64 refinement, one HIP graph",
+                   "n": n, "maps": nmaps, "pattern": "S(A_k^2)",
+                   "max_rows": info["max_rows"], "max_cols": info["max_cols"]},
         "roofline": {"bound": "alu", "achieved": achieved_tf, "peak": PEAK["fp32_TFs"], "unit": "TFLOP/s",
                      "frac": achieved_tf / PEAK["fp32_TFs"], "traffic": None,
-                     "kernel": "numeric build of one map (k_numeric + fixed-order residual sum)",
-                     "kernel_ms": build_ms, "algorithmic_flops": flops,
+                     "kernel": "k_numeric<float,4,7,13> (numeric build of one map, + fixed-order residual sum)",
+                     "kernel_us": build_ms * 1e3, "algorithmic_flops": flops,
                      "algorithmic_bytes": cost["bytes"], "hbm_GBs": achieved_gbs,
                      "hbm_frac": achieved_gbs / PEAK["hbm_GBs"]},
         "cpu_baseline": cpu,

@@ -433,6 +433,8 @@ sam_status sam_plan_create(sam_ctx* ctx, const sam_csc* Ak, const sam_csc* A0, c
     if ((st = check_csc_args(ctx, Ak, "Ak", false))) return st;
     if ((st = check_csc_args(ctx, A0, "A0", false))) return st;
     if (Ak->n != A0->n) return fail(ctx, SAM_ERR_SHAPE, "Ak is %d x %d but A0 is %d x %d", Ak->n, Ak->n, A0->n, A0->n);
+    if (Ak->n > 0 && (Ak->nnz == 0 || A0->nnz == 0))
+        return fail(ctx, SAM_ERR_ARG, "Ak and A0 must have stored entries (a nonsingular source has at least n)");
     if (nnz_S < 0) return fail(ctx, SAM_ERR_ARG, "nnz_S < 0");
     if (nnz_S > INT_MAX) return fail(ctx, SAM_ERR_OVERFLOW, "nnz_S = %lld does not fit in int32", (long long)nnz_S);
     if (!S_colptr || (nnz_S > 0 && !S_rowind)) return fail(ctx, SAM_ERR_ARG, "pattern array is NULL");

@@ -311,6 +311,23 @@ __device__ inline int row_excl_scan_i(int v) {
 
 enum { kModeCount = 0, kModeFill = 1, kModePositions = 2 };
 
+constexpr int kListRounds = 2;   // lists per lane held in registers (32 per column)
+constexpr int kListLen = 8;      // entries per list held in registers
+
+__device__ inline int row_max_i(int v) {
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, true));
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, true));
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x141, 0xF, 0xF, true));
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x140, 0xF, 0xF, true));
+    return v;
+}
+
+// Rank of row d (relative to the chunk base) inside the chunk's bitmap.
+__device__ inline int chunk_rank(const unsigned* bm, const int* wpre, int d) {
+    const int w = d >> 5;
+    return wpre[w] + __popc(bm[w] & ((1u << (d & 31)) - 1u));
+}
+
 template <int MODE>
 __global__ void __launch_bounds__(kSymThreads)
 k_union(int n, const int* P_cp, const int* P_ri, const int* Q_cp, const int* Q_ri, int* counts,
@@ -325,15 +342,50 @@ k_union(int n, const int* P_cp, const int* P_ri, const int* Q_cp, const int* Q_r
     const int stride = gridDim.x * kGroupsPerBlock;
     for (int j = blockIdx.x * kGroupsPerBlock + grp; j < n; j += stride) {
         const int pa = P_cp[j], pb = P_cp[j + 1];
-        // first candidate row: lists are sorted, so their heads bound it
-        int lo = INT_MAX;
-        for (int t = pa + g; t < pb; t += kGS) {
-            const int l = P_ri[t];
-            if (l < 0 || l >= n) {
-                if (bad) atomicMin(bad, j);
-                continue;
+        // Lists t = pa + g + 16 u of this lane, first kListLen rows of each in
+        // registers (all loads independent); `big` marks columns that need the
+        // memory loops (more than 32 lists, or a list longer than kListLen).
+        int qa[kListRounds], len[kListRounds], lofs[kListRounds];
+        int rows[kListRounds][kListLen];
+        int big = (pb - pa > kGS * kListRounds) ? 1 : 0;
+        int lo = INT_MAX, carry = 0;
+#pragma unroll
+        for (int u = 0; u < kListRounds; ++u) {
+            const int t = pa + g + u * kGS;
+            int l = -1;
+            if (t < pb) {
+                l = P_ri[t];
+                if (l < 0 || l >= n) {
+                    if (bad) atomicMin(bad, j);
+                    l = -1;
+                }
             }
-            if (Q_cp[l + 1] > Q_cp[l]) lo = min(lo, Q_ri[Q_cp[l]]);
+            qa[u] = l >= 0 ? Q_cp[l] : 0;
+            len[u] = l >= 0 ? Q_cp[l + 1] - qa[u] : 0;
+            big |= len[u] > kListLen ? 1 : 0;
+            // flat offset of this list among the column's gathered entries
+            lofs[u] = carry + row_excl_scan_i(len[u]);
+            carry += row_sum_i(len[u]);
+            if (len[u] > 0) {
+#pragma unroll
+                for (int e = 0; e < kListLen; ++e) {
+                    const bool ok = e < len[u];
+                    const int r = Q_ri[qa[u] + (ok ? e : 0)];  // clamped: always in bounds
+                    rows[u][e] = ok ? r : INT_MAX;
+                }
+            } else {
+#pragma unroll
+                for (int e = 0; e < kListLen; ++e) rows[u][e] = INT_MAX;
+            }
+            lo = min(lo, rows[u][0]);
+        }
+        big = row_max_i(big);
+        if (big) {  // heads of every list, from memory
+            lo = INT_MAX;
+            for (int t = pa + g; t < pb; t += kGS) {
+                const int l = P_ri[t];
+                if (l >= 0 && l < n && Q_cp[l + 1] > Q_cp[l]) lo = min(lo, Q_ri[Q_cp[l]]);
+            }
         }
         lo = row_min_i(lo);
         if (MODE == kModePositions)
@@ -345,16 +397,26 @@ k_union(int n, const int* P_cp, const int* P_ri, const int* Q_cp, const int* Q_r
             for (int w = 0; w < 4; ++w) bm[g * 4 + w] = 0u;
             wave_sync();
             int next = INT_MAX;
-            for (int t = pa + g; t < pb; t += kGS) {
-                const int l = P_ri[t];
-                if (l < 0 || l >= n) continue;
-                for (int f = Q_cp[l]; f < Q_cp[l + 1]; ++f) {
-                    const int d = Q_ri[f] - base;
-                    if (d >= kChunk) {
-                        next = min(next, d + base);
-                        break;
+            if (!big) {
+#pragma unroll
+                for (int u = 0; u < kListRounds; ++u)
+#pragma unroll
+                    for (int e = 0; e < kListLen; ++e) {
+                        const int r = rows[u][e];
+                        const int d = r - base;  // r = INT_MAX for empty slots: d >= kChunk
+                        if (d >= 0 && d < kChunk) atomicOr(&bm[d >> 5], 1u << (d & 31));
+                        if (d >= kChunk) next = min(next, r);
                     }
-                    if (d >= 0) atomicOr(&bm[d >> 5], 1u << (d & 31));
+            } else {
+                for (int t = pa + g; t < pb; t += kGS) {
+                    const int l = P_ri[t];
+                    if (l < 0 || l >= n) continue;
+                    for (int f = Q_cp[l]; f < Q_cp[l + 1]; ++f) {
+                        const int r = Q_ri[f];
+                        const int d = r - base;
+                        if (d >= 0 && d < kChunk) atomicOr(&bm[d >> 5], 1u << (d & 31));
+                        if (d >= kChunk) next = min(next, r);
+                    }
                 }
             }
             wave_sync();
@@ -386,46 +448,43 @@ k_union(int n, const int* P_cp, const int* P_ri, const int* Q_cp, const int* Q_r
             }
             if (MODE == kModePositions) {
                 // ranks of the gathered A_k entries, in the order of the lists
-                int carry = 0;
-                for (int t0 = pa; t0 < pb; t0 += kGS) {
-                    const int t = t0 + g;
-                    int l = -1, len = 0;
-                    if (t < pb) {
-                        l = P_ri[t];
-                        if (l >= 0 && l < n) len = Q_cp[l + 1] - Q_cp[l];
-                    }
-                    const int off = carry + row_excl_scan_i(len);
-                    if (len > 0) {
-                        const int qa = Q_cp[l];
-                        for (int f = 0; f < len; ++f) {
-                            const int d = Q_ri[qa + f] - base;
-                            if (d >= kChunk) break;
-                            if (d >= 0) {
-                                const int w = d >> 5;
-                                const int rank = wpre[w] + __popc(bm[w] & ((1u << (d & 31)) - 1u));
-                                posA[eoff[j] + off + f] = (unsigned char)min(rank, 255);
-                            }
+                unsigned char* pj = posA + eoff[j];
+                if (!big) {
+#pragma unroll
+                    for (int u = 0; u < kListRounds; ++u)
+#pragma unroll
+                        for (int e = 0; e < kListLen; ++e) {
+                            const int d = rows[u][e] - base;
+                            if (d >= 0 && d < kChunk) pj[lofs[u] + e] = (unsigned char)min(chunk_rank(bm, wpre, d), 255);
                         }
+                } else {
+                    int cy = 0;
+                    for (int t0 = pa; t0 < pb; t0 += kGS) {
+                        const int t = t0 + g;
+                        int l = -1, ln = 0;
+                        if (t < pb) {
+                            l = P_ri[t];
+                            if (l >= 0 && l < n) ln = Q_cp[l + 1] - Q_cp[l];
+                        }
+                        const int off = cy + row_excl_scan_i(ln);
+                        for (int f = 0; f < ln; ++f) {
+                            const int d = Q_ri[Q_cp[l] + f] - base;
+                            if (d >= 0 && d < kChunk) pj[off + f] = (unsigned char)min(chunk_rank(bm, wpre, d), 255);
+                        }
+                        cy += row_sum_i(ln);
                     }
-                    carry += row_sum_i(len);
                 }
                 for (int e = A0_cp[j] + g; e < A0_cp[j + 1]; e += kGS) {
                     const int d = A0_ri[e] - base;
-                    if (d >= 0 && d < kChunk && ((bm[d >> 5] >> (d & 31)) & 1u)) {
-                        const int w = d >> 5;
-                        const int rank = wpre[w] + __popc(bm[w] & ((1u << (d & 31)) - 1u));
-                        posB[e] = (unsigned char)min(rank, 254);
-                    }
+                    if (d >= 0 && d < kChunk && ((bm[d >> 5] >> (d & 31)) & 1u))
+                        posB[e] = (unsigned char)min(chunk_rank(bm, wpre, d), 254);
                 }
             }
             running += tot;
             base = row_min_i(next);
             wave_sync();
         }
-        if (g == 0) {
-            if (MODE == kModeCount) counts[j] = running;
-            if (MODE == kModePositions) counts[j] = running;  // |I_j|
-        }
+        if (g == 0 && MODE != kModeFill) counts[j] = running;  // |union| (= |I_j| for positions)
     }
 }
 

@@ -103,3 +103,11 @@ def test_build_and_residual_argument_checks(hctx):
     # apply
     assert lib.sam_apply_prepare(h, 4, 1, 1, 2 ** 31, 1, 1, 1, None) == 4
     assert lib.sam_apply(h, 4, 1, 1, 1, 1, 9, 1, 1, None) == 1
+
+
+def test_empty_matrices_rejected(hctx):
+    lib, h = hctx
+    pl = ctypes.c_void_p()
+    a, b = csc(n=4, nnz=0), csc(n=4)
+    assert lib.sam_plan_create(h, ctypes.byref(a), ctypes.byref(b), 1, 1, 4, ctypes.byref(pl), None) == 1
+    assert "stored entries" in lib.sam_last_error(h).decode()

@@ -200,3 +200,32 @@ def test_full_size_config2_sampled(ctx, prec, power):
     cols = sample_columns(Ak.n, Sp.colptr, k=3000, seed=power)
     _, _, wc, we = check_build(ctx, A0, Ak, power, prec, cols=cols)
     print(f"cfg2 full p={power} {prec}: colmax {wc:.2e} entrywise {we:.2e}")
+
+
+def random_wide(n=240, per_col=11, seed=12):
+    """Unstructured sparse matrix with long columns: level-2 columns have
+    more than 32 lists and lists longer than 8 (the kernels' memory path)."""
+    rng = np.random.default_rng(seed)
+    d = np.zeros((n, n))
+    for j in range(n):
+        rows = rng.choice(n, size=per_col, replace=False)
+        d[rows, j] = rng.uniform(-1, 1, per_col)
+    d += np.diag(np.abs(d).sum(axis=0) + 1.0)
+    return P.dense_to_csc(d)
+
+
+@pytest.mark.parametrize("power", [1, 2, 3])
+def test_pattern_long_lists(ctx, power):
+    A = random_wide()
+    want = O.pattern(A, power)
+    cp, ri = gpu_pattern(ctx, A, power)
+    assert np.array_equal(cp, want.colptr) and np.array_equal(ri, want.rowind)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_build_long_lists(ctx, prec):
+    """|J_j| = 12, |I_j| up to ~120: the widest buckets and the memory path
+    of the gather for columns longer than the register cache."""
+    A0 = random_wide(seed=13)
+    Ak = A0.with_values(A0.val * (1 + 0.05 * np.random.default_rng(1).standard_normal(A0.nnz)))
+    check_build(ctx, A0, Ak, 1, prec)
