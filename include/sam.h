@@ -298,14 +298,18 @@ sam_status sam_build_weighted(sam_plan* plan, const double* Ak_val, const double
 
 /* Adjoint of L = dL * ||A_k M - A_0||_F^2 for the soft-weighted map M: the
  * QR of each stacked block is recomputed (nothing is stored by the forward
- * pass), lambda = (A^T A + P)^{-1} 2 A^T r with r = A m - b, and
+ * pass), lambda = (A^T A + P)^{-1} 2 A^T r with r = A m - b (FP32 mode: two
+ * FP64-residual refinement steps on lambda), and
  *   gAk  (nnz(A_k), overwritten): sum over columns j of
- *        2 r m^T - r lambda^T - (A lambda) m^T at the stored entries,
- *   gA0  (nnz(A_0), overwritten): -2 r + A lambda on I_j, 2 A_0(i,j) outside,
- *   gw   (nnz_S, optional):       mu lambda_l m_l / w_l^2,
- *   loss (optional device scalar): the value of L.
- * The A_k gradient is summed per entry in a fixed order (no atomics).
- * Allocates nothing (uses the plan's gradient staging buffer). */
+ *        dL (2 r m^T - r lambda^T - (A lambda) m^T) at the stored entries,
+ *   gA0  (nnz(A_0), overwritten): dL (-2 r + A lambda) on I_j, dL 2 a_0(i,j)
+ *        outside I_j,
+ *   gw   (nnz_S, optional):       dL mu lambda_l m_l / w_l^2,
+ *   loss (optional device scalar): ||A_k M - A_0||_F^2 (not scaled by dL).
+ * The A_k gradient is summed per entry over the columns in ascending order
+ * from a staging buffer (no atomics: bitwise reproducible).  The staging
+ * buffer and the row view of S are allocated on the first call on a plan
+ * (that call synchronises); later calls allocate nothing. */
 sam_status sam_backward(sam_plan* plan, const double* Ak_val, const double* A0_val,
                         const double* w, double mu, double dL, sam_precision prec,
                         double* gAk, double* gA0, double* gw, double* loss,

@@ -91,6 +91,12 @@ struct NumericArgs {
     // soft weights (nullptr for the plain map)
     const double* w;
     double mu;
+    // adjoint outputs (backward launches only)
+    double dL;
+    double* contrib;      // per gathered entry, at eoff[j] + offset in the block
+    int64_t* segoff;      // per S entry: where its column's contributions start
+    double* gA0;          // nnz(A_0)
+    double* gw;           // nnz(S) or nullptr
 };
 
 // One kernel variant of the menu: solves every column of one bucket whose
@@ -102,6 +108,7 @@ struct NumericVariant {
     int NC;          // max columns
     int weighted;    // 1: stacked penalty rows
     hipError_t (*launch)(const NumericArgs&, int grid, hipStream_t);
+    hipError_t (*launch_backward)(const NumericArgs&, int grid, hipStream_t);  // weighted only
     int max_rows() const { return G * R; }
     int per_wave() const { return 64 / G; }
 };
@@ -133,24 +140,10 @@ hipError_t spmv_rows(int n, const int* rowptr, const int* colind, const int* per
                      const void* val, int val_f32, const double* x, double* y, hipStream_t s);
 
 // ---------------------------------------------------------------- adjoint
-struct BackwardArgs {
-    NumericArgs fw;        // forward arguments (w, mu set)
-    double dL;
-    double* contrib;       // staging: per gathered entry (eoff order)
-    double* gA0;           // nnz(A_0)
-    double* gw;            // nnz_S or nullptr
-};
-struct BackwardVariant {
-    int G, R, NC;
-    hipError_t (*launch)(const BackwardArgs&, int grid, hipStream_t);
-    int max_rows() const { return G * R; }
-    int per_wave() const { return 64 / G; }
-};
-const BackwardVariant* backward_menu(int* count);
-// gAk[e] = sum over the S entries (l, j) with l = column of e of the staged
-// contribution of column j to entry e, in ascending j (uses the row view of S).
-hipError_t backward_scatter(int n, const int* Ak_cp, const int* ST_rowptr, const int* ST_colind,
-                            const int* ST_perm, const int* S_cp, const int64_t* eoff,
-                            const double* contrib, double* gAk, hipStream_t s);
+// gAk[f] = sum over the S entries (l, j) with l the column of entry f, in
+// ascending j (row view of S: ST_rowptr / ST_perm), of the staged
+// contribution of column j to entry f.
+hipError_t backward_scatter(int n, const int* Ak_cp, const int* ST_rowptr, const int* ST_perm,
+                            const int64_t* segoff, const double* contrib, double* gAk, hipStream_t s);
 
 }  // namespace samk

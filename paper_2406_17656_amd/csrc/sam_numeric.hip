@@ -66,9 +66,14 @@ __device__ inline double root<double>(double x) { return sqrt(x); }
 // |I_j| (+ |J_j| when weighted) <= G*R rows and |J_j| <= NC columns.  The
 // code is straight-line in NC and R (no runtime column guards): columns past
 // |J_j| are zero and pass through the Householder steps as identities.
-template <typename TQ, int G, int R, int NC, int TC, int LPL, bool WEIGHTED>
+// MODE 0: plain least squares; 1: soft-weighted (stacked penalty rows);
+// 2: adjoint of the soft-weighted map (forward recomputed, then lambda and
+// the gradient contributions).
+template <typename TQ, int G, int R, int NC, int TC, int LPL, int MODE>
 __global__ void __launch_bounds__(64)
 k_numeric(NumericArgs a) {
+    constexpr bool WEIGHTED = MODE >= 1;
+    constexpr bool BACKWARD = MODE == 2;
     constexpr int P = 64 / G;        // problems per wave
     constexpr int RM = G * R;        // rows per problem (padded)
     constexpr int RX = RM + G;       // plus one scratch row per lane
@@ -79,6 +84,7 @@ k_numeric(NumericArgs a) {
     __shared__ int cst[P][NC + 1];        // entry offset of column c in the block
     __shared__ int vbs[P][NC];            // start of A_k(:, J_j[c]) in the value array
     __shared__ int cln[P][NC];            // nnz of A_k(:, J_j[c])
+    __shared__ double alsh[BACKWARD ? P * RX : 1];  // A lambda (adjoint)
 
     const int lane = threadIdx.x;
     const int g = lane % G;
@@ -316,53 +322,130 @@ k_numeric(NumericArgs a) {
         }
 
         double* rsh = tile + q * RX;  // residual vector (the tile is free now)
+
+        // Sparse FP64 passes over the gathered entries of the block.  Rows are
+        // distinct inside one column, so the lanes of a group never update
+        // one LDS slot in the same instruction, and the wave's LDS operations
+        // complete in program order from column to column.  The values are
+        // reloaded (L2-resident) with all loads issued first.
+        auto load_entries = [&]() {
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                const int len = cln[q][c];
+                const int e0 = cst[q][c];
+                const int vb = vbs[q][c];
+#pragma unroll
+                for (int u = 0; u < LPL; ++u) {
+                    const int e = g + u * G;
+                    const bool ok = e < len;
+                    const int ec = ok ? e : 0;
+                    const int p = a.posA[eo + e0 + ec];
+                    const double v = a.Ak_v[vb + ec];
+                    pp[c][u] = ok ? p : trash;
+                    pv[c][u] = ok ? v : 0.0;
+                }
+            }
+        };
+        // vec += sgn * A x
+        auto scatter = [&](double* vec, const double (&x)[NC], double sgn) {
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                const double xc = sgn * x[c];
+#pragma unroll
+                for (int u = 0; u < LPL; ++u) vec[pp[c][u]] += pv[c][u] * xc;
+                const int len = cln[q][c];
+                if (len > LPL * G) {  // long columns
+                    const int e0 = cst[q][c], vb = vbs[q][c];
+                    for (int e = g + LPL * G; e < len; e += G) vec[a.posA[eo + e0 + e]] += a.Ak_v[vb + e] * xc;
+                }
+            }
+            wave_sync();
+        };
+        // out = A^T vec (summed over the group)
+        auto gather = [&](const double* vec, double (&out)[NC]) {
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                double sacc = 0.0;
+#pragma unroll
+                for (int u = 0; u < LPL; ++u) sacc += pv[c][u] * vec[pp[c][u]];
+                const int len = cln[q][c];
+                if (len > LPL * G) {
+                    const int e0 = cst[q][c], vb = vbs[q][c];
+                    for (int e = g + LPL * G; e < len; e += G) sacc += a.Ak_v[vb + e] * vec[a.posA[eo + e0 + e]];
+                }
+                out[c] = sacc;
+            }
+#pragma unroll
+            for (int c = 0; c < NC; ++c) out[c] = group_sum<G>(out[c]);
+        };
+        // x = R^{-1} R^{-T} rhs in the QR's precision (R^T R = A^T A + P);
+        // y = R^{-T} rhs is returned too
+        auto solve_normal = [&](const double (&rhs)[NC], double (&x)[NC], double (&y)[NC]) {
+            TQ ydist[R];
+            TQ yrep[NC];
+#pragma unroll
+            for (int t = 0; t < R; ++t) ydist[t] = 0;
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                TQ part = 0;
+#pragma unroll
+                for (int t = 0; t < R; ++t) {
+                    const int row = t * G + g;
+                    if (t * G < c) part += (row < c) ? A[t][c] * ydist[t] : (TQ)0;
+                }
+                part = group_sum<G>(part);
+                TQ yc = ((TQ)rhs[c] - part) * rinv[c];
+                yc = (c < nJ) ? yc : (TQ)0;
+                yrep[c] = yc;
+                if (g == c % G) ydist[c / G] = yc;
+            }
+            TQ dl[NC];
+#pragma unroll
+            for (int k = NC - 1; k >= 0; --k) {
+                const int tk = k / G, gk = k % G;
+                TQ sacc = yrep[k];
+#pragma unroll
+                for (int c = k + 1; c < NC; ++c) sacc -= A[tk][c] * dl[c];
+                const TQ dk = group_bcast<G>(sacc * rinv[k], g, gk);
+                dl[k] = (k < nJ) ? dk : (TQ)0;
+            }
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                x[c] = (double)dl[c];
+                y[c] = (double)yrep[c];
+            }
+        };
+        auto reset = [&](double* vec, bool from_b) {
+#pragma unroll
+            for (int t = 0; t < R; ++t) vec[t * G + g] = from_b ? bsh[q * RX + t * G + g] : 0.0;
+            vec[trash] = 0.0;
+        };
+
+        // penalty p_c = mu (1/w_c - 1) on the map's entries
+        double pen[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) pen[c] = 0.0;
+        if constexpr (WEIGHTED) {
+#pragma unroll
+            for (int c = 0; c < NC; ++c)
+                if (valid && c < nJ) pen[c] = a.mu * (1.0 / a.w[scol + c] - 1.0);
+        }
+
         double mfin[NC];
         double rr;
         if constexpr (REFINE) {
-            // One FP64 pass r = b - A m over the gathered entries into rsh.
-            // Rows are distinct inside one column, so the lanes of a group
-            // never update one slot in the same instruction, and the wave's
-            // LDS operations complete in program order from column to column.
-            // The values are reloaded (L2-resident), all loads issued first.
+            // refinement on the normal equations (A^T A + P) m = A^T b with the
+            // residual in FP64:  r = b - A m,  m += R^{-1} R^{-T} (A^T r - P m)
             double m64[NC];
 #pragma unroll
             for (int c = 0; c < NC; ++c) m64[c] = (double)m[c];
             double rr_it = 0.0;
 #pragma unroll
             for (int it = 0; it < (WEIGHTED ? 2 : 1); ++it) {
-#pragma unroll
-                for (int t = 0; t < R; ++t) rsh[t * G + g] = bsh[q * RX + t * G + g];
-                rsh[trash] = 0.0;
-#pragma unroll
-                for (int c = 0; c < NC; ++c) {
-                    const int len = cln[q][c];
-                    const int e0 = cst[q][c];
-                    const int vb = vbs[q][c];
-#pragma unroll
-                    for (int u = 0; u < LPL; ++u) {
-                        const int e = g + u * G;
-                        const bool ok = e < len;
-                        const int ec = ok ? e : 0;
-                        const int p = a.posA[eo + e0 + ec];
-                        const double v = a.Ak_v[vb + ec];
-                        pp[c][u] = ok ? p : trash;
-                        pv[c][u] = ok ? v : 0.0;
-                    }
-                }
+                reset(rsh, true);
+                load_entries();
                 wave_sync();
-#pragma unroll
-                for (int c = 0; c < NC; ++c) {
-                    const double mc = m64[c];
-#pragma unroll
-                    for (int u = 0; u < LPL; ++u) rsh[pp[c][u]] -= pv[c][u] * mc;
-                    const int len = cln[q][c];
-                    if (len > LPL * G) {  // long columns
-                        const int e0 = cst[q][c], vb = vbs[q][c];
-                        for (int e = g + LPL * G; e < len; e += G) rsh[a.posA[eo + e0 + e]] -= a.Ak_v[vb + e] * mc;
-                    }
-                }
-                wave_sync();
-                // ||r||^2 over the rows of I_j and gA = A^T r (FP64)
+                scatter(rsh, m64, -1.0);
                 double r2 = 0.0;
 #pragma unroll
                 for (int t = 0; t < R; ++t) {
@@ -370,75 +453,20 @@ k_numeric(NumericArgs a) {
                     r2 += (t * G + g < nIj) ? x * x : 0.0;
                 }
                 rr_it = group_sum<G>(r2);
-                double gA[NC], gc[NC];
+                double gA[NC], gc[NC], dl[NC], yv[NC];
+                gather(rsh, gA);
 #pragma unroll
-                for (int c = 0; c < NC; ++c) {
-                    double sacc = 0.0;
-#pragma unroll
-                    for (int u = 0; u < LPL; ++u) sacc += pv[c][u] * rsh[pp[c][u]];
-                    const int len = cln[q][c];
-                    if (len > LPL * G) {
-                        const int e0 = cst[q][c], vb = vbs[q][c];
-                        for (int e = g + LPL * G; e < len; e += G) sacc += a.Ak_v[vb + e] * rsh[a.posA[eo + e0 + e]];
-                    }
-                    gA[c] = sacc;
-                }
-#pragma unroll
-                for (int c = 0; c < NC; ++c) {
-                    gA[c] = group_sum<G>(gA[c]);
-                    gc[c] = gA[c];
-                }
-                // normal-equation residual of the penalised problem: g - P m
-                double pen[NC];
-#pragma unroll
-                for (int c = 0; c < NC; ++c) pen[c] = 0.0;
-                if constexpr (WEIGHTED) {
-#pragma unroll
-                    for (int c = 0; c < NC; ++c) {
-                        if (valid && c < nJ) pen[c] = a.mu * (1.0 / a.w[scol + c] - 1.0);
-                        gc[c] -= pen[c] * m64[c];
-                    }
-                }
-                // y = R^{-T} g (FP32): y_c = (g_c - sum_{k<c} R_kc y_k) / R_cc
-                TQ ydist[R];
-                TQ yrep[NC];
-#pragma unroll
-                for (int t = 0; t < R; ++t) ydist[t] = 0;
-#pragma unroll
-                for (int c = 0; c < NC; ++c) {
-                    TQ part = 0;
-#pragma unroll
-                    for (int t = 0; t < R; ++t) {
-                        const int row = t * G + g;
-                        if (t * G < c) part += (row < c) ? A[t][c] * ydist[t] : (TQ)0;
-                    }
-                    part = group_sum<G>(part);
-                    TQ yc = ((TQ)gc[c] - part) * rinv[c];
-                    yc = (c < nJ) ? yc : (TQ)0;
-                    yrep[c] = yc;
-                    if (g == c % G) ydist[c / G] = yc;
-                }
-                // delta = R^{-1} y
-                TQ dl[NC];
-#pragma unroll
-                for (int k = NC - 1; k >= 0; --k) {
-                    const int tk = k / G, gk = k % G;
-                    TQ sacc = yrep[k];
-#pragma unroll
-                    for (int c = k + 1; c < NC; ++c) sacc -= A[tk][c] * dl[c];
-                    const TQ dk = group_bcast<G>(sacc * rinv[k], g, gk);
-                    dl[k] = (k < nJ) ? dk : (TQ)0;
-                }
+                for (int c = 0; c < NC; ++c) gc[c] = gA[c] - pen[c] * m64[c];
+                solve_normal(gc, dl, yv);
                 // ||b - A(m + d)||^2 = ||r||^2 - 2 d^T A^T r + ||A d||^2, and
                 // ||A d||^2 = ||R d||^2 - d^T P d with R d = y (second order in d)
                 double dg = 0.0, yy = 0.0, pdd = 0.0;
 #pragma unroll
                 for (int c = 0; c < NC; ++c) {
-                    const double d = (double)dl[c];
-                    dg += d * gA[c];
-                    yy += (double)yrep[c] * (double)yrep[c];
-                    pdd += pen[c] * d * d;
-                    m64[c] += d;
+                    dg += dl[c] * gA[c];
+                    yy += yv[c] * yv[c];
+                    pdd += pen[c] * dl[c] * dl[c];
+                    m64[c] += dl[c];
                 }
                 rr_it = rr_it - 2.0 * dg + (yy - pdd);
             }
@@ -456,12 +484,80 @@ k_numeric(NumericArgs a) {
                 r2 += (t * G + g >= nJ) ? x * x : 0.0;
             }
             rr = group_sum<G>(r2);
-            if constexpr (WEIGHTED) {
 #pragma unroll
-                for (int c = 0; c < NC; ++c)
-                    if (valid && c < nJ) rr -= a.mu * (1.0 / a.w[scol + c] - 1.0) * mfin[c] * mfin[c];
-            }
+            for (int c = 0; c < NC; ++c) rr -= pen[c] * mfin[c] * mfin[c];
             rr += outj;
+        }
+
+        if constexpr (BACKWARD) {
+            // r = A m - b is held as rsh = b - A m = -r
+            double* al = alsh + q * RX;
+            reset(rsh, true);
+            load_entries();
+            wave_sync();
+            scatter(rsh, mfin, -1.0);
+            // h = 2 A^T r,  lambda = (A^T A + P)^{-1} h
+            double h[NC], lam[NC], yv[NC];
+            gather(rsh, h);
+#pragma unroll
+            for (int c = 0; c < NC; ++c) h[c] = -2.0 * h[c];
+            solve_normal(h, lam, yv);
+            if constexpr (REFINE) {
+#pragma unroll
+                for (int it = 0; it < 2; ++it) {  // FP64-residual refinement of lambda
+                    reset(al, false);
+                    wave_sync();
+                    scatter(al, lam, 1.0);
+                    double qv[NC], res[NC], dl[NC];
+                    gather(al, qv);
+#pragma unroll
+                    for (int c = 0; c < NC; ++c) res[c] = h[c] - qv[c] - pen[c] * lam[c];
+                    solve_normal(res, dl, yv);
+#pragma unroll
+                    for (int c = 0; c < NC; ++c) lam[c] += dl[c];
+                }
+            }
+            reset(al, false);
+            wave_sync();
+            scatter(al, lam, 1.0);
+            // dL/dA at the gathered entries: 2 r m^T - r lambda^T - (A lambda) m^T
+            const double dL = a.dL;
+            double* cj = a.contrib + eo;
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                const int e0 = cst[q][c];
+#pragma unroll
+                for (int u = 0; u < LPL; ++u) {
+                    const int p = pp[c][u];
+                    if (p != trash)
+                        cj[e0 + g + u * G] = dL * (-2.0 * rsh[p] * mfin[c] + rsh[p] * lam[c] - al[p] * mfin[c]);
+                }
+                const int len = cln[q][c];
+                if (len > LPL * G) {
+                    for (int e = g + LPL * G; e < len; e += G) {
+                        const int p = a.posA[eo + e0 + e];
+                        cj[e0 + e] = dL * (-2.0 * rsh[p] * mfin[c] + rsh[p] * lam[c] - al[p] * mfin[c]);
+                    }
+                }
+            }
+            // dL/dA_0(:, j): -2 r + A lambda inside I_j, 2 a_0 outside
+            for (int e = a0 + g; e < a1; e += G) {
+                const int p = a.posB[e];
+                a.gA0[e] = p != 0xFF ? dL * (2.0 * rsh[p] + al[p]) : dL * 2.0 * a.A0_v[e];
+            }
+            if (valid) {
+#pragma unroll
+                for (int c = 0; c < NC; ++c) {
+                    if (c < nJ && (c % G) == g) {
+                        a.segoff[scol + c] = eo + cst[q][c];
+                        if (a.gw) {
+                            const double wl = a.w[scol + c];
+                            a.gw[scol + c] = dL * a.mu * lam[c] * mfin[c] / (wl * wl);
+                        }
+                    }
+                }
+            }
+            wave_sync();
         }
 
         // ---- outputs
@@ -469,11 +565,13 @@ k_numeric(NumericArgs a) {
 #pragma unroll
         for (int c = 0; c < NC; ++c) nonfinite |= (c < nJ) && !isfinite(mfin[c]);
         if (valid) {
+            if (a.M) {
 #pragma unroll
-            for (int c = 0; c < NC; ++c) {
-                if (c < nJ && (c % G) == g) {
-                    if constexpr (REFINE) static_cast<float*>(a.M)[scol + c] = (float)mfin[c];
-                    else static_cast<double*>(a.M)[scol + c] = mfin[c];
+                for (int c = 0; c < NC; ++c) {
+                    if (c < nJ && (c % G) == g) {
+                        if constexpr (REFINE) static_cast<float*>(a.M)[scol + c] = (float)mfin[c];
+                        else static_cast<double*>(a.M)[scol + c] = mfin[c];
+                    }
                 }
             }
             if (g == 0) {
@@ -485,16 +583,26 @@ k_numeric(NumericArgs a) {
     }
 }
 
-template <typename TQ, int G, int R, int NC, int TC, int LPL, bool W>
+template <typename TQ, int G, int R, int NC, int TC, int LPL, int MODE>
 hipError_t launch_numeric(const NumericArgs& args, int grid, hipStream_t s) {
-    hipLaunchKernelGGL((k_numeric<TQ, G, R, NC, TC, LPL, W>), dim3(grid), dim3(64), 0, s, args);
+    hipLaunchKernelGGL((k_numeric<TQ, G, R, NC, TC, LPL, MODE>), dim3(grid), dim3(64), 0, s, args);
     return hipGetLastError();
 }
 
 // LPL: entries of one A_k column a lane moves with static indices (longer
 // columns fall back to a loop over memory), sized for 5- to 9-point stencils.
-#define SAM_VARIANT(TQ, PREC, G, R, NC, TC, LPL, W) \
-    NumericVariant{PREC, G, R, NC, W, &launch_numeric<TQ, G, R, NC, TC, LPL, W>}
+using LaunchFn = hipError_t (*)(const NumericArgs&, int, hipStream_t);
+
+// the adjoint exists for the weighted variants only
+template <typename TQ, int G, int R, int NC, int TC, int LPL, bool W>
+constexpr LaunchFn backward_launcher() {
+    if constexpr (W) return &launch_numeric<TQ, G, R, NC, TC, LPL, 2>;
+    else return nullptr;
+}
+
+#define SAM_VARIANT(TQ, PREC, G, R, NC, TC, LPL, W)                                      \
+    NumericVariant{PREC, G, R, NC, W, &launch_numeric<TQ, G, R, NC, TC, LPL, W ? 1 : 0>, \
+                   backward_launcher<TQ, G, R, NC, TC, LPL, W>()}
 
 // Menu per precision, cheapest first.  Shapes of the workloads: 2D 5-point
 // level 1 (13 x 5), level 2 (25 x 13); 3D 7-point level 2 (63 x 25); 2D

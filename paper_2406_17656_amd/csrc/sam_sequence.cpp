@@ -337,9 +337,4 @@ sam_status sam_sequence_run(sam_seq* q, const double* const* Ak_vals, void* cons
     return SAM_OK;
 }
 
-sam_status sam_backward(sam_plan*, const double*, const double*, const double*, double, double, sam_precision, double*,
-                        double*, double*, double*, sam_stream_t) {
-    return SAM_ERR_UNSUPPORTED;
-}
-
 }  // extern "C"
