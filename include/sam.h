@@ -197,6 +197,24 @@ sam_status sam_plan_info(const sam_plan* plan, int32_t* n, int32_t* max_rows, in
 sam_status sam_plan_cost(const sam_plan* plan, sam_precision prec, double* flops32, double* flops64,
                          double* bytes);
 
+/* The numeric kernel variants compiled for `prec` (weighted = 0: plain maps,
+ * 1: soft-weighted), in their default order.  Each serves column blocks of
+ * at most G*R rows (G*R - |J_j| penalty rows aside when weighted) and NC
+ * columns; G lanes of a wave64 own one column problem, TC columns are staged
+ * per LDS pass.  Host outputs of `capacity` entries (any may be NULL);
+ * *count receives the number of variants.  Needs no context and no device. */
+sam_status sam_menu(sam_precision prec, int32_t weighted, int32_t capacity, int32_t* count, int32_t* G,
+                    int32_t* R, int32_t* NC, int32_t* TC);
+
+/* Choose the variants of the plan's plain builds in precision `prec`:
+ * `order` lists 1..16 indices into sam_menu(prec, 0); every column is served
+ * by the first listed variant its block fits (this is how the size buckets
+ * are formed).  Re-sorts the plan's buckets; synchronising.  Errors:
+ * SAM_ERR_ARG (bad index or count), SAM_ERR_UNSUPPORTED (some column fits no
+ * listed variant; the previous choice stays). */
+sam_status sam_plan_select(sam_plan* plan, sam_precision prec, const int32_t* order, int32_t count,
+                           sam_stream_t stream);
+
 /* Numeric SAM build on a plan (Section 2): for every column j solve
  * min ||A_k(I_j,J_j) m - A_0(I_j,j)||_2 by Householder QR and back
  * substitution (prec selects FP64 or FP32 + FP64-residual refinement), write
@@ -274,6 +292,9 @@ sam_status sam_sequence_info(const sam_seq* seq, int64_t* nnz_bound);
  * nnz_bound entries); *nnz_S (host) receives its size.  Synchronising. */
 sam_status sam_sequence_pattern(sam_seq* seq, int32_t k, int32_t* S_colptr, int32_t* S_rowind, int64_t* nnz_S,
                                 sam_stream_t stream);
+
+/* sam_plan_select for the sequence's precision; the next run re-captures. */
+sam_status sam_sequence_select(sam_seq* seq, const int32_t* order, int32_t count, sam_stream_t stream);
 
 /* Build every map of the sequence: Ak_vals (host array of n_src device
  * pointers), M_vals (host array of n_src device pointers), res2 (device,

@@ -61,6 +61,9 @@ SIGNATURES = {
                                 ctypes.POINTER(c_int32), ctypes.POINTER(c_int32)]),
     "sam_plan_cost": (c_int32, [P, c_int32, ctypes.POINTER(c_double), ctypes.POINTER(c_double),
                                 ctypes.POINTER(c_double)]),
+    "sam_menu": (c_int32, [c_int32, c_int32, c_int32, ctypes.POINTER(c_int32), P, P, P, P]),
+    "sam_plan_select": (c_int32, [P, c_int32, P, c_int32, P]),
+    "sam_sequence_select": (c_int32, [P, P, c_int32, P]),
     "sam_build_planned": (c_int32, [P, P, P, c_int32, P, P, P, P]),
     "sam_build": (c_int32, [P, CSCP, CSCP, P, P, c_int64, c_int32, P, P, P, P]),
     "sam_residual": (c_int32, [P, CSCP, CSCP, P, P, c_int64, P, c_int32, P, P, P]),

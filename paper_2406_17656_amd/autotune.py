@@ -1,0 +1,120 @@
+"""Autotuner of the numeric kernel's size classes.
+
+The library compiles a menu of kernel variants per precision (lanes per
+column problem G, rows per lane R, columns NC, LDS tile chunk TC; see
+sam_menu).  A plan buckets each column into the first variant of an ordered
+list that its block fits.  ``tune`` times candidate orders on the plan's own
+shape histogram -- the default order and, for every variant, the order that
+puts it first -- keeps the fastest (sam_plan_select) and caches the choice
+per device, precision and shape signature in a JSON file
+($SAM_TUNE_CACHE, default ~/.cache/sam_mi355x_tune.json).
+"""
+from __future__ import annotations
+
+import ctypes
+import hashlib
+import json
+import os
+
+import torch
+
+from . import _capi as C
+from .sam import PREC, SamError, _prec
+
+CACHE = os.environ.get("SAM_TUNE_CACHE", os.path.join(os.path.expanduser("~"), ".cache",
+                                                      "sam_mi355x_tune.json"))
+
+
+def menu(prec="f32", weighted=0) -> list[dict]:
+    lib = C.load()
+    cap = 64
+    cnt = ctypes.c_int32()
+    arrs = [(ctypes.c_int32 * cap)() for _ in range(4)]
+    st = lib.sam_menu(_prec(prec), int(weighted), cap, ctypes.byref(cnt), *arrs)
+    if st != C.SAM_OK:
+        raise SamError(st, "sam_menu")
+    return [{"index": i, "G": arrs[0][i], "R": arrs[1][i], "NC": arrs[2][i], "TC": arrs[3][i],
+             "max_rows": arrs[0][i] * arrs[1][i]} for i in range(min(cnt.value, cap))]
+
+
+def candidate_orders(n_variants: int) -> list[list[int]]:
+    default = list(range(n_variants))
+    out = [default]
+    for i in range(n_variants):
+        o = [i] + [k for k in default if k != i]
+        if o not in out:
+            out.append(o)
+    return [o[:16] for o in out]
+
+
+def signature(plan, prec) -> str:
+    info = plan.info()
+    dev = torch.cuda.get_device_name(plan.ctx.device)
+    # selection-invariant shape data (the bucket split depends on the selection)
+    key = json.dumps([dev, prec, info["n"], info["max_rows"], info["max_cols"], info["gathered"],
+                      plan.nnz_S])
+    return hashlib.sha256(key.encode()).hexdigest()[:24]
+
+
+def _time(plan, Ak_val, A0_val, prec, reps):
+    M = torch.empty(max(plan.nnz_S, 1), dtype=torch.float32 if PREC[prec] == 1 else torch.float64,
+                    device=Ak_val.device)
+    r = torch.empty(1, dtype=torch.float64, device=Ak_val.device)
+    plan.build(Ak_val, A0_val, prec, M=M, res2=r)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        plan.build(Ak_val, A0_val, prec, M=M, res2=r)
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps * 1e3  # microseconds
+
+
+def _load_cache() -> dict:
+    try:
+        with open(CACHE) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def _store_cache(d: dict) -> None:
+    try:
+        os.makedirs(os.path.dirname(CACHE), exist_ok=True)
+        tmp = CACHE + ".tmp%d" % os.getpid()
+        with open(tmp, "w") as f:
+            json.dump(d, f, indent=1)
+        os.replace(tmp, CACHE)
+    except OSError:
+        pass
+
+
+def tune(plan, Ak_val, A0_val, prec="f32", reps=10, use_cache=True) -> dict:
+    """Pick the fastest variant order for this plan; returns
+    {"order", "us", "timings", "cached"} and leaves the plan selected."""
+    sig = signature(plan, prec)
+    cache = _load_cache() if use_cache else {}
+    if sig in cache:
+        order = cache[sig]["order"]
+        plan.select(order, prec)
+        return {"order": order, "us": cache[sig]["us"], "timings": cache[sig].get("timings", {}),
+                "cached": True}
+    n_var = len(menu(prec))
+    timings = {}
+    best = None
+    for order in candidate_orders(n_var):
+        try:
+            plan.select(order, prec)
+        except SamError:
+            continue  # some column fits none of the listed variants
+        us = _time(plan, Ak_val, A0_val, prec, reps)
+        timings[",".join(map(str, order[:3]))] = us
+        if best is None or us < best[1]:
+            best = (order, us)
+    plan.select(best[0], prec)
+    if use_cache:
+        cache[sig] = {"order": best[0], "us": best[1], "timings": timings}
+        _store_cache(cache)
+    return {"order": best[0], "us": best[1], "timings": timings, "cached": False}

@@ -203,11 +203,30 @@ BucketTable menu_table(int prec, int weighted, std::vector<const NumericVariant*
     return tab;
 }
 
+BucketTable table_of(const std::vector<const NumericVariant*>& vars, int weighted) {
+    BucketTable tab{};
+    tab.nb = (int)std::min<size_t>(vars.size(), samk::kMaxBuckets);
+    tab.rows_plus_cols = weighted;
+    for (int b = 0; b < tab.nb; ++b) {
+        tab.max_rows[b] = vars[b]->max_rows();
+        tab.max_cols[b] = vars[b]->NC;
+    }
+    return tab;
+}
+
 sam_status plan_combo(sam_plan* pl, int prec, int weighted, void* temp, int* unfit_d, hipStream_t s) {
+    std::vector<const NumericVariant*> vars;
+    menu_table(prec, weighted, &vars);
+    return plan_combo_with(pl, prec, weighted, vars, temp, unfit_d, s);
+}
+
+sam_status plan_combo_with(sam_plan* pl, int prec, int weighted, const std::vector<const NumericVariant*>& vars,
+                           void* temp, int* unfit_d, hipStream_t s) {
     sam_ctx* ctx = pl->ctx;
     Combo& cb = pl->combo[prec][weighted];
-    cb.variants.clear();
-    BucketTable tab = menu_table(prec, weighted, &cb.variants);
+    cb.variants = vars;
+    if (cb.variants.size() > (size_t)samk::kMaxBuckets) cb.variants.resize(samk::kMaxBuckets);
+    BucketTable tab = table_of(cb.variants, weighted);
     cb.tab = tab;
     HIP_TRY(ctx, hipMemsetAsync(unfit_d, 0, sizeof(int), s));
     HIP_TRY(ctx, samk::bucket_sort(pl->n, pl->S_cp, pl->nI, tab, cb.queue, cb.bstart, unfit_d, nullptr, temp, s));
@@ -696,6 +715,80 @@ sam_status sam_build_weighted(sam_plan* plan, const double* Ak_val, const double
     if (st) return st;
     return run_numeric(plan, Ak_val, A0_val, w, mu, prec == SAM_PREC_F32_REFINE ? 1 : 0, 1, M_val, col_res2, res2,
                        S(stream));
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------- variants
+
+namespace samh {
+
+std::vector<const NumericVariant*> menu_subset(int prec, int weighted, const int32_t* order, int32_t count,
+                                               bool* ok) {
+    std::vector<const NumericVariant*> all, out;
+    menu_table(prec, weighted, &all);
+    *ok = count >= 1 && count <= samk::kMaxBuckets && order != nullptr;
+    for (int32_t i = 0; *ok && i < count; ++i) {
+        if (order[i] < 0 || order[i] >= (int32_t)all.size()) *ok = false;
+        else out.push_back(all[order[i]]);
+    }
+    return out;
+}
+
+sam_status plan_select(sam_plan* pl, int prec, const std::vector<const NumericVariant*>& vars, hipStream_t s) {
+    sam_ctx* ctx = pl->ctx;
+    const int n = pl->n;
+    const size_t need = align256(samk::bucket_temp_bytes(n)) + 512;
+    HIP_TRY(ctx, grow(ctx->ws, need));
+    Carve cv(ctx->ws.p);
+    void* btemp = cv.take<char>(samk::bucket_temp_bytes(n));
+    int* flag = cv.take<int>(4);
+    Combo& cb = pl->combo[prec][0];
+    const std::vector<const NumericVariant*> previous = cb.variants;
+    sam_status st = plan_combo_with(pl, prec, 0, vars, btemp, flag, s);
+    if (st) return st;
+    if (!cb.ok) {
+        const std::string why = cb.why;
+        st = plan_combo_with(pl, prec, 0, previous, btemp, flag, s);
+        if (st) return st;
+        return fail(ctx, SAM_ERR_UNSUPPORTED, "selection rejected: %s", why.c_str());
+    }
+    return SAM_OK;
+}
+
+}  // namespace samh
+
+extern "C" {
+
+sam_status sam_menu(sam_precision prec, int32_t weighted, int32_t capacity, int32_t* count, int32_t* G, int32_t* R,
+                    int32_t* NC, int32_t* TC) {
+    if (!prec_ok(prec) || (weighted != 0 && weighted != 1) || !count || capacity < 0) return SAM_ERR_ARG;
+    std::vector<const NumericVariant*> all;
+    menu_table(prec == SAM_PREC_F32_REFINE ? 1 : 0, weighted, &all);
+    *count = (int32_t)all.size();
+    for (int32_t i = 0; i < capacity && i < (int32_t)all.size(); ++i) {
+        if (G) G[i] = all[i]->G;
+        if (R) R[i] = all[i]->R;
+        if (NC) NC[i] = all[i]->NC;
+        if (TC) TC[i] = all[i]->TC;
+    }
+    return SAM_OK;
+}
+
+sam_status sam_plan_select(sam_plan* plan, sam_precision prec, const int32_t* order, int32_t count,
+                           sam_stream_t stream) {
+    if (!plan || !plan->ctx) return SAM_ERR_ARG;
+    sam_ctx* ctx = plan->ctx;
+    check_ctx(ctx);
+    if (!prec_ok(prec)) return fail(ctx, SAM_ERR_ARG, "unknown precision %d", (int)prec);
+    const int pi = prec == SAM_PREC_F32_REFINE ? 1 : 0;
+    bool ok = false;
+    std::vector<const NumericVariant*> vars = menu_subset(pi, 0, order, count, &ok);
+    if (!ok) return fail(ctx, SAM_ERR_ARG, "variant order must list 1..%d valid menu indices", samk::kMaxBuckets);
+    sam_status st = need_device(ctx);
+    if (st) return st;
+    if (plan->n == 0) return SAM_OK;
+    return plan_select(plan, pi, vars, S(stream));
 }
 
 }  // extern "C"

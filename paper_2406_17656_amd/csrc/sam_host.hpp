@@ -123,6 +123,15 @@ sam_status compute_pattern(sam_ctx* ctx, const sam_csc* Ak, const sam_pattern_sp
 // The bucket table of one (precision, weighted) combination of the menu.
 samk::BucketTable menu_table(int prec, int weighted, std::vector<const samk::NumericVariant*>* variants);
 sam_status plan_combo(sam_plan* pl, int prec, int weighted, void* temp, int* unfit_d, hipStream_t s);
+// Bucket the plan's columns over an explicit ordered list of variants.
+sam_status plan_combo_with(sam_plan* pl, int prec, int weighted, const std::vector<const samk::NumericVariant*>& vars,
+                           void* temp, int* unfit_d, hipStream_t s);
+samk::BucketTable table_of(const std::vector<const samk::NumericVariant*>& vars, int weighted);
+// Variants of sam_menu(prec, weighted) in the given order (nullptr entries when out of range).
+std::vector<const samk::NumericVariant*> menu_subset(int prec, int weighted, const int32_t* order, int32_t count,
+                                                     bool* ok);
+// Re-bucket a plan's plain builds over a selected variant order (synchronising).
+sam_status plan_select(sam_plan* pl, int prec, const std::vector<const samk::NumericVariant*>& vars, hipStream_t s);
 sam_status run_numeric(sam_plan* pl, const double* Ak_val, const double* A0_val, const double* w, double mu, int prec,
                        int weighted, void* M_val, double* col_res2, double* res2, hipStream_t s);
 

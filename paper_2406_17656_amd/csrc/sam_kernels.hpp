@@ -107,6 +107,8 @@ struct NumericVariant {
     int R;           // rows per lane
     int NC;          // max columns
     int weighted;    // 1: stacked penalty rows
+    int TC;          // columns staged per LDS tile pass
+    int LPL;         // entries per lane and column moved with static indices
     hipError_t (*launch)(const NumericArgs&, int grid, hipStream_t);
     hipError_t (*launch_backward)(const NumericArgs&, int grid, hipStream_t);  // weighted only
     int max_rows() const { return G * R; }

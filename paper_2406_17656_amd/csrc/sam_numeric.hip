@@ -600,13 +600,16 @@ constexpr LaunchFn backward_launcher() {
     else return nullptr;
 }
 
-#define SAM_VARIANT(TQ, PREC, G, R, NC, TC, LPL, W)                                      \
-    NumericVariant{PREC, G, R, NC, W, &launch_numeric<TQ, G, R, NC, TC, LPL, W ? 1 : 0>, \
+#define SAM_VARIANT(TQ, PREC, G, R, NC, TC, LPL, W)                                                \
+    NumericVariant{PREC, G, R, NC, W, TC, LPL, &launch_numeric<TQ, G, R, NC, TC, LPL, W ? 1 : 0>, \
                    backward_launcher<TQ, G, R, NC, TC, LPL, W>()}
 
 // Menu per precision, cheapest first.  Shapes of the workloads: 2D 5-point
 // level 1 (13 x 5), level 2 (25 x 13); 3D 7-point level 2 (63 x 25); 2D
 // 9-point level 2 with thresholds (<= 49 x 24); weighted 3D (88 x 25).
+// The first fitting entry of a (precision, weighting) group serves a column
+// by default; later entries of the same shape class are alternatives the
+// autotuner can put in front (sam_plan_select).
 const NumericVariant kMenu[] = {
     // FP32 + refinement
     SAM_VARIANT(float, 1, 2, 8, 5, 4, 3, false),
@@ -615,6 +618,10 @@ const NumericVariant kMenu[] = {
     SAM_VARIANT(float, 1, 4, 8, 16, 2, 2, false),
     SAM_VARIANT(float, 1, 16, 4, 25, 1, 1, false),
     SAM_VARIANT(float, 1, 32, 4, 32, 1, 1, false),
+    SAM_VARIANT(float, 1, 1, 13, 5, 1, 5, false),   // one problem per lane, no reductions
+    SAM_VARIANT(float, 1, 4, 7, 13, 1, 2, false),
+    SAM_VARIANT(float, 1, 8, 4, 13, 2, 1, false),
+    SAM_VARIANT(float, 1, 32, 2, 25, 1, 1, false),
     // FP64
     SAM_VARIANT(double, 0, 2, 8, 5, 4, 3, false),
     SAM_VARIANT(double, 0, 2, 8, 8, 4, 3, false),
@@ -622,6 +629,8 @@ const NumericVariant kMenu[] = {
     SAM_VARIANT(double, 0, 8, 4, 16, 2, 1, false),
     SAM_VARIANT(double, 0, 32, 2, 25, 1, 1, false),
     SAM_VARIANT(double, 0, 64, 2, 32, 1, 1, false),
+    SAM_VARIANT(double, 0, 1, 13, 5, 1, 5, false),
+    SAM_VARIANT(double, 0, 8, 4, 13, 2, 1, false),
     // soft-weighted (stacked penalty rows)
     SAM_VARIANT(float, 1, 4, 8, 13, 2, 2, true),
     SAM_VARIANT(float, 1, 32, 3, 25, 1, 1, true),

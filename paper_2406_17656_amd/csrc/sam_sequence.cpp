@@ -297,6 +297,32 @@ sam_status sam_sequence_pattern(sam_seq* q, int32_t k, int32_t* S_colptr, int32_
     return SAM_OK;
 }
 
+sam_status sam_sequence_select(sam_seq* q, const int32_t* order, int32_t count, sam_stream_t stream) {
+    if (!q || !q->ctx) return SAM_ERR_ARG;
+    sam_ctx* ctx = q->ctx;
+    check_ctx(ctx);
+    bool ok = false;
+    std::vector<const samk::NumericVariant*> vars = menu_subset(q->prec, 0, order, count, &ok);
+    if (!ok) return fail(ctx, SAM_ERR_ARG, "variant order must list 1..%d valid menu indices", samk::kMaxBuckets);
+    sam_status st = need_device(ctx);
+    if (st) return st;
+    if ((st = plan_select(q->plan, q->prec, vars, S(stream)))) return st;
+    if (q->replan) {
+        Combo& cb = q->dplan.combo[q->prec][0];
+        cb.variants = q->plan->combo[q->prec][0].variants;
+        cb.tab = q->plan->combo[q->prec][0].tab;
+        const std::vector<int>& sc = q->plan->combo[q->prec][0].counts;
+        cb.counts.assign(sc.size(), 0);
+        int suffix = 0;
+        for (int b = (int)sc.size() - 1; b >= 0; --b) {
+            suffix += sc[b];
+            cb.counts[b] = suffix;
+        }
+    }
+    drop_graph(q);  // the next run captures the new launches
+    return SAM_OK;
+}
+
 sam_status sam_sequence_run(sam_seq* q, const double* const* Ak_vals, void* const* M_vals, double* res2,
                             sam_stream_t stream) {
     if (!q || !q->ctx) return SAM_ERR_ARG;

@@ -225,6 +225,11 @@ class Plan:
         return {"n": n.value, "max_rows": mr.value, "max_cols": mc.value, "gathered": ga.value,
                 "bucket_cols": list(bc[:nb.value])}
 
+    def select(self, order, prec="f32"):
+        """sam_plan_select: serve columns with the first listed menu variant that fits."""
+        arr = (ctypes.c_int32 * len(order))(*order)
+        self.ctx.check(self.ctx.lib.sam_plan_select(self.h, _prec(prec), arr, len(order), self.ctx.stream()))
+
     def cost(self, prec="f32") -> dict:
         f32 = ctypes.c_double(); f64 = ctypes.c_double(); by = ctypes.c_double()
         self.ctx.check(self.ctx.lib.sam_plan_cost(self.h, _prec(prec), ctypes.byref(f32), ctypes.byref(f64),
@@ -303,6 +308,10 @@ class Sequence:
         dev = self.A0.colptr.device
         return [torch.empty(max(self.nnz_bound, 1), dtype=_mdtype(self.prec), device=dev)
                 for _ in range(self.n_src)]
+
+    def select(self, order):
+        arr = (ctypes.c_int32 * len(order))(*order)
+        self.ctx.check(self.ctx.lib.sam_sequence_select(self.h, arr, len(order), self.ctx.stream()))
 
     def run(self, Ak_vals, M_vals, res2):
         arr_a = (ctypes.c_void_p * self.n_src)(*[t.data_ptr() for t in Ak_vals])

@@ -111,3 +111,23 @@ def test_empty_matrices_rejected(hctx):
     a, b = csc(n=4, nnz=0), csc(n=4)
     assert lib.sam_plan_create(h, ctypes.byref(a), ctypes.byref(b), 1, 1, 4, ctypes.byref(pl), None) == 1
     assert "stored entries" in lib.sam_last_error(h).decode()
+
+
+def test_menu_without_device():
+    from paper_2406_17656_amd import autotune
+    for prec in ("f32", "f64"):
+        m = autotune.menu(prec)
+        assert len(m) >= 6 and all(v["max_rows"] >= 13 and v["NC"] >= 5 for v in m)
+        assert autotune.menu(prec, weighted=1)
+    orders = autotune.candidate_orders(5)
+    assert orders[0] == [0, 1, 2, 3, 4] and [3, 0, 1, 2, 4] in orders
+    lib = C.load()
+    cnt = ctypes.c_int32()
+    assert lib.sam_menu(7, 0, 0, ctypes.byref(cnt), None, None, None, None) == 1
+
+
+def test_plan_select_validation(hctx):
+    lib, h = hctx
+    # no plan: argument error before anything else
+    arr = (ctypes.c_int32 * 1)(0)
+    assert lib.sam_plan_select(None, 1, arr, 1, None) == 1
