@@ -79,7 +79,11 @@ k_numeric(NumericArgs a) {
     constexpr int RX = RM + G;       // plus one scratch row per lane
     constexpr bool REFINE = std::is_same<TQ, float>::value;
     static_assert(TC >= 1, "tile chunk");
-    __shared__ double tile[P * RX * TC];  // gather staging, later the residual vector
+    // gather staging in the QR's precision; afterwards the same memory holds
+    // the FP64 residual vector (P * RX doubles)
+    constexpr int kTileD = (P * RX * TC * (int)sizeof(TQ) + 7) / 8;
+    __shared__ double lds_tile[kTileD > P * RX ? kTileD : P * RX];
+    TQ* tile = reinterpret_cast<TQ*>(lds_tile);
     __shared__ double bsh[P * RX];        // b = A_0(I_j, j)
     __shared__ int cst[P][NC + 1];        // entry offset of column c in the block
     __shared__ int vbs[P][NC];            // start of A_k(:, J_j[c]) in the value array
@@ -196,7 +200,7 @@ k_numeric(NumericArgs a) {
             for (int t = 0; t <= R; ++t) {
                 const int row = t < R ? t * G + g : trash;
 #pragma unroll
-                for (int cc = 0; cc < TC; ++cc) tile[(q * RX + row) * TC + cc] = 0.0;
+                for (int cc = 0; cc < TC; ++cc) tile[(q * RX + row) * TC + cc] = (TQ)0;
             }
             wave_sync();
 #pragma unroll
@@ -204,12 +208,12 @@ k_numeric(NumericArgs a) {
                 const int c = c0 + cc;
                 if (c < NC) {
 #pragma unroll
-                    for (int s = 0; s < LPL; ++s) tile[(q * RX + pp[c][s]) * TC + cc] = pv[c][s];
+                    for (int s = 0; s < LPL; ++s) tile[(q * RX + pp[c][s]) * TC + cc] = (TQ)pv[c][s];
                     const int len = cln[q][c];
                     if (len > LPL * G) {  // long columns: the rest straight from memory
                         const int e0 = cst[q][c], vb = vbs[q][c];
                         for (int e = g + LPL * G; e < len; e += G)
-                            tile[(q * RX + a.posA[eo + e0 + e]) * TC + cc] = a.Ak_v[vb + e];
+                            tile[(q * RX + a.posA[eo + e0 + e]) * TC + cc] = (TQ)a.Ak_v[vb + e];
                     }
                 }
             }
@@ -218,7 +222,7 @@ k_numeric(NumericArgs a) {
             for (int t = 0; t < R; ++t)
 #pragma unroll
                 for (int cc = 0; cc < TC; ++cc)
-                    if (c0 + cc < NC) A[t][c0 + cc] = (TQ)tile[(q * RX + t * G + g) * TC + cc];
+                    if (c0 + cc < NC) A[t][c0 + cc] = tile[(q * RX + t * G + g) * TC + cc];
             wave_sync();
         }
         // penalty rows: row nIj + c holds sqrt(p_c) in column c
@@ -321,7 +325,7 @@ k_numeric(NumericArgs a) {
             m[k] = (k < nJ) ? mk : (TQ)0;
         }
 
-        double* rsh = tile + q * RX;  // residual vector (the tile is free now)
+        double* rsh = lds_tile + q * RX;  // residual vector (the tile is free now)
 
         // Sparse FP64 passes over the gathered entries of the block.  Rows are
         // distinct inside one column, so the lanes of a group never update
