@@ -109,11 +109,23 @@ samk::SparsifySpec to_sp(const sam_pattern_spec* spec) {
 // p-1 times S <- expand(S, B).  Produces device arrays into out_cp/out_ri
 // (grown as needed) and the host nnz.
 sam_status compute_pattern(sam_ctx* ctx, const sam_csc* Ak, const sam_pattern_spec* spec, DevBuf& out_cp,
-                           DevBuf& out_ri, int64_t* nnz_out, hipStream_t s, std::vector<int64_t>* level_nnz) {
+                           DevBuf& out_ri, int64_t* nnz_out, hipStream_t s, PatternLevels* levels) {
     const int n = Ak->n;
+    const size_t cp_bytes = (size_t)(n + 1) * 4;
+    DevBuf* levels_cp = levels ? levels->cp : nullptr;
+    if (levels) {
+        levels->nnz.clear();
+        levels->maxcol.clear();
+    }
+    if (levels_cp) HIP_TRY(ctx, grow(*levels_cp, cp_bytes * (size_t)std::max(spec->power, 1)));
+    auto keep_level = [&](int lev, const int* cp) {
+        return levels_cp ? hipMemcpyAsync((char*)levels_cp->p + cp_bytes * lev, cp, cp_bytes,
+                                          hipMemcpyDeviceToDevice, s)
+                         : hipSuccess;
+    };
     samk::SparsifySpec sp = to_sp(spec);
     // workspace: counts (n int), scan out (n+1 int64), scan temp, D (n double),
-    // B_cp (n+1), B_ri (nnz+n), overflow flag, bad flag
+    // B_cp (n+1), B_ri (nnz+n), flags (overflow, bad column, longest column)
     const size_t nnzB_bound = (size_t)Ak->nnz + (size_t)n;
     size_t need = align256((size_t)n * 4) + align256((size_t)(n + 1) * 8) + align256(samk::scan_temp_bytes(n)) +
                   align256((size_t)n * 8) + align256((size_t)(n + 1) * 4) + align256(nnzB_bound * 4) + 512;
@@ -125,10 +137,9 @@ sam_status compute_pattern(sam_ctx* ctx, const sam_csc* Ak, const sam_pattern_sp
     double* D = cv.take<double>(n);
     int* B_cp = cv.take<int>(n + 1);
     int* B_ri = cv.take<int>(nnzB_bound);
-    int* flags = cv.take<int>(2);  // [0] overflow, [1] bad column
-    HIP_TRY(ctx, hipMemsetAsync(flags, 0, sizeof(int), s));
-    const int nbad = n;
-    HIP_TRY(ctx, hipMemcpyAsync(flags + 1, &nbad, sizeof(int), hipMemcpyHostToDevice, s));
+    int* flags = cv.take<int>(3);  // [0] overflow, [1] bad column, [2] longest column of the last level
+    const int init[3] = {0, n, 0};
+    HIP_TRY(ctx, hipMemcpyAsync(flags, init, sizeof init, hipMemcpyHostToDevice, s));
     if (n == 0) {
         HIP_TRY(ctx, grow(out_cp, sizeof(int)));
         HIP_TRY(ctx, hipMemsetAsync(out_cp.p, 0, sizeof(int), s));
@@ -136,22 +147,37 @@ sam_status compute_pattern(sam_ctx* ctx, const sam_csc* Ak, const sam_pattern_sp
         HIP_TRY(ctx, hipStreamSynchronize(s));
         return SAM_OK;
     }
+    // total and longest column of the level just counted
+    auto level_facts = [&](int64_t* tot, int* maxc) {
+        hipError_t e = hipMemcpyAsync(tot, off + n, sizeof(int64_t), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(maxc, flags + 2, sizeof(int), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        return e;
+    };
     HIP_TRY(ctx, samk::sparsify_count(n, Ak->colptr, Ak->rowind, Ak->val, sp, D, counts, s));
-    HIP_TRY(ctx, samk::scan_counts(counts, n, off, B_cp, flags, stemp, s));
+    HIP_TRY(ctx, samk::scan_counts(counts, n, off, B_cp, flags, stemp, s, flags + 2));
     HIP_TRY(ctx, samk::sparsify_fill(n, Ak->colptr, Ak->rowind, Ak->val, sp, D, B_cp, B_ri, s));
+    HIP_TRY(ctx, keep_level(0, B_cp));
     int64_t nnzB = 0;
-    HIP_TRY(ctx, read_back(off + n, &nnzB, s));
-    if (level_nnz) level_nnz->assign(1, nnzB);
+    int maxB = 0;
+    HIP_TRY(ctx, level_facts(&nnzB, &maxB));
+    if (levels) {
+        levels->nnz.push_back(nnzB);
+        levels->maxcol.push_back(maxB);
+    }
     const int* cur_cp = B_cp;
     const int* cur_ri = B_ri;
     int64_t cur_nnz = nnzB;
+    int cur_max = maxB;
     DevBuf level_cp, level_ri;  // alternating level buffers
     DevBuf level_cp2, level_ri2;
     for (int lev = 1; lev < spec->power; ++lev) {
-        HIP_TRY(ctx, samk::expand_count(n, cur_cp, cur_ri, B_cp, B_ri, counts, flags + 1, s));
-        HIP_TRY(ctx, samk::scan_counts(counts, n, off, nullptr, flags, stemp, s));
+        HIP_TRY(ctx, samk::expand_count(n, cur_cp, cur_ri, B_cp, B_ri, counts, flags + 1, cur_max, s));
+        HIP_TRY(ctx, hipMemsetAsync(flags + 2, 0, sizeof(int), s));
+        HIP_TRY(ctx, samk::scan_counts(counts, n, off, nullptr, flags, stemp, s, flags + 2));
         int64_t tot = 0;
-        HIP_TRY(ctx, read_back(off + n, &tot, s));
+        int tmax = 0;
+        HIP_TRY(ctx, level_facts(&tot, &tmax));
         if (tot > INT_MAX) {
             release(level_cp); release(level_ri); release(level_cp2); release(level_ri2);
             return fail(ctx, SAM_ERR_OVERFLOW, "pattern level %d has %lld entries (>= 2^31)", lev + 1, (long long)tot);
@@ -161,11 +187,16 @@ sam_status compute_pattern(sam_ctx* ctx, const sam_csc* Ak, const sam_pattern_sp
         HIP_TRY(ctx, grow(ncp, (size_t)(n + 1) * 4));
         HIP_TRY(ctx, grow(nri, (size_t)std::max<int64_t>(tot, 1) * 4));
         HIP_TRY(ctx, samk::scan_counts(counts, n, off, (int*)ncp.p, flags, stemp, s));
-        HIP_TRY(ctx, samk::expand_fill(n, cur_cp, cur_ri, B_cp, B_ri, (int*)ncp.p, (int*)nri.p, s));
+        HIP_TRY(ctx, samk::expand_fill(n, cur_cp, cur_ri, B_cp, B_ri, (int*)ncp.p, (int*)nri.p, cur_max, s));
+        HIP_TRY(ctx, keep_level(lev, (const int*)ncp.p));
         cur_cp = (int*)ncp.p;
         cur_ri = (int*)nri.p;
         cur_nnz = tot;
-        if (level_nnz) level_nnz->push_back(tot);
+        cur_max = tmax;
+        if (levels) {
+            levels->nnz.push_back(tot);
+            levels->maxcol.push_back(tmax);
+        }
     }
     int hflags[2] = {0, n};
     HIP_TRY(ctx, hipMemcpyAsync(hflags, flags, sizeof hflags, hipMemcpyDeviceToHost, s));
@@ -492,6 +523,22 @@ sam_status sam_plan_create(sam_ctx* ctx, const sam_csc* Ak, const sam_csc* A0, c
     void* btemp = tw.take<char>(samk::bucket_temp_bytes(n));
     int* flags = tw.take<int>(4);
 
+    // S's column pointers are checked on the host before any kernel reads S
+    std::vector<int> hcp((size_t)n + 1, 0);
+    int longest = 0;
+    if (n > 0) {
+        if ((he = hipMemcpyAsync(hcp.data(), S_colptr, (size_t)(n + 1) * 4, hipMemcpyDeviceToHost, s)) != hipSuccess ||
+            (he = hipStreamSynchronize(s)) != hipSuccess)
+            return bail(fail(ctx, SAM_ERR_HIP, "reading S_colptr: %s", hipGetErrorString(he)));
+        if (hcp[0] != 0 || hcp[n] != nnz_S)
+            return bail(fail(ctx, SAM_ERR_SHAPE, "S_colptr[0] = %d, S_colptr[n] = %d but nnz_S = %lld", hcp[0], hcp[n],
+                             (long long)nnz_S));
+        for (int j = 0; j < n; ++j) {
+            if (hcp[j + 1] < hcp[j])
+                return bail(fail(ctx, SAM_ERR_UNSORTED, "S_colptr decreases at column %d", j));
+            longest = std::max(longest, hcp[j + 1] - hcp[j]);
+        }
+    }
     int64_t E = 0;
     if (n > 0) {
         if ((he = samk::plan_gather_count(n, S_colptr, S_rowind, Ak->colptr, counts, s)) != hipSuccess ||
@@ -519,22 +566,15 @@ sam_status sam_plan_create(sam_ctx* ctx, const sam_csc* Ak, const sam_csc* A0, c
     pl->rtemp = cv.take<char>(samk::reduce_temp_bytes(n));
 
     if (n > 0) {
+        std::vector<int> hnI(n);
         if ((he = hipMemcpyAsync(pl->eoff, off, (size_t)(n + 1) * 8, hipMemcpyDeviceToDevice, s)) != hipSuccess ||
             (he = samk::plan_positions(n, S_colptr, S_rowind, Ak->colptr, Ak->rowind, A0->colptr, A0->rowind,
-                                       pl->eoff, pl->nI, pl->posA, pl->posB, s)) != hipSuccess)
+                                       pl->eoff, pl->nI, pl->posA, pl->posB, longest, s)) != hipSuccess)
             return bail(fail(ctx, SAM_ERR_HIP, "plan positions: %s", hipGetErrorString(he)));
-        // shape statistics (host)
-        std::vector<int> hnI(n), hcp(n + 1);
         if ((he = hipMemcpyAsync(hnI.data(), pl->nI, (size_t)n * 4, hipMemcpyDeviceToHost, s)) != hipSuccess ||
-            (he = hipMemcpyAsync(hcp.data(), S_colptr, (size_t)(n + 1) * 4, hipMemcpyDeviceToHost, s)) != hipSuccess ||
             (he = hipStreamSynchronize(s)) != hipSuccess)
             return bail(fail(ctx, SAM_ERR_HIP, "plan stats: %s", hipGetErrorString(he)));
-        if (hcp[0] != 0 || hcp[n] != nnz_S)
-            return bail(fail(ctx, SAM_ERR_SHAPE, "S_colptr[0] = %d, S_colptr[n] = %d but nnz_S = %lld", hcp[0], hcp[n],
-                             (long long)nnz_S));
         for (int j = 0; j < n; ++j) {
-            if (hcp[j + 1] < hcp[j])
-                return bail(fail(ctx, SAM_ERR_UNSORTED, "S_colptr decreases at column %d", j));
             pl->max_rows = std::max(pl->max_rows, hnI[j]);
             pl->max_cols = std::max(pl->max_cols, hcp[j + 1] - hcp[j]);
             const double r = hnI[j], c = hcp[j + 1] - hcp[j];

@@ -118,8 +118,19 @@ hipError_t read_back(const T* dptr, T* host, hipStream_t s) {
     return hipStreamSynchronize(s);
 }
 
+// Per-level facts of a pattern computation: the size and longest column of
+// every level (level 0 is B, the last is S), and optionally (cp != null)
+// every level's column pointers (p arrays of n+1 int32, level after level,
+// grown as needed).
+struct PatternLevels {
+    std::vector<int64_t> nnz;
+    std::vector<int> maxcol;
+    DevBuf* cp = nullptr;
+};
+
+// Pattern S((I + B)^p) on the device.
 sam_status compute_pattern(sam_ctx* ctx, const sam_csc* Ak, const sam_pattern_spec* spec, DevBuf& out_cp,
-                           DevBuf& out_ri, int64_t* nnz_out, hipStream_t s, std::vector<int64_t>* level_nnz = nullptr);
+                           DevBuf& out_ri, int64_t* nnz_out, hipStream_t s, PatternLevels* levels = nullptr);
 // The bucket table of one (precision, weighted) combination of the menu.
 samk::BucketTable menu_table(int prec, int weighted, std::vector<const samk::NumericVariant*>* variants);
 sam_status plan_combo(sam_plan* pl, int prec, int weighted, void* temp, int* unfit_d, hipStream_t s);

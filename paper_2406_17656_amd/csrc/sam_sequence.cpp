@@ -32,14 +32,17 @@ struct sam_seq {
     // otherwise) and its plan
     DevBuf S_cp, S_ri;
     int64_t nnzS = 0;
-    std::vector<int64_t> level_nnz;
+    PatternLevels levels;          // structural level sizes, longest columns, column pointers
     sam_plan* plan = nullptr;
-    // replanning mode
+    // replanning mode: every level of the pattern is written into slots laid
+    // out like the structural level (lev_cp, p arrays of n+1), with its
+    // column lengths beside it; only the final S_k is compacted (Sk_cp/Sk_ri)
     DevBuf dyn;
+    DevBuf lev_cp;
     sam_plan dplan;                // views into dyn
     std::vector<int*> Sk_cp, Sk_ri;
-    int *counts = nullptr, *B_cp = nullptr, *B_ri = nullptr, *L_cp[2] = {nullptr, nullptr},
-        *L_ri[2] = {nullptr, nullptr}, *flags = nullptr;
+    int *B_ri = nullptr, *B_cnt = nullptr, *L_ri[2] = {nullptr, nullptr}, *L_cnt[2] = {nullptr, nullptr},
+        *F_ri = nullptr, *F_cnt = nullptr, *flags = nullptr;
     int64_t* off = nullptr;
     void *stemp = nullptr, *btemp = nullptr;
     double* D = nullptr;
@@ -61,38 +64,43 @@ void drop_graph(sam_seq* q) {
 }
 
 // Symbolic work for source k (replanning mode), then its numeric build.
+// A sparsified level is a subset of the structural one, column by column,
+// so each level is written straight into the structural layout (one launch
+// per level, no count pass); the final level is compacted by the positions
+// kernel after one scan of its lengths, and the gathered entries of column j
+// go to the structural offsets eoff[j] of the static plan.
 sam_status enqueue_replanned(sam_seq* q, int k, const double* vals, void* M, double* res2, hipStream_t s) {
     sam_ctx* ctx = q->ctx;
     const int n = q->n;
     const samk::SparsifySpec sp = to_sp(&q->spec);
     const int p = q->spec.power;
+    const int* lcp = (const int*)q->lev_cp.p;
+    auto level_cp = [&](int lev) { return lcp + (size_t)lev * (n + 1); };
     int* Scp = q->Sk_cp[k];
     int* Sri = q->Sk_ri[k];
-    // B = S(A~_k) plus the diagonal (written straight into S_k when p = 1)
-    int* bcp = p == 1 ? Scp : q->B_cp;
-    int* bri = p == 1 ? Sri : q->B_ri;
-    HIP_TRY(ctx, samk::sparsify_count(n, q->Ak_cp, q->Ak_ri, vals, sp, q->D, q->counts, s));
-    HIP_TRY(ctx, samk::scan_counts(q->counts, n, q->off, bcp, nullptr, q->stemp, s));
-    HIP_TRY(ctx, samk::sparsify_fill(n, q->Ak_cp, q->Ak_ri, vals, sp, q->D, bcp, bri, s));
-    const int* cur_cp = bcp;
-    const int* cur_ri = bri;
+    // B = S(A~_k) plus the diagonal, in the slots of the structural B
+    int* b_ri = p == 1 ? q->F_ri : q->B_ri;
+    int* b_cnt = p == 1 ? q->F_cnt : q->B_cnt;
+    HIP_TRY(ctx, samk::sparsify_slots(n, q->Ak_cp, q->Ak_ri, vals, sp, q->D, level_cp(0), b_ri, b_cnt, s));
+    const int* cur_ri = b_ri;
+    const int* cur_cnt = b_cnt;
     for (int lev = 1; lev < p; ++lev) {
-        int* dcp = lev == p - 1 ? Scp : q->L_cp[lev & 1];
-        int* dri = lev == p - 1 ? Sri : q->L_ri[lev & 1];
-        HIP_TRY(ctx, samk::expand_count(n, cur_cp, cur_ri, q->B_cp, q->B_ri, q->counts, nullptr, s));
-        HIP_TRY(ctx, samk::scan_counts(q->counts, n, q->off, dcp, nullptr, q->stemp, s));
-        HIP_TRY(ctx, samk::expand_fill(n, cur_cp, cur_ri, q->B_cp, q->B_ri, dcp, dri, s));
-        cur_cp = dcp;
+        int* dri = lev == p - 1 ? q->F_ri : q->L_ri[lev & 1];
+        int* dcnt = lev == p - 1 ? q->F_cnt : q->L_cnt[lev & 1];
+        HIP_TRY(ctx, samk::expand_slots(n, level_cp(lev - 1), cur_cnt, cur_ri, level_cp(0), q->B_cnt, q->B_ri,
+                                        level_cp(lev), dri, dcnt, q->levels.maxcol[(size_t)lev - 1], s));
         cur_ri = dri;
+        cur_cnt = dcnt;
     }
-    // plan of the column problems on S_k
+    // compact column pointers of S_k, then row sets, gather positions and the
+    // compact S_k in one pass, then the size buckets
+    HIP_TRY(ctx, samk::scan_counts(q->F_cnt, n, q->off, Scp, nullptr, q->stemp, s));
     sam_plan* pl = &q->dplan;
     pl->S_cp = Scp;
     pl->S_ri = Sri;
-    HIP_TRY(ctx, samk::plan_gather_count(n, Scp, Sri, q->Ak_cp, q->counts, s));
-    HIP_TRY(ctx, samk::scan_counts(q->counts, n, pl->eoff, nullptr, nullptr, q->stemp, s));
-    HIP_TRY(ctx, samk::plan_positions(n, Scp, Sri, q->Ak_cp, q->Ak_ri, q->A0_cp, q->A0_ri, pl->eoff, pl->nI,
-                                      pl->posA, pl->posB, s));
+    HIP_TRY(ctx, samk::plan_positions_slots(n, level_cp(p - 1), q->F_cnt, q->F_ri, Scp, Sri, q->Ak_cp, q->Ak_ri,
+                                            q->A0_cp, q->A0_ri, pl->eoff, pl->nI, pl->posA, pl->posB,
+                                            q->plan->max_cols, s));
     Combo& cb = pl->combo[q->prec][0];
     HIP_TRY(ctx, samk::bucket_sort(n, Scp, pl->nI, cb.tab, cb.queue, cb.bstart, nullptr, ctx->d_status, q->btemp, s));
     return run_numeric(pl, vals, q->A0_val, nullptr, 0.0, q->prec, 0, M, nullptr, res2, s);
@@ -154,36 +162,43 @@ sam_status sam_sequence_create(sam_ctx* ctx, const sam_csc* A0, const sam_csc* A
     structural.kind = SAM_SPARSIFY_NONE;
     sam_csc skel = *Ak_struct;
     skel.val = nullptr;
-    if ((st = compute_pattern(ctx, &skel, &structural, q->S_cp, q->S_ri, &q->nnzS, s, &q->level_nnz))) return bail(st);
+    q->levels.cp = &q->lev_cp;
+    if ((st = compute_pattern(ctx, &skel, &structural, q->S_cp, q->S_ri, &q->nnzS, s, &q->levels))) return bail(st);
     if ((st = sam_plan_create(ctx, &skel, A0, (const int*)q->S_cp.p, (const int*)q->S_ri.p, q->nnzS, &q->plan, stream)))
         return bail(st);
     if (!q->plan->combo[q->prec][0].ok)
         return bail(fail(ctx, SAM_ERR_UNSUPPORTED, "%s", q->plan->combo[q->prec][0].why.c_str()));
 
     if (q->replan) {
-        int64_t lev_max = 1;
-        for (size_t i = 0; i + 1 < q->level_nnz.size(); ++i) lev_max = std::max(lev_max, q->level_nnz[i]);
-        const int64_t nnzB = (int64_t)q->nnzA + n;
+        // slot sizes: the structural level sizes (level 0 is B, the last is S)
+        const int p = std::max(spec->power, 1);
+        if ((int)q->levels.nnz.size() < p) {   // n = 0
+            q->levels.nnz.resize((size_t)p, 0);
+            q->levels.maxcol.resize((size_t)p, 0);
+        }
+        auto lev_nnz = [&](int lev) { return std::max<int64_t>(q->levels.nnz[(size_t)lev], 1); };
+        int64_t mid_max = 1;
+        for (int lev = 1; lev + 1 < p; ++lev) mid_max = std::max(mid_max, lev_nnz(lev));
         const int64_t E = std::max<int64_t>(q->plan->E, 1);
         size_t need = 0;
         auto add = [&](size_t b) { need += align256(b); };
-        add((size_t)n * 4);                      // counts
         add((size_t)(n + 1) * 8);                // off
         add(samk::scan_temp_bytes(n));           // stemp
         add(samk::bucket_temp_bytes(n));         // btemp
         add((size_t)n * 8);                      // D
-        add((size_t)(n + 1) * 4);                // B_cp
-        add((size_t)nnzB * 4);                   // B_ri
+        add((size_t)lev_nnz(0) * 4);             // B slots
+        add((size_t)n * 4);                      // B lengths
         for (int i = 0; i < 2; ++i) {
-            add((size_t)(n + 1) * 4);
-            add((size_t)lev_max * 4);
+            add((size_t)mid_max * 4);            // intermediate level slots
+            add((size_t)n * 4);
         }
+        add((size_t)lev_nnz(p - 1) * 4);         // final level slots
+        add((size_t)n * 4);
         for (int k = 0; k < n_src; ++k) {
             add((size_t)(n + 1) * 4);
             add((size_t)std::max<int64_t>(q->nnzS, 1) * 4);
         }
         add((size_t)n * 4);                      // nI
-        add((size_t)(n + 1) * 8);                // eoff
         add((size_t)E);                          // posA
         add((size_t)std::max(q->nnzA0, 1));      // posB
         add((size_t)n * 4);                      // queue
@@ -195,17 +210,18 @@ sam_status sam_sequence_create(sam_ctx* ctx, const sam_csc* A0, const sam_csc* A
         if (he != hipSuccess) return bail(fail(ctx, SAM_ERR_NOMEM, "sequence buffers (%zu bytes): %s", need,
                                                hipGetErrorString(he)));
         Carve cv(q->dyn.p);
-        q->counts = cv.take<int>(n);
         q->off = cv.take<int64_t>(n + 1);
         q->stemp = cv.take<char>(samk::scan_temp_bytes(n));
         q->btemp = cv.take<char>(samk::bucket_temp_bytes(n));
         q->D = cv.take<double>(n);
-        q->B_cp = cv.take<int>(n + 1);
-        q->B_ri = cv.take<int>((size_t)nnzB);
+        q->B_ri = cv.take<int>((size_t)lev_nnz(0));
+        q->B_cnt = cv.take<int>(n);
         for (int i = 0; i < 2; ++i) {
-            q->L_cp[i] = cv.take<int>(n + 1);
-            q->L_ri[i] = cv.take<int>((size_t)lev_max);
+            q->L_ri[i] = cv.take<int>((size_t)mid_max);
+            q->L_cnt[i] = cv.take<int>(n);
         }
+        q->F_ri = cv.take<int>((size_t)lev_nnz(p - 1));
+        q->F_cnt = cv.take<int>(n);
         for (int k = 0; k < n_src; ++k) {
             q->Sk_cp.push_back(cv.take<int>(n + 1));
             q->Sk_ri.push_back(cv.take<int>((size_t)std::max<int64_t>(q->nnzS, 1)));
@@ -221,7 +237,7 @@ sam_status sam_sequence_create(sam_ctx* ctx, const sam_csc* A0, const sam_csc* A
         d.A0_cp = q->A0_cp;
         d.A0_ri = q->A0_ri;
         d.nI = cv.take<int>(n);
-        d.eoff = cv.take<int64_t>(n + 1);
+        d.eoff = q->plan->eoff;   // structural offsets of the gathered entries
         d.posA = cv.take<unsigned char>((size_t)E);
         d.posB = cv.take<unsigned char>((size_t)std::max(q->nnzA0, 1));
         Combo& cb = d.combo[q->prec][0];
@@ -262,6 +278,7 @@ sam_status sam_sequence_destroy(sam_seq* q) {
     release(q->S_cp);
     release(q->S_ri);
     release(q->dyn);
+    release(q->lev_cp);
     delete q;
     return SAM_OK;
 }

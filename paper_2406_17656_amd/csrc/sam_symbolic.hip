@@ -18,121 +18,151 @@ namespace samk {
 namespace {
 
 constexpr int kScanThreads = 256;
-constexpr int kScanItems = 4;
-constexpr int kScanTile = kScanThreads * kScanItems;
+constexpr int kScanItems = 8;
+constexpr int kScanTile = kScanThreads * kScanItems;   // 2048 values per tile
 
-__device__ inline int64_t block_exclusive_scan(int64_t v, int64_t* sh, int64_t* total) {
-    // Hillis-Steele over kScanThreads values in LDS
-    const int t = threadIdx.x;
-    sh[t] = v;
-    __syncthreads();
-    for (int d = 1; d < kScanThreads; d <<= 1) {
-        int64_t add = t >= d ? sh[t - d] : 0;
-        __syncthreads();
-        sh[t] += add;
-        __syncthreads();
+int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// Inclusive scan of one int64 per lane over the wave (shuffles through
+// ds_bpermute; lanes below the distance add nothing).
+__device__ inline int64_t wave_incl_scan(int64_t v) {
+    const int lane = wave_lane();
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int64_t u = __shfl_up(v, d, 64);
+        if (lane >= d) v += u;
     }
-    int64_t incl = sh[t];
-    *total = sh[kScanThreads - 1];
-    __syncthreads();
-    return incl - v;
+    return v;
 }
 
-// Scans in[0..N) where in[i] = i < n_in ? src[i] : 0 (the last virtual zero
-// gives the total at off[n_in]).
+__device__ inline int64_t block_sum_i64(int64_t v, int64_t* sh) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+    if (wave_lane() == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    int64_t t = 0;
+#pragma unroll
+    for (int w = 0; w < kScanThreads / 64; ++w) t += sh[w];
+    __syncthreads();
+    return t;
+}
+
+// Pass 1: the sum of every tile of kScanTile inputs (and the largest input,
+// when asked).
 template <typename Tin>
 __global__ void __launch_bounds__(kScanThreads)
-k_scan_local(const Tin* src, int64_t n_in, int64_t N, int64_t* out, int64_t* block_tot) {
-    __shared__ int64_t sh[kScanThreads];
+k_scan_tiles(const Tin* src, int64_t n_in, int64_t* tile_sum, int* maxval) {
+    __shared__ int64_t sh[kScanThreads / 64];
     const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    int64_t s = 0, mx = 0;
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) {
+        const int64_t idx = base + i;
+        const int64_t x = idx < n_in ? (int64_t)src[idx] : 0;
+        s += x;
+        mx = x > mx ? x : mx;
+    }
+    const int64_t t = block_sum_i64(s, sh);
+    if (threadIdx.x == 0) tile_sum[blockIdx.x] = t;
+    if (maxval) {
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) {
+            const int64_t o = __shfl_xor(mx, d, 64);
+            mx = o > mx ? o : mx;
+        }
+        if (wave_lane() == 0 && mx > 0) atomicMax(maxval, (int)(mx < INT_MAX ? mx : INT_MAX));
+    }
+}
+
+// Pass 2: every tile adds the sums of the tiles before it (read directly
+// when tile_off is null, else taken from tile_off) and scans its own inputs.
+template <typename Tin>
+__global__ void __launch_bounds__(kScanThreads)
+k_scan_apply(const Tin* src, int64_t n_in, int64_t N, const int64_t* tile_sum, const int64_t* tile_off,
+             int64_t* out, int* out32, int* overflow) {
+    __shared__ int64_t sh[kScanThreads / 64];
+    __shared__ int64_t wsum[kScanThreads / 64];
+    const int lane = wave_lane();
+    const int wv = threadIdx.x >> 6;
+    const int tile = blockIdx.x;
+    int64_t before_tile;
+    if (tile_off) {
+        before_tile = tile_off[tile];
+    } else {
+        int64_t acc = 0;
+        for (int t = threadIdx.x; t < tile; t += kScanThreads) acc += tile_sum[t];
+        before_tile = block_sum_i64(acc, sh);
+    }
+    const int64_t base = (int64_t)tile * kScanTile + (int64_t)threadIdx.x * kScanItems;
     int64_t v[kScanItems];
     int64_t s = 0;
 #pragma unroll
     for (int i = 0; i < kScanItems; ++i) {
-        int64_t idx = base + i;
-        v[i] = (idx < n_in) ? (int64_t)src[idx] : 0;
+        const int64_t idx = base + i;
+        v[i] = idx < n_in ? (int64_t)src[idx] : 0;
         s += v[i];
     }
-    int64_t tot;
-    int64_t pre = block_exclusive_scan(s, sh, &tot);
+    const int64_t wincl = wave_incl_scan(s);
+    if (lane == 63) wsum[wv] = wincl;
+    __syncthreads();
+    int64_t run = before_tile + wincl - s;
+#pragma unroll
+    for (int w = 0; w < kScanThreads / 64; ++w) run += w < wv ? wsum[w] : 0;
+    bool big = false;
 #pragma unroll
     for (int i = 0; i < kScanItems; ++i) {
-        int64_t idx = base + i;
-        if (idx < N) out[idx] = pre;
-        pre += v[i];
+        const int64_t idx = base + i;
+        if (idx < N) {
+            out[idx] = run;
+            if (out32) out32[idx] = (int)run;
+            big |= run > INT_MAX;
+        }
+        run += v[i];
     }
-    if (threadIdx.x == 0) block_tot[blockIdx.x] = tot;
+    if (overflow && big) atomicOr(overflow, 1);
 }
 
-__global__ void k_scan_add(int64_t* out, int64_t N, const int64_t* block_off) {
-    const int64_t i = (int64_t)blockIdx.x * kScanTile + threadIdx.x;
-    const int64_t add = block_off[blockIdx.x];
-#pragma unroll
-    for (int k = 0; k < kScanItems; ++k) {
-        int64_t idx = i + (int64_t)k * kScanThreads;
-        if (idx < N) out[idx] += add;
-    }
-}
+constexpr int64_t kDirectTiles = 1024;   // tiles summed directly by pass 2
 
-__global__ void k_to_i32(const int64_t* off, int64_t N, int* off32, int* overflow) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < N) {
-        int64_t v = off[i];
-        if (off32) off32[i] = (int)v;
-        if (v > INT_MAX && overflow) atomicOr(overflow, 1);
-    }
-}
+int64_t scan_tiles(int64_t N) { return std::max<int64_t>(ceil_div(N, kScanTile), 1); }
 
-int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+size_t scan_temp_rec(int64_t N) {
+    const int64_t nt = scan_tiles(N);
+    size_t b = (size_t)((nt * 8 + 255) / 256) * 256;
+    if (nt > kDirectTiles) b += (size_t)(((nt + 1) * 8 + 255) / 256) * 256 + scan_temp_rec(nt);
+    return b;
+}
 
 }  // namespace
 
-size_t scan_temp_bytes(int64_t n) {
-    int64_t N = n + 1;
-    size_t bytes = 0;
-    while (true) {
-        int64_t nb = ceil_div(N, kScanTile);
-        bytes += (size_t)(2 * nb + 1) * sizeof(int64_t);
-        if (nb <= 1) break;
-        N = nb;
-    }
-    return bytes + 256;
-}
+size_t scan_temp_bytes(int64_t n) { return scan_temp_rec(n + 1) + 256; }
 
-// Recursive three-phase scan.  Level buffers live in `temp`.
-static hipError_t scan_i64_levels(int64_t* out, int64_t N, int64_t* temp, hipStream_t s);
-
+// Reduce-then-scan: two launches while the tile count allows the direct
+// sum (2^21 values), recursing on the tile sums beyond that.  No state
+// survives between calls, so the temporary memory may hold anything.
 template <typename Tin>
-static hipError_t scan_any(const Tin* src, int64_t n_in, int64_t N, int64_t* out, int64_t* temp,
-                           hipStream_t s) {
-    const int64_t nb = ceil_div(N, kScanTile);
-    int64_t* tot = temp;
-    int64_t* totoff = temp + nb;
-    hipLaunchKernelGGL(k_scan_local<Tin>, dim3((unsigned)nb), dim3(kScanThreads), 0, s, src, n_in, N,
-                       out, tot);
-    if (nb > 1) {
-        // exclusive scan of the block totals (nb values, one virtual zero not needed)
-        hipError_t e = scan_any<int64_t>(tot, nb, nb, totoff, temp + 2 * nb + 1, s);
+static hipError_t scan_any(const Tin* src, int64_t n_in, int64_t N, int64_t* out, int* out32, int* overflow,
+                           int* maxval, void* temp, hipStream_t s) {
+    const int64_t nt = scan_tiles(N);
+    char* p = (char*)temp;
+    int64_t* tile_sum = (int64_t*)p;
+    p += ((nt * 8 + 255) / 256) * 256;
+    int64_t* tile_off = nullptr;
+    hipLaunchKernelGGL(k_scan_tiles<Tin>, dim3((unsigned)nt), dim3(kScanThreads), 0, s, src, n_in, tile_sum, maxval);
+    if (nt > kDirectTiles) {
+        tile_off = (int64_t*)p;
+        p += (((nt + 1) * 8 + 255) / 256) * 256;
+        hipError_t e = scan_any<int64_t>(tile_sum, nt, nt, tile_off, nullptr, nullptr, nullptr, p, s);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_scan_add, dim3((unsigned)nb), dim3(kScanThreads), 0, s, out, N, totoff);
     }
+    hipLaunchKernelGGL(k_scan_apply<Tin>, dim3((unsigned)nt), dim3(kScanThreads), 0, s, src, n_in, N, tile_sum,
+                       tile_off, out, out32, overflow);
     return hipGetLastError();
-}
-
-static hipError_t scan_i64_levels(int64_t* out, int64_t N, int64_t* temp, hipStream_t s) {
-    return scan_any<int64_t>(out, N, N, out, temp, s);
 }
 
 hipError_t scan_counts(const int* counts, int64_t n, int64_t* off, int* off32, int* overflow,
-                       void* temp, hipStream_t s) {
-    const int64_t N = n + 1;
-    hipError_t e = scan_any<int>(counts, n, N, off, (int64_t*)temp, s);
-    if (e != hipSuccess) return e;
-    if (off32 || overflow) {
-        hipLaunchKernelGGL(k_to_i32, dim3((unsigned)ceil_div(N, 256)), dim3(256), 0, s, off, N, off32,
-                           overflow);
-    }
-    return hipGetLastError();
+                       void* temp, hipStream_t s, int* maxcount) {
+    return scan_any<int>(counts, n, n + 1, off, off32, overflow, maxcount, temp, s);
 }
 
 // ----------------------------------------------------------------- checks
@@ -242,7 +272,7 @@ __global__ void k_sparsify(int n, const int* cp, const int* ri, const double* v,
         if (FILL) out_ri[o + cnt] = j;
         ++cnt;
     }
-    if (!FILL) counts[j] = cnt;
+    if (counts) counts[j] = cnt;   // the count pass, or a fill into bound-sized slots
 }
 
 hipError_t sparsify_count(int n, const int* cp, const int* ri, const double* v, SparsifySpec sp,
@@ -264,63 +294,81 @@ hipError_t sparsify_fill(int n, const int* cp, const int* ri, const double* v, S
     return hipGetLastError();
 }
 
+hipError_t sparsify_slots(int n, const int* cp, const int* ri, const double* v, SparsifySpec sp,
+                          double* dscratch, const int* slot_cp, int* slot_ri, int* counts, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const unsigned nb = (unsigned)ceil_div(n, 256);
+    if (sp.kind == 1) hipLaunchKernelGGL(k_diag_scale, dim3(nb), dim3(256), 0, s, n, cp, ri, v, dscratch);
+    hipLaunchKernelGGL(k_sparsify<true>, dim3(nb), dim3(256), 0, s, n, cp, ri, v, sp, dscratch, counts,
+                       slot_cp, slot_ri);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------- row-set bitmaps
 //
-// One 16-lane DPP row per column (four columns per wave).  The candidates of
-// column j are the rows of Q(:, l) for l in P(:, j); lane g of the group owns
-// the lists l = P(:, j)[g], P(:, j)[g+16], ...  The window of candidate rows
-// is swept in chunks of kChunk rows: each chunk gets an LDS bitmap (four
-// 32-bit words per lane), set with ds_or, counted with popcount and a row
-// prefix scan.  After a chunk the sweep jumps to the smallest candidate
-// beyond it, so only occupied chunks cost anything, whatever the bandwidth.
+// A group of GS lanes (8 or 16: eight or four columns per wave) per column.  The
+// candidates of column j are the rows of Q(:, l) for l in P(:, j); lane g of
+// the group owns the lists l = P(:, j)[g], P(:, j)[g + GS], ...  The window
+// of candidate rows is swept in chunks of kChunk rows: each chunk gets an
+// LDS bitmap (128 words per column), set with ds_or, counted with popcount
+// and a prefix scan over the group.  After a chunk the sweep jumps to the
+// smallest candidate beyond it, so only occupied chunks cost anything,
+// whatever the bandwidth.
 
-constexpr int kGS = 16;                   // lanes per column
-constexpr int kChunkWords = 64;           // 4 words per lane
-constexpr int kChunk = kChunkWords * 32;  // 2048 rows
+constexpr int kChunkWords = 128;
+constexpr int kChunk = kChunkWords * 32;  // 4096 rows
 constexpr int kSymThreads = 256;
-constexpr int kGroupsPerBlock = kSymThreads / kGS;
+constexpr int kListLen = 8;               // entries per list held in registers
 
 template <int CTRL>
 __device__ inline int dppi(int v) { return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false); }
+template <int CTRL>
+__device__ inline int dppb(int v) { return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, true); }
 
-// sums / minima over the 16 lanes of a row (all lanes get the result)
-__device__ inline int row_sum_i(int v) {
-    v += __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, true);
-    v += __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, true);
-    v += __builtin_amdgcn_update_dpp(0, v, 0x141, 0xF, 0xF, true);
-    v += __builtin_amdgcn_update_dpp(0, v, 0x140, 0xF, 0xF, true);
+// sums / minima / maxima over the GS lanes of a group (all lanes get the
+// result): quad exchanges, then the half-row mirror, then (GS = 16) the row
+// mirror
+template <int GS>
+__device__ inline int grp_sum(int v) {
+    v += dppb<0xB1>(v);
+    v += dppb<0x4E>(v);
+    v += dppb<0x141>(v);
+    if (GS == 16) v += dppb<0x140>(v);
     return v;
 }
-__device__ inline int row_min_i(int v) {
-    v = min(v, __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, true));
-    v = min(v, __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, true));
-    v = min(v, __builtin_amdgcn_update_dpp(0, v, 0x141, 0xF, 0xF, true));
-    v = min(v, __builtin_amdgcn_update_dpp(0, v, 0x140, 0xF, 0xF, true));
+template <int GS>
+__device__ inline int grp_min(int v) {
+    v = min(v, dppb<0xB1>(v));
+    v = min(v, dppb<0x4E>(v));
+    v = min(v, dppb<0x141>(v));
+    if (GS == 16) v = min(v, dppb<0x140>(v));
     return v;
 }
-// exclusive prefix sum inside the row (Kogge-Stone with row_shr; lanes whose
-// source lies before the row start add 0)
-__device__ inline int row_excl_scan_i(int v) {
-    int x = v;
-    x += dppi<0x111>(x);
-    x += dppi<0x112>(x);
-    x += dppi<0x114>(x);
-    x += dppi<0x118>(x);
+template <int GS>
+__device__ inline int grp_max(int v) {
+    v = max(v, dppb<0xB1>(v));
+    v = max(v, dppb<0x4E>(v));
+    v = max(v, dppb<0x141>(v));
+    if (GS == 16) v = max(v, dppb<0x140>(v));
+    return v;
+}
+// exclusive prefix sum inside the group (Kogge-Stone with row_shr; a lane
+// whose source lies before its group's first lane adds 0)
+template <int GS>
+__device__ inline int grp_excl_scan(int v) {
+    const int p = (int)(threadIdx.x & (GS - 1));
+    int x = v, y;
+    y = dppi<0x111>(x);
+    x += (GS == 16 || p >= 1) ? y : 0;
+    y = dppi<0x112>(x);
+    x += (GS == 16 || p >= 2) ? y : 0;
+    y = dppi<0x114>(x);
+    x += (GS == 16 || p >= 4) ? y : 0;
+    if (GS == 16) x += dppi<0x118>(x);
     return x - v;
 }
 
 enum { kModeCount = 0, kModeFill = 1, kModePositions = 2 };
-
-constexpr int kListRounds = 2;   // lists per lane held in registers (32 per column)
-constexpr int kListLen = 8;      // entries per list held in registers
-
-__device__ inline int row_max_i(int v) {
-    v = max(v, __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, true));
-    v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, true));
-    v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x141, 0xF, 0xF, true));
-    v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x140, 0xF, 0xF, true));
-    return v;
-}
 
 // Rank of row d (relative to the chunk base) inside the chunk's bitmap.
 __device__ inline int chunk_rank(const unsigned* bm, const int* wpre, int d) {
@@ -328,49 +376,73 @@ __device__ inline int chunk_rank(const unsigned* bm, const int* wpre, int d) {
     return wpre[w] + __popc(bm[w] & ((1u << (d & 31)) - 1u));
 }
 
-template <int MODE>
+// Operands of the union kernel.  A list set X is (X_cp, X_cnt, X_ri): list l
+// holds X_ri[X_cp[l] .. X_cp[l] + len), len = X_cnt[l] when X_cnt is given
+// (lists in bound-sized slots), X_cp[l+1] - X_cp[l] otherwise.
+struct UnionArgs {
+    int n;
+    const int *P_cp, *P_cnt, *P_ri;       // the lists of column j: P(:, j)
+    const int *Q_cp, *Q_cnt, *Q_ri;       // the candidates of list l: Q(:, l)
+    int* counts;                          // |union| per column (may be null in fill mode)
+    const int* out_cp;                    // fill: where column j's union goes
+    int* out_ri;
+    const int64_t* eoff;                  // positions: start of column j's gathered entries
+    unsigned char* posA;
+    const int *A0_cp, *A0_ri;
+    unsigned char* posB;
+    const int* cP_cp;                     // positions: compact copy of P (may be null)
+    int* cP_ri;
+    int* bad;                             // count mode: earliest column with a bad index
+};
+
+// ROUNDS lists per lane (GS * ROUNDS per column) and their first kListLen
+// rows live in registers; longer columns or lists take the memory loops.
+template <int MODE, int GS, int ROUNDS>
 __global__ void __launch_bounds__(kSymThreads)
-k_union(int n, const int* P_cp, const int* P_ri, const int* Q_cp, const int* Q_ri, int* counts,
-        const int* out_cp, int* out_ri, const int64_t* eoff, unsigned char* posA, const int* A0_cp,
-        const int* A0_ri, unsigned char* posB, int* bad) {
-    __shared__ unsigned bm_all[kGroupsPerBlock][kChunkWords];
-    __shared__ int pre_all[kGroupsPerBlock][kChunkWords];
-    const int grp = threadIdx.x / kGS;
-    const int g = threadIdx.x % kGS;
+k_union(UnionArgs a) {
+    constexpr int kGroups = kSymThreads / GS;
+    constexpr int kWPL = kChunkWords / GS;   // bitmap words per lane
+    __shared__ unsigned bm_all[kGroups][kChunkWords];
+    __shared__ int pre_all[kGroups][kChunkWords];
+    const int n = a.n;
+    const int grp = threadIdx.x / GS;
+    const int g = threadIdx.x % GS;
     unsigned* bm = bm_all[grp];
     int* wpre = pre_all[grp];
-    const int stride = gridDim.x * kGroupsPerBlock;
-    for (int j = blockIdx.x * kGroupsPerBlock + grp; j < n; j += stride) {
-        const int pa = P_cp[j], pb = P_cp[j + 1];
-        // Lists t = pa + g + 16 u of this lane, first kListLen rows of each in
-        // registers (all loads independent); `big` marks columns that need the
-        // memory loops (more than 32 lists, or a list longer than kListLen).
-        int qa[kListRounds], len[kListRounds], lofs[kListRounds];
-        int rows[kListRounds][kListLen];
-        int big = (pb - pa > kGS * kListRounds) ? 1 : 0;
+    unsigned* mine = bm + g * kWPL;
+    const int stride = gridDim.x * kGroups;
+    auto q_len = [&](int l) { return a.Q_cnt ? a.Q_cnt[l] : a.Q_cp[l + 1] - a.Q_cp[l]; };
+    for (int j = blockIdx.x * kGroups + grp; j < n; j += stride) {
+        const int pa = a.P_cp[j];
+        const int pb = a.P_cnt ? pa + a.P_cnt[j] : a.P_cp[j + 1];
+        // lists t = pa + g + GS u of this lane (all loads independent); `big`
+        // marks columns that need the memory loops
+        int qa[ROUNDS], len[ROUNDS], lofs[ROUNDS];
+        int rows[ROUNDS][kListLen];
+        int big = (pb - pa > GS * ROUNDS) ? 1 : 0;
         int lo = INT_MAX, carry = 0;
 #pragma unroll
-        for (int u = 0; u < kListRounds; ++u) {
-            const int t = pa + g + u * kGS;
+        for (int u = 0; u < ROUNDS; ++u) {
+            const int t = pa + g + u * GS;
             int l = -1;
             if (t < pb) {
-                l = P_ri[t];
+                l = a.P_ri[t];
                 if (l < 0 || l >= n) {
-                    if (bad) atomicMin(bad, j);
+                    if (a.bad) atomicMin(a.bad, j);
                     l = -1;
                 }
             }
-            qa[u] = l >= 0 ? Q_cp[l] : 0;
-            len[u] = l >= 0 ? Q_cp[l + 1] - qa[u] : 0;
+            qa[u] = l >= 0 ? a.Q_cp[l] : 0;
+            len[u] = l >= 0 ? q_len(l) : 0;
             big |= len[u] > kListLen ? 1 : 0;
             // flat offset of this list among the column's gathered entries
-            lofs[u] = carry + row_excl_scan_i(len[u]);
-            carry += row_sum_i(len[u]);
+            lofs[u] = carry + grp_excl_scan<GS>(len[u]);
+            carry += grp_sum<GS>(len[u]);
             if (len[u] > 0) {
 #pragma unroll
                 for (int e = 0; e < kListLen; ++e) {
                     const bool ok = e < len[u];
-                    const int r = Q_ri[qa[u] + (ok ? e : 0)];  // clamped: always in bounds
+                    const int r = a.Q_ri[qa[u] + (ok ? e : 0)];  // clamped: always in bounds
                     rows[u][e] = ok ? r : INT_MAX;
                 }
             } else {
@@ -379,27 +451,32 @@ k_union(int n, const int* P_cp, const int* P_ri, const int* Q_cp, const int* Q_r
             }
             lo = min(lo, rows[u][0]);
         }
-        big = row_max_i(big);
+        big = grp_max<GS>(big);
         if (big) {  // heads of every list, from memory
             lo = INT_MAX;
-            for (int t = pa + g; t < pb; t += kGS) {
-                const int l = P_ri[t];
-                if (l >= 0 && l < n && Q_cp[l + 1] > Q_cp[l]) lo = min(lo, Q_ri[Q_cp[l]]);
+            for (int t = pa + g; t < pb; t += GS) {
+                const int l = a.P_ri[t];
+                if (l >= 0 && l < n && q_len(l) > 0) lo = min(lo, a.Q_ri[a.Q_cp[l]]);
             }
         }
-        lo = row_min_i(lo);
-        if (MODE == kModePositions)
-            for (int e = A0_cp[j] + g; e < A0_cp[j + 1]; e += kGS) posB[e] = 0xFF;
+        lo = grp_min<GS>(lo);
+        if (MODE == kModePositions) {
+            for (int e = a.A0_cp[j] + g; e < a.A0_cp[j + 1]; e += GS) a.posB[e] = 0xFF;
+            if (a.cP_ri) {
+                const int oc = a.cP_cp[j] - pa;
+                for (int t = pa + g; t < pb; t += GS) a.cP_ri[oc + t] = a.P_ri[t];
+            }
+        }
         int running = 0;
         int base = lo;
         while (base != INT_MAX) {
 #pragma unroll
-            for (int w = 0; w < 4; ++w) bm[g * 4 + w] = 0u;
+            for (int w = 0; w < kWPL; ++w) mine[w] = 0u;
             wave_sync();
             int next = INT_MAX;
             if (!big) {
 #pragma unroll
-                for (int u = 0; u < kListRounds; ++u)
+                for (int u = 0; u < ROUNDS; ++u)
 #pragma unroll
                     for (int e = 0; e < kListLen; ++e) {
                         const int r = rows[u][e];
@@ -408,11 +485,12 @@ k_union(int n, const int* P_cp, const int* P_ri, const int* Q_cp, const int* Q_r
                         if (d >= kChunk) next = min(next, r);
                     }
             } else {
-                for (int t = pa + g; t < pb; t += kGS) {
-                    const int l = P_ri[t];
+                for (int t = pa + g; t < pb; t += GS) {
+                    const int l = a.P_ri[t];
                     if (l < 0 || l >= n) continue;
-                    for (int f = Q_cp[l]; f < Q_cp[l + 1]; ++f) {
-                        const int r = Q_ri[f];
+                    const int f0 = a.Q_cp[l], f1 = f0 + q_len(l);
+                    for (int f = f0; f < f1; ++f) {
+                        const int r = a.Q_ri[f];
                         const int d = r - base;
                         if (d >= 0 && d < kChunk) atomicOr(&bm[d >> 5], 1u << (d & 31));
                         if (d >= kChunk) next = min(next, r);
@@ -420,93 +498,130 @@ k_union(int n, const int* P_cp, const int* P_ri, const int* Q_cp, const int* Q_r
                 }
             }
             wave_sync();
+            unsigned wd[kWPL];
             int c = 0;
 #pragma unroll
-            for (int w = 0; w < 4; ++w) c += __popc(bm[g * 4 + w]);
-            const int pre = row_excl_scan_i(c);
-            const int tot = row_sum_i(c);
-            if (MODE != kModeCount) {
+            for (int w = 0; w < kWPL; ++w) {
+                wd[w] = mine[w];
+                c += __popc(wd[w]);
+            }
+            const int pre = grp_excl_scan<GS>(c);
+            const int tot = grp_sum<GS>(c);
+            if (MODE == kModePositions) {
                 int run = running + pre;
 #pragma unroll
-                for (int w = 0; w < 4; ++w) {
-                    wpre[g * 4 + w] = run;
-                    run += __popc(bm[g * 4 + w]);
+                for (int w = 0; w < kWPL; ++w) {
+                    wpre[g * kWPL + w] = run;
+                    run += __popc(wd[w]);
                 }
             }
-            wave_sync();
             if (MODE == kModeFill) {
-                int o = out_cp[j] + running + pre;
+                int o = a.out_cp[j] + running + pre;
 #pragma unroll
-                for (int w = 0; w < 4; ++w) {
-                    unsigned x = bm[g * 4 + w];
+                for (int w = 0; w < kWPL; ++w) {
+                    unsigned x = wd[w];
                     while (x) {
                         const int b = __ffs(x) - 1;
                         x &= x - 1;
-                        out_ri[o++] = base + ((g * 4 + w) << 5) + b;
+                        a.out_ri[o++] = base + ((g * kWPL + w) << 5) + b;
                     }
                 }
             }
             if (MODE == kModePositions) {
+                wave_sync();
                 // ranks of the gathered A_k entries, in the order of the lists
-                unsigned char* pj = posA + eoff[j];
+                unsigned char* pj = a.posA + a.eoff[j];
                 if (!big) {
 #pragma unroll
-                    for (int u = 0; u < kListRounds; ++u)
+                    for (int u = 0; u < ROUNDS; ++u)
 #pragma unroll
                         for (int e = 0; e < kListLen; ++e) {
                             const int d = rows[u][e] - base;
-                            if (d >= 0 && d < kChunk) pj[lofs[u] + e] = (unsigned char)min(chunk_rank(bm, wpre, d), 255);
+                            if (d >= 0 && d < kChunk)
+                                pj[lofs[u] + e] = (unsigned char)min(chunk_rank(bm, wpre, d), 255);
                         }
                 } else {
                     int cy = 0;
-                    for (int t0 = pa; t0 < pb; t0 += kGS) {
+                    for (int t0 = pa; t0 < pb; t0 += GS) {
                         const int t = t0 + g;
                         int l = -1, ln = 0;
                         if (t < pb) {
-                            l = P_ri[t];
-                            if (l >= 0 && l < n) ln = Q_cp[l + 1] - Q_cp[l];
+                            l = a.P_ri[t];
+                            if (l >= 0 && l < n) ln = q_len(l);
                         }
-                        const int off = cy + row_excl_scan_i(ln);
+                        const int off = cy + grp_excl_scan<GS>(ln);
                         for (int f = 0; f < ln; ++f) {
-                            const int d = Q_ri[Q_cp[l] + f] - base;
+                            const int d = a.Q_ri[a.Q_cp[l] + f] - base;
                             if (d >= 0 && d < kChunk) pj[off + f] = (unsigned char)min(chunk_rank(bm, wpre, d), 255);
                         }
-                        cy += row_sum_i(ln);
+                        cy += grp_sum<GS>(ln);
                     }
                 }
-                for (int e = A0_cp[j] + g; e < A0_cp[j + 1]; e += kGS) {
-                    const int d = A0_ri[e] - base;
+                for (int e = a.A0_cp[j] + g; e < a.A0_cp[j + 1]; e += GS) {
+                    const int d = a.A0_ri[e] - base;
                     if (d >= 0 && d < kChunk && ((bm[d >> 5] >> (d & 31)) & 1u))
-                        posB[e] = (unsigned char)min(chunk_rank(bm, wpre, d), 254);
+                        a.posB[e] = (unsigned char)min(chunk_rank(bm, wpre, d), 254);
                 }
             }
             running += tot;
-            base = row_min_i(next);
+            base = grp_min<GS>(next);
             wave_sync();
         }
-        if (g == 0 && MODE != kModeFill) counts[j] = running;  // |union| (= |I_j| for positions)
+        if (g == 0 && a.counts) a.counts[j] = running;  // |union| (= |I_j| for positions)
     }
 }
 
-static unsigned union_grid(int n) {
-    int64_t blocks = ceil_div(n, kGroupsPerBlock);
-    return (unsigned)std::min<int64_t>(blocks, 256 * 32);
+// One list per lane while the columns allow (8 lanes per column up to 8
+// lists, 16 up to 16), then two per lane (32 lists in registers); beyond
+// that the memory loops.  max_lists <= 0: unknown.
+template <int MODE>
+static hipError_t launch_union(const UnionArgs& a, int max_lists, hipStream_t s) {
+    auto grid = [&](int gs) {
+        return dim3((unsigned)std::min<int64_t>(ceil_div(a.n, kSymThreads / gs), 256 * 32));
+    };
+    const dim3 block(kSymThreads);
+    if (max_lists > 0 && max_lists <= 8)
+        hipLaunchKernelGGL((k_union<MODE, 8, 1>), grid(8), block, 0, s, a);
+    else if (max_lists > 0 && max_lists <= 16)
+        hipLaunchKernelGGL((k_union<MODE, 16, 1>), grid(16), block, 0, s, a);
+    else
+        hipLaunchKernelGGL((k_union<MODE, 16, 2>), grid(16), block, 0, s, a);
+    return hipGetLastError();
+}
+
+static UnionArgs union_args(int n) {
+    UnionArgs a{};
+    a.n = n;
+    return a;
 }
 
 hipError_t expand_count(int n, const int* P_cp, const int* P_ri, const int* Q_cp, const int* Q_ri,
-                        int* counts, int* bad, hipStream_t s) {
+                        int* counts, int* bad, int max_lists, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_union<kModeCount>, dim3(union_grid(n)), dim3(kSymThreads), 0, s, n, P_cp, P_ri, Q_cp,
-                       Q_ri, counts, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, bad);
-    return hipGetLastError();
+    UnionArgs a = union_args(n);
+    a.P_cp = P_cp; a.P_ri = P_ri; a.Q_cp = Q_cp; a.Q_ri = Q_ri;
+    a.counts = counts; a.bad = bad;
+    return launch_union<kModeCount>(a, max_lists, s);
 }
 
 hipError_t expand_fill(int n, const int* P_cp, const int* P_ri, const int* Q_cp, const int* Q_ri,
-                       const int* out_cp, int* out_ri, hipStream_t s) {
+                       const int* out_cp, int* out_ri, int max_lists, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_union<kModeFill>, dim3(union_grid(n)), dim3(kSymThreads), 0, s, n, P_cp, P_ri, Q_cp,
-                       Q_ri, nullptr, out_cp, out_ri, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr);
-    return hipGetLastError();
+    UnionArgs a = union_args(n);
+    a.P_cp = P_cp; a.P_ri = P_ri; a.Q_cp = Q_cp; a.Q_ri = Q_ri;
+    a.out_cp = out_cp; a.out_ri = out_ri;
+    return launch_union<kModeFill>(a, max_lists, s);
+}
+
+hipError_t expand_slots(int n, const int* P_cp, const int* P_cnt, const int* P_ri, const int* Q_cp,
+                        const int* Q_cnt, const int* Q_ri, const int* slot_cp, int* slot_ri, int* counts,
+                        int max_lists, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    UnionArgs a = union_args(n);
+    a.P_cp = P_cp; a.P_cnt = P_cnt; a.P_ri = P_ri;
+    a.Q_cp = Q_cp; a.Q_cnt = Q_cnt; a.Q_ri = Q_ri;
+    a.out_cp = slot_cp; a.out_ri = slot_ri; a.counts = counts;
+    return launch_union<kModeFill>(a, max_lists, s);
 }
 
 // ------------------------------------------------------------------ plan
@@ -536,11 +651,22 @@ hipError_t plan_gather_count(int n, const int* S_cp, const int* S_ri, const int*
 // not in I_j).  nI[j] = |I_j|.
 hipError_t plan_positions(int n, const int* S_cp, const int* S_ri, const int* Ak_cp, const int* Ak_ri,
                           const int* A0_cp, const int* A0_ri, const int64_t* eoff, int* nI,
-                          unsigned char* posA, unsigned char* posB, hipStream_t s) {
+                          unsigned char* posA, unsigned char* posB, int max_lists, hipStream_t s) {
+    return plan_positions_slots(n, S_cp, nullptr, S_ri, nullptr, nullptr, Ak_cp, Ak_ri, A0_cp, A0_ri, eoff, nI,
+                                posA, posB, max_lists, s);
+}
+
+hipError_t plan_positions_slots(int n, const int* S_cp, const int* S_cnt, const int* S_ri, const int* cS_cp,
+                                int* cS_ri, const int* Ak_cp, const int* Ak_ri, const int* A0_cp,
+                                const int* A0_ri, const int64_t* eoff, int* nI, unsigned char* posA,
+                                unsigned char* posB, int max_lists, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_union<kModePositions>, dim3(union_grid(n)), dim3(kSymThreads), 0, s, n, S_cp, S_ri,
-                       Ak_cp, Ak_ri, nI, nullptr, nullptr, eoff, posA, A0_cp, A0_ri, posB, nullptr);
-    return hipGetLastError();
+    UnionArgs a = union_args(n);
+    a.P_cp = S_cp; a.P_cnt = S_cnt; a.P_ri = S_ri;
+    a.Q_cp = Ak_cp; a.Q_ri = Ak_ri;
+    a.counts = nI; a.eoff = eoff; a.posA = posA; a.A0_cp = A0_cp; a.A0_ri = A0_ri; a.posB = posB;
+    a.cP_cp = cS_cp; a.cP_ri = cS_ri;
+    return launch_union<kModePositions>(a, max_lists, s);
 }
 
 // --------------------------------------------------------------- buckets
@@ -554,16 +680,30 @@ __device__ inline int bucket_of(int nI, int nJ, const BucketTable& tab) {
     return -1;
 }
 
-// hist is bucket-major: hist[b * nblocks + block]
+// The columns are cut into at most kBucketBlocks contiguous ranges (a
+// multiple of 256 columns each); pass 1 counts every range's columns per
+// bucket (hist is bucket-major: hist[b * nblk + blk]), pass 2 lets every
+// range sum the counts before it (all ranges of earlier buckets, earlier
+// ranges of its own bucket) and scatter its columns in column order.
+constexpr int kBucketBlocks = 1024;
+
+__host__ __device__ inline int64_t range_len(int n) {
+    const int64_t per = ((int64_t)n + kBucketBlocks * kBucketThreads - 1) / ((int64_t)kBucketBlocks * kBucketThreads);
+    return (per > 8 ? per : 8) * kBucketThreads;
+}
+
 __global__ void __launch_bounds__(kBucketThreads)
 k_bucket_hist(int n, const int* S_cp, const int* nI, BucketTable tab, int* hist, int* unfit,
               unsigned long long* status) {
     __shared__ int h[kMaxBuckets];
     if (threadIdx.x < kMaxBuckets) h[threadIdx.x] = 0;
     __syncthreads();
-    const int j = blockIdx.x * kBucketThreads + threadIdx.x;
-    if (j < n) {
-        int b = bucket_of(nI[j], S_cp[j + 1] - S_cp[j], tab);
+    const int64_t len = range_len(n);
+    const int64_t j0 = (int64_t)blockIdx.x * len;
+    const int64_t j1 = std::min<int64_t>(j0 + len, n);
+    for (int64_t jj = j0 + threadIdx.x; jj < j1; jj += kBucketThreads) {
+        const int j = (int)jj;
+        const int b = bucket_of(nI[j], S_cp[j + 1] - S_cp[j], tab);
         if (b >= 0) {
             atomicAdd(&h[b], 1);
         } else {
@@ -576,56 +716,83 @@ k_bucket_hist(int n, const int* S_cp, const int* nI, BucketTable tab, int* hist,
 }
 
 __global__ void __launch_bounds__(kBucketThreads)
-k_bucket_scatter(int n, const int* S_cp, const int* nI, BucketTable tab, const int64_t* off,
-                 int* queue) {
+k_bucket_scatter(int n, const int* S_cp, const int* nI, BucketTable tab, const int* hist, int* queue,
+                 int* bstart) {
+    __shared__ int tot[kMaxBuckets], pre[kMaxBuckets], base[kMaxBuckets + 1];
     __shared__ int wcount[kBucketThreads / 64][kMaxBuckets];
-    const int j = blockIdx.x * kBucketThreads + threadIdx.x;
-    const int wv = threadIdx.x >> 6;
-    const int lane = wave_lane();
-    int b = -1;
-    if (j < n) b = bucket_of(nI[j], S_cp[j + 1] - S_cp[j], tab);
-    int my_rank = 0;
-    for (int k = 0; k < tab.nb; ++k) {
-        unsigned long long m = __ballot(b == k);
-        if (b == k) my_rank = __popcll(m & ((1ull << lane) - 1ull));
-        if (lane == 0) wcount[wv][k] = __popcll(m);
+    const int nblk = gridDim.x;
+    const int me = blockIdx.x;
+    if (threadIdx.x < kMaxBuckets) tot[threadIdx.x] = pre[threadIdx.x] = 0;
+    __syncthreads();
+    {
+        const int b = threadIdx.x % kMaxBuckets;
+        int t = 0, p = 0;
+        if (b < tab.nb)
+            for (int blk = threadIdx.x / kMaxBuckets; blk < nblk; blk += kBucketThreads / kMaxBuckets) {
+                const int c = hist[b * nblk + blk];
+                t += c;
+                p += blk < me ? c : 0;
+            }
+        if (t) atomicAdd(&tot[b], t);
+        if (p) atomicAdd(&pre[b], p);
     }
     __syncthreads();
-    if (b >= 0) {
-        int r = my_rank;
-        for (int w = 0; w < wv; ++w) r += wcount[w][b];
-        queue[off[(int64_t)b * gridDim.x + blockIdx.x] + r] = j;
+    if (threadIdx.x == 0) {
+        int run = 0;
+        for (int b = 0; b < tab.nb; ++b) {
+            if (me == 0) bstart[b] = run;
+            base[b] = run + pre[b];
+            run += tot[b];
+        }
+        if (me == 0) bstart[tab.nb] = run;
+    }
+    __syncthreads();
+    const int wv = threadIdx.x >> 6;
+    const int lane = wave_lane();
+    const int64_t len = range_len(n);
+    const int64_t j0 = (int64_t)me * len;
+    const int64_t j1 = std::min<int64_t>(j0 + len, n);
+    for (int64_t c0 = j0; c0 < j1; c0 += kBucketThreads) {
+        const int64_t jj = c0 + threadIdx.x;
+        int b = -1;
+        if (jj < j1) b = bucket_of(nI[jj], S_cp[jj + 1] - S_cp[jj], tab);
+        int my_rank = 0;
+        for (int k = 0; k < tab.nb; ++k) {
+            const unsigned long long m = __ballot(b == k);
+            if (b == k) my_rank = __popcll(m & ((1ull << lane) - 1ull));
+            if (lane == 0) wcount[wv][k] = __popcll(m);
+        }
+        __syncthreads();
+        if (b >= 0) {
+            int r = base[b] + my_rank;
+            for (int w = 0; w < wv; ++w) r += wcount[w][b];
+            queue[r] = (int)jj;
+        }
+        __syncthreads();
+        if (threadIdx.x < tab.nb) {
+            int c = 0;
+            for (int w = 0; w < kBucketThreads / 64; ++w) c += wcount[w][threadIdx.x];
+            base[threadIdx.x] += c;
+        }
+        __syncthreads();
     }
 }
 
-__global__ void k_bucket_starts(int nb, int nblocks, const int64_t* off, int* bstart) {
-    const int b = threadIdx.x;
-    if (b <= nb) bstart[b] = (int)off[(int64_t)b * nblocks];
-}
+static int bucket_blocks(int n) { return (int)ceil_div(std::max(n, 1), range_len(n)); }
 
 size_t bucket_temp_bytes(int n) {
-    int64_t nblocks = ceil_div(std::max(n, 1), kBucketThreads);
-    int64_t cells = nblocks * kMaxBuckets;
-    return (size_t)cells * sizeof(int) + (size_t)(cells + 1) * sizeof(int64_t) + scan_temp_bytes(cells) + 512;
+    return (size_t)kBucketBlocks * kMaxBuckets * sizeof(int) + 512;
 }
 
 hipError_t bucket_sort(int n, const int* S_cp, const int* nI, BucketTable tab, int* queue, int* bstart,
                        int* unfit, unsigned long long* status, void* temp, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    const int nblocks = (int)ceil_div(n, kBucketThreads);
-    const int64_t cells = (int64_t)nblocks * tab.nb;
-    char* p = (char*)temp;
-    int* hist = (int*)p;
-    p += (((size_t)nblocks * kMaxBuckets * sizeof(int)) + 255) / 256 * 256;
-    int64_t* off = (int64_t*)p;
-    p += (((size_t)(nblocks * kMaxBuckets + 1) * sizeof(int64_t)) + 255) / 256 * 256;
-    hipLaunchKernelGGL(k_bucket_hist, dim3(nblocks), dim3(kBucketThreads), 0, s, n, S_cp, nI, tab, hist,
-                       unfit, status);
-    hipError_t e = scan_counts(hist, cells, off, nullptr, nullptr, p, s);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_bucket_scatter, dim3(nblocks), dim3(kBucketThreads), 0, s, n, S_cp, nI, tab, off,
-                       queue);
-    hipLaunchKernelGGL(k_bucket_starts, dim3(1), dim3(kMaxBuckets + 1), 0, s, tab.nb, nblocks, off, bstart);
+    const int nblk = bucket_blocks(n);
+    int* hist = (int*)temp;
+    hipLaunchKernelGGL(k_bucket_hist, dim3(nblk), dim3(kBucketThreads), 0, s, n, S_cp, nI, tab, hist, unfit,
+                       status);
+    hipLaunchKernelGGL(k_bucket_scatter, dim3(nblk), dim3(kBucketThreads), 0, s, n, S_cp, nI, tab, hist, queue,
+                       bstart);
     return hipGetLastError();
 }
 
