@@ -83,6 +83,9 @@ sam_status sam_backward(sam_plan* plan, const double* Ak_val, const double* A0_v
 
     samk::NumericArgs a{};
     a.n = plan->n;
+    a.nnzA = (uint32_t)plan->nnzA;
+    a.nnzA0 = (uint32_t)plan->nnzA0;
+    a.E = (uint32_t)plan->E;
     a.Ak_cp = plan->Ak_cp;
     a.Ak_v = Ak_val;
     a.A0_cp = plan->A0_cp;

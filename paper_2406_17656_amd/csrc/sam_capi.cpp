@@ -288,6 +288,9 @@ sam_status run_numeric(sam_plan* pl, const double* Ak_val, const double* A0_val,
     if (!cb.ok) return fail(ctx, SAM_ERR_UNSUPPORTED, "%s", cb.why.c_str());
     NumericArgs a{};
     a.n = pl->n;
+    a.nnzA = (uint32_t)pl->nnzA;
+    a.nnzA0 = (uint32_t)pl->nnzA0;
+    a.E = (uint32_t)pl->E;
     a.Ak_cp = pl->Ak_cp;
     a.Ak_v = Ak_val;
     a.A0_cp = pl->A0_cp;
@@ -547,6 +550,14 @@ sam_status sam_plan_create(sam_ctx* ctx, const sam_csc* Ak, const sam_csc* A0, c
             return bail(fail(ctx, SAM_ERR_HIP, "plan count: %s", hipGetErrorString(he)));
     }
     pl->E = E;
+    // the numeric kernels address A_k, A_0 and the gathered positions with
+    // 32-bit byte offsets
+    if ((int64_t)Ak->nnz * 8 > (int64_t)UINT32_MAX || (int64_t)A0->nnz * 8 > (int64_t)UINT32_MAX ||
+        E > (int64_t)UINT32_MAX)
+        return bail(fail(ctx, SAM_ERR_UNSUPPORTED,
+                         "nnz(A_k) = %d, nnz(A_0) = %d, gathered entries = %lld: the numeric kernels need "
+                         "nnz < 2^29 and fewer than 2^32 gathered entries (split the columns)",
+                         Ak->nnz, A0->nnz, (long long)E));
     size_t mem = align256((size_t)n * 4) + align256((size_t)(n + 1) * 8) + align256((size_t)std::max<int64_t>(E, 1)) +
                  align256((size_t)std::max(A0->nnz, 1)) + 4 * (align256((size_t)n * 4) + align256(64 * 4)) +
                  align256((size_t)n * 8) + align256(samk::reduce_temp_bytes(n)) + 1024;

@@ -93,6 +93,9 @@ hipError_t bucket_sort(int n, const int* S_cp, const int* nI, BucketTable tab, i
 // --------------------------------------------------------------- numeric
 struct NumericArgs {
     int n;
+    // extents of the arrays the kernels read through 32-bit buffer offsets
+    // (the plan guarantees nnz(A_k) * 8, nnz(A_0) * 8 and E below 2^32)
+    uint32_t nnzA, nnzA0, E;
     const int* Ak_cp;
     const double* Ak_v;
     const int* A0_cp;

@@ -48,6 +48,19 @@ __device__ inline int logical_block() {
     return (b & 7) * (nb >> 3) + (b >> 3);
 }
 
+// Raw buffer resources over the arrays the gather reads: 32-bit byte offsets
+// (no 64-bit address arithmetic per load, constant parts folded into the
+// instruction's offset field) and loads past the extent return 0.
+__device__ inline __amdgpu_buffer_rsrc_t buf_rsrc(const void* p, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
+}
+__device__ inline double ld_f64(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
+}
+__device__ inline int ld_u8(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+    return (int)__builtin_amdgcn_raw_buffer_load_b8(r, (int)off, 0, 0);
+}
+
 template <typename T>
 __device__ inline T recip(T x);
 template <>
@@ -101,6 +114,10 @@ k_numeric(NumericArgs a) {
     const int lb = logical_block();
     const int grp_lo = lb * per_block;
     const int grp_hi = min(ngroups, grp_lo + per_block);
+    const __amdgpu_buffer_rsrc_t rAv = buf_rsrc(a.Ak_v, a.nnzA * 8u);
+    const __amdgpu_buffer_rsrc_t rA0 = buf_rsrc(a.A0_v, a.nnzA0 * 8u);
+    const __amdgpu_buffer_rsrc_t rPA = buf_rsrc(a.posA, a.E);
+    const __amdgpu_buffer_rsrc_t rPB = buf_rsrc(a.posB, a.nnzA0);
 
     for (int grp = grp_lo; grp < grp_hi; ++grp) {
         const int slot = grp * P + q;
@@ -116,7 +133,9 @@ k_numeric(NumericArgs a) {
         }
         const int nrows = WEIGHTED ? nIj + nJ : nIj;
 
-        // ---- column metadata: lane g resolves columns g, g+G, ... of J_j
+        // ---- column metadata: lane g resolves columns g, g+G, ... of J_j;
+        //      longc (wave-uniform): some column needs the memory loops
+        bool mylong = false;
 #pragma unroll
         for (int c = g; c < NC; c += G) {
             int vb = 0, len = 0;
@@ -127,7 +146,9 @@ k_numeric(NumericArgs a) {
             }
             vbs[q][c] = vb;
             cln[q][c] = len;
+            mylong |= len > LPL * G;
         }
+        const bool longc = __ballot(mylong) != 0ull;
         // ---- b = A_0(I_j, j) and out_j (rows outside I_j)
 #pragma unroll
         for (int t = 0; t < R; ++t) bsh[q * RX + t * G + g] = 0.0;
@@ -138,11 +159,10 @@ k_numeric(NumericArgs a) {
         double bv[LPL];
 #pragma unroll
         for (int s = 0; s < LPL; ++s) {
-            const int e = a0 + g + s * G;
-            const bool ok = e < a1;
-            const int ec = ok ? e : 0;
-            const int p = a.posB[ec];
-            const double v = a.A0_v[ec];
+            const bool ok = a0 + g + s * G < a1;
+            const uint32_t e = (uint32_t)(a0 + g) + (uint32_t)(s * G);
+            const int p = ld_u8(rPB, e);
+            const double v = ld_f64(rA0, e * 8u);
             bp[s] = ok ? p : -1;
             bv[s] = ok ? v : 0.0;
         }
@@ -180,15 +200,13 @@ k_numeric(NumericArgs a) {
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
             const int len = cln[q][c];
-            const int e0 = cst[q][c];
-            const int vb = vbs[q][c];
+            const uint32_t po = (uint32_t)eo + (uint32_t)(cst[q][c] + g);
+            const uint32_t vo = (uint32_t)(vbs[q][c] + g) * 8u;
 #pragma unroll
             for (int s = 0; s < LPL; ++s) {
-                const int e = g + s * G;
-                const bool ok = e < len;
-                const int ec = ok ? e : 0;  // clamped: the load is always in bounds
-                const int p = a.posA[eo + e0 + ec];
-                const double v = a.Ak_v[vb + ec];
+                const bool ok = g + s * G < len;
+                const int p = ld_u8(rPA, po + s * G);
+                const double v = ld_f64(rAv, vo + s * G * 8);
                 pp[c][s] = ok ? p : trash;
                 pv[c][s] = ok ? v : 0.0;
             }
@@ -209,7 +227,7 @@ k_numeric(NumericArgs a) {
                 if (c < NC) {
 #pragma unroll
                     for (int s = 0; s < LPL; ++s) tile[(q * RX + pp[c][s]) * TC + cc] = (TQ)pv[c][s];
-                    const int len = cln[q][c];
+                    const int len = longc ? cln[q][c] : 0;
                     if (len > LPL * G) {  // long columns: the rest straight from memory
                         const int e0 = cst[q][c], vb = vbs[q][c];
                         for (int e = g + LPL * G; e < len; e += G)
@@ -336,15 +354,13 @@ k_numeric(NumericArgs a) {
 #pragma unroll
             for (int c = 0; c < NC; ++c) {
                 const int len = cln[q][c];
-                const int e0 = cst[q][c];
-                const int vb = vbs[q][c];
+                const uint32_t po = (uint32_t)eo + (uint32_t)(cst[q][c] + g);
+                const uint32_t vo = (uint32_t)(vbs[q][c] + g) * 8u;
 #pragma unroll
                 for (int u = 0; u < LPL; ++u) {
-                    const int e = g + u * G;
-                    const bool ok = e < len;
-                    const int ec = ok ? e : 0;
-                    const int p = a.posA[eo + e0 + ec];
-                    const double v = a.Ak_v[vb + ec];
+                    const bool ok = g + u * G < len;
+                    const int p = ld_u8(rPA, po + u * G);
+                    const double v = ld_f64(rAv, vo + u * G * 8);
                     pp[c][u] = ok ? p : trash;
                     pv[c][u] = ok ? v : 0.0;
                 }
@@ -357,8 +373,12 @@ k_numeric(NumericArgs a) {
                 const double xc = sgn * x[c];
 #pragma unroll
                 for (int u = 0; u < LPL; ++u) vec[pp[c][u]] += pv[c][u] * xc;
-                const int len = cln[q][c];
-                if (len > LPL * G) {  // long columns
+            }
+            if (longc) {  // long columns: the rest straight from memory
+#pragma unroll
+                for (int c = 0; c < NC; ++c) {
+                    const int len = cln[q][c];
+                    const double xc = sgn * x[c];
                     const int e0 = cst[q][c], vb = vbs[q][c];
                     for (int e = g + LPL * G; e < len; e += G) vec[a.posA[eo + e0 + e]] += a.Ak_v[vb + e] * xc;
                 }
@@ -372,19 +392,24 @@ k_numeric(NumericArgs a) {
                 double sacc = 0.0;
 #pragma unroll
                 for (int u = 0; u < LPL; ++u) sacc += pv[c][u] * vec[pp[c][u]];
-                const int len = cln[q][c];
-                if (len > LPL * G) {
-                    const int e0 = cst[q][c], vb = vbs[q][c];
-                    for (int e = g + LPL * G; e < len; e += G) sacc += a.Ak_v[vb + e] * vec[a.posA[eo + e0 + e]];
-                }
                 out[c] = sacc;
+            }
+            if (longc) {
+#pragma unroll
+                for (int c = 0; c < NC; ++c) {
+                    const int len = cln[q][c];
+                    const int e0 = cst[q][c], vb = vbs[q][c];
+                    double sacc = 0.0;
+                    for (int e = g + LPL * G; e < len; e += G) sacc += a.Ak_v[vb + e] * vec[a.posA[eo + e0 + e]];
+                    out[c] += sacc;
+                }
             }
 #pragma unroll
             for (int c = 0; c < NC; ++c) out[c] = group_sum<G>(out[c]);
         };
         // x = R^{-1} R^{-T} rhs in the QR's precision (R^T R = A^T A + P);
-        // y = R^{-T} rhs is returned too
-        auto solve_normal = [&](const double (&rhs)[NC], double (&x)[NC], double (&y)[NC]) {
+        // returns ||y||^2 for y = R^{-T} rhs
+        auto solve_normal = [&](const double (&rhs)[NC], double (&x)[NC]) {
             TQ ydist[R];
             TQ yrep[NC];
 #pragma unroll
@@ -413,11 +438,13 @@ k_numeric(NumericArgs a) {
                 const TQ dk = group_bcast<G>(sacc * rinv[k], g, gk);
                 dl[k] = (k < nJ) ? dk : (TQ)0;
             }
+            double yy = 0.0;
 #pragma unroll
             for (int c = 0; c < NC; ++c) {
                 x[c] = (double)dl[c];
-                y[c] = (double)yrep[c];
+                yy += (double)yrep[c] * (double)yrep[c];
             }
+            return yy;
         };
         auto reset = [&](double* vec, bool from_b) {
 #pragma unroll
@@ -457,19 +484,18 @@ k_numeric(NumericArgs a) {
                     r2 += (t * G + g < nIj) ? x * x : 0.0;
                 }
                 rr_it = group_sum<G>(r2);
-                double gA[NC], gc[NC], dl[NC], yv[NC];
+                double gA[NC], gc[NC], dl[NC];
                 gather(rsh, gA);
 #pragma unroll
-                for (int c = 0; c < NC; ++c) gc[c] = gA[c] - pen[c] * m64[c];
-                solve_normal(gc, dl, yv);
+                for (int c = 0; c < NC; ++c) gc[c] = WEIGHTED ? gA[c] - pen[c] * m64[c] : gA[c];
+                const double yy = solve_normal(gc, dl);
                 // ||b - A(m + d)||^2 = ||r||^2 - 2 d^T A^T r + ||A d||^2, and
                 // ||A d||^2 = ||R d||^2 - d^T P d with R d = y (second order in d)
-                double dg = 0.0, yy = 0.0, pdd = 0.0;
+                double dg = 0.0, pdd = 0.0;
 #pragma unroll
                 for (int c = 0; c < NC; ++c) {
                     dg += dl[c] * gA[c];
-                    yy += yv[c] * yv[c];
-                    pdd += pen[c] * dl[c] * dl[c];
+                    if constexpr (WEIGHTED) pdd += pen[c] * dl[c] * dl[c];
                     m64[c] += dl[c];
                 }
                 rr_it = rr_it - 2.0 * dg + (yy - pdd);
@@ -488,8 +514,10 @@ k_numeric(NumericArgs a) {
                 r2 += (t * G + g >= nJ) ? x * x : 0.0;
             }
             rr = group_sum<G>(r2);
+            if constexpr (WEIGHTED) {
 #pragma unroll
-            for (int c = 0; c < NC; ++c) rr -= pen[c] * mfin[c] * mfin[c];
+                for (int c = 0; c < NC; ++c) rr -= pen[c] * mfin[c] * mfin[c];
+            }
             rr += outj;
         }
 
@@ -501,11 +529,11 @@ k_numeric(NumericArgs a) {
             wave_sync();
             scatter(rsh, mfin, -1.0);
             // h = 2 A^T r,  lambda = (A^T A + P)^{-1} h
-            double h[NC], lam[NC], yv[NC];
+            double h[NC], lam[NC];
             gather(rsh, h);
 #pragma unroll
             for (int c = 0; c < NC; ++c) h[c] = -2.0 * h[c];
-            solve_normal(h, lam, yv);
+            solve_normal(h, lam);
             if constexpr (REFINE) {
 #pragma unroll
                 for (int it = 0; it < 2; ++it) {  // FP64-residual refinement of lambda
@@ -516,7 +544,7 @@ k_numeric(NumericArgs a) {
                     gather(al, qv);
 #pragma unroll
                     for (int c = 0; c < NC; ++c) res[c] = h[c] - qv[c] - pen[c] * lam[c];
-                    solve_normal(res, dl, yv);
+                    solve_normal(res, dl);
 #pragma unroll
                     for (int c = 0; c < NC; ++c) lam[c] += dl[c];
                 }
@@ -536,7 +564,7 @@ k_numeric(NumericArgs a) {
                     if (p != trash)
                         cj[e0 + g + u * G] = dL * (-2.0 * rsh[p] * mfin[c] + rsh[p] * lam[c] - al[p] * mfin[c]);
                 }
-                const int len = cln[q][c];
+                const int len = longc ? cln[q][c] : 0;
                 if (len > LPL * G) {
                     for (int e = g + LPL * G; e < len; e += G) {
                         const int p = a.posA[eo + e0 + e];

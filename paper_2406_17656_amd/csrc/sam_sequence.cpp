@@ -232,6 +232,7 @@ sam_status sam_sequence_create(sam_ctx* ctx, const sam_csc* A0, const sam_csc* A
         d.nnzA = q->nnzA;
         d.nnzA0 = q->nnzA0;
         d.nnzS = q->nnzS;
+        d.E = q->plan->E;
         d.Ak_cp = q->Ak_cp;
         d.Ak_ri = q->Ak_ri;
         d.A0_cp = q->A0_cp;
