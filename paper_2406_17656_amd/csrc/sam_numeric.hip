@@ -90,18 +90,22 @@ k_numeric(NumericArgs a) {
     constexpr int P = 64 / G;        // problems per wave
     constexpr int RM = G * R;        // rows per problem (padded)
     constexpr int RX = RM + G;       // plus one scratch row per lane
+    // LDS stride between the problems of a wave: RS = G (mod 16) rows, so
+    // that rows t*G + g of the P problems spread over all the banks (a
+    // stride of 32 rows would put all 16 problems of a G = 4 wave on one)
+    constexpr int RS = RX + (((G - RX) % 16) + 16) % 16;
     constexpr bool REFINE = std::is_same<TQ, float>::value;
     static_assert(TC >= 1, "tile chunk");
     // gather staging in the QR's precision; afterwards the same memory holds
-    // the FP64 residual vector (P * RX doubles)
-    constexpr int kTileD = (P * RX * TC * (int)sizeof(TQ) + 7) / 8;
-    __shared__ double lds_tile[kTileD > P * RX ? kTileD : P * RX];
+    // the FP64 residual vector (P * RS doubles)
+    constexpr int kTileD = (P * RS * TC * (int)sizeof(TQ) + 7) / 8;
+    __shared__ double lds_tile[kTileD > P * RS ? kTileD : P * RS];
     TQ* tile = reinterpret_cast<TQ*>(lds_tile);
-    __shared__ double bsh[P * RX];        // b = A_0(I_j, j)
+    __shared__ double bsh[P * RS];        // b = A_0(I_j, j)
     __shared__ int cst[P][NC + 1];        // entry offset of column c in the block
     __shared__ int vbs[P][NC];            // start of A_k(:, J_j[c]) in the value array
     __shared__ int cln[P][NC];            // nnz of A_k(:, J_j[c])
-    __shared__ double alsh[BACKWARD ? P * RX : 1];  // A lambda (adjoint)
+    __shared__ double alsh[BACKWARD ? P * RS : 1];  // A lambda (adjoint)
 
     const int lane = threadIdx.x;
     const int g = lane % G;
@@ -151,8 +155,8 @@ k_numeric(NumericArgs a) {
         const bool longc = __ballot(mylong) != 0ull;
         // ---- b = A_0(I_j, j) and out_j (rows outside I_j)
 #pragma unroll
-        for (int t = 0; t < R; ++t) bsh[q * RX + t * G + g] = 0.0;
-        bsh[q * RX + trash] = 0.0;
+        for (int t = 0; t < R; ++t) bsh[q * RS + t * G + g] = 0.0;
+        bsh[q * RS + trash] = 0.0;
         const int a0 = valid ? a.A0_cp[j] : 0;
         const int a1 = valid ? a.A0_cp[j + 1] : 0;
         int bp[LPL];
@@ -180,12 +184,12 @@ k_numeric(NumericArgs a) {
 #pragma unroll
         for (int s = 0; s < LPL; ++s) {
             outj += bp[s] == 0xFF ? bv[s] * bv[s] : 0.0;
-            bsh[q * RX + ((bp[s] >= 0 && bp[s] != 0xFF) ? bp[s] : trash)] = bv[s];
+            bsh[q * RS + ((bp[s] >= 0 && bp[s] != 0xFF) ? bp[s] : trash)] = bv[s];
         }
         for (int e = a0 + g + LPL * G; e < a1; e += G) {  // long columns
             const int p = a.posB[e];
             const double v = a.A0_v[e];
-            if (p != 0xFF) bsh[q * RX + p] = v;
+            if (p != 0xFF) bsh[q * RS + p] = v;
             else outj += v * v;
         }
         outj = group_sum<G>(outj);
@@ -218,7 +222,7 @@ k_numeric(NumericArgs a) {
             for (int t = 0; t <= R; ++t) {
                 const int row = t < R ? t * G + g : trash;
 #pragma unroll
-                for (int cc = 0; cc < TC; ++cc) tile[(q * RX + row) * TC + cc] = (TQ)0;
+                for (int cc = 0; cc < TC; ++cc) tile[(q * RS + row) * TC + cc] = (TQ)0;
             }
             wave_sync();
 #pragma unroll
@@ -226,12 +230,12 @@ k_numeric(NumericArgs a) {
                 const int c = c0 + cc;
                 if (c < NC) {
 #pragma unroll
-                    for (int s = 0; s < LPL; ++s) tile[(q * RX + pp[c][s]) * TC + cc] = (TQ)pv[c][s];
+                    for (int s = 0; s < LPL; ++s) tile[(q * RS + pp[c][s]) * TC + cc] = (TQ)pv[c][s];
                     const int len = longc ? cln[q][c] : 0;
                     if (len > LPL * G) {  // long columns: the rest straight from memory
                         const int e0 = cst[q][c], vb = vbs[q][c];
                         for (int e = g + LPL * G; e < len; e += G)
-                            tile[(q * RX + a.posA[eo + e0 + e]) * TC + cc] = (TQ)a.Ak_v[vb + e];
+                            tile[(q * RS + a.posA[eo + e0 + e]) * TC + cc] = (TQ)a.Ak_v[vb + e];
                     }
                 }
             }
@@ -240,7 +244,7 @@ k_numeric(NumericArgs a) {
             for (int t = 0; t < R; ++t)
 #pragma unroll
                 for (int cc = 0; cc < TC; ++cc)
-                    if (c0 + cc < NC) A[t][c0 + cc] = tile[(q * RX + t * G + g) * TC + cc];
+                    if (c0 + cc < NC) A[t][c0 + cc] = tile[(q * RS + t * G + g) * TC + cc];
             wave_sync();
         }
         // penalty rows: row nIj + c holds sqrt(p_c) in column c
@@ -259,7 +263,7 @@ k_numeric(NumericArgs a) {
         }
         TQ bq[R];
 #pragma unroll
-        for (int t = 0; t < R; ++t) bq[t] = (TQ)bsh[q * RX + t * G + g];
+        for (int t = 0; t < R; ++t) bq[t] = (TQ)bsh[q * RS + t * G + g];
 
         // ---- Householder QR (dgeqr2 conventions), applied to b as well
         TQ rdiag[NC], rinv[NC];
@@ -343,7 +347,7 @@ k_numeric(NumericArgs a) {
             m[k] = (k < nJ) ? mk : (TQ)0;
         }
 
-        double* rsh = lds_tile + q * RX;  // residual vector (the tile is free now)
+        double* rsh = lds_tile + q * RS;  // residual vector (the tile is free now)
 
         // Sparse FP64 passes over the gathered entries of the block.  Rows are
         // distinct inside one column, so the lanes of a group never update
@@ -448,7 +452,7 @@ k_numeric(NumericArgs a) {
         };
         auto reset = [&](double* vec, bool from_b) {
 #pragma unroll
-            for (int t = 0; t < R; ++t) vec[t * G + g] = from_b ? bsh[q * RX + t * G + g] : 0.0;
+            for (int t = 0; t < R; ++t) vec[t * G + g] = from_b ? bsh[q * RS + t * G + g] : 0.0;
             vec[trash] = 0.0;
         };
 
@@ -523,7 +527,7 @@ k_numeric(NumericArgs a) {
 
         if constexpr (BACKWARD) {
             // r = A m - b is held as rsh = b - A m = -r
-            double* al = alsh + q * RX;
+            double* al = alsh + q * RS;
             reset(rsh, true);
             load_entries();
             wave_sync();
