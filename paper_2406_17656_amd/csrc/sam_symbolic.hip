@@ -370,10 +370,21 @@ __device__ inline int grp_excl_scan(int v) {
 
 enum { kModeCount = 0, kModeFill = 1, kModePositions = 2 };
 
+// Bitmap word wi (rows 32 wi .. 32 wi + 31 of the chunk) belongs to lane
+// wi / WPL of the group (the lanes own consecutive row ranges, so ranks
+// follow a prefix over the lanes) but is stored at (wi % WPL) * GS + wi / WPL:
+// the passes in which every lane touches its own words hit GS consecutive
+// banks instead of GS / 4.
+template <int GS, int WPL>
+__device__ inline int word_slot(int wi) {
+    return ((wi & (WPL - 1)) * GS) | (wi / WPL);
+}
+
 // Rank of row d (relative to the chunk base) inside the chunk's bitmap.
+template <int GS, int WPL>
 __device__ inline int chunk_rank(const unsigned* bm, const int* wpre, int d) {
-    const int w = d >> 5;
-    return wpre[w] + __popc(bm[w] & ((1u << (d & 31)) - 1u));
+    const int p = word_slot<GS, WPL>(d >> 5);
+    return wpre[p] + __popc(bm[p] & ((1u << (d & 31)) - 1u));
 }
 
 // Operands of the union kernel.  A list set X is (X_cp, X_cnt, X_ri): list l
@@ -402,14 +413,16 @@ __global__ void __launch_bounds__(kSymThreads)
 k_union(UnionArgs a) {
     constexpr int kGroups = kSymThreads / GS;
     constexpr int kWPL = kChunkWords / GS;   // bitmap words per lane
-    __shared__ unsigned bm_all[kGroups][kChunkWords];
-    __shared__ int pre_all[kGroups][kChunkWords];
+    // group stride padded by GS words: the groups of a wave start on
+    // different banks
+    __shared__ unsigned bm_all[kGroups][kChunkWords + GS];
+    __shared__ int pre_all[kGroups][kChunkWords + GS];
     const int n = a.n;
     const int grp = threadIdx.x / GS;
     const int g = threadIdx.x % GS;
     unsigned* bm = bm_all[grp];
     int* wpre = pre_all[grp];
-    unsigned* mine = bm + g * kWPL;
+    auto slot = [](int wi) { return word_slot<GS, kWPL>(wi); };
     const int stride = gridDim.x * kGroups;
     auto q_len = [&](int l) { return a.Q_cnt ? a.Q_cnt[l] : a.Q_cp[l + 1] - a.Q_cp[l]; };
     for (int j = blockIdx.x * kGroups + grp; j < n; j += stride) {
@@ -471,7 +484,7 @@ k_union(UnionArgs a) {
         int base = lo;
         while (base != INT_MAX) {
 #pragma unroll
-            for (int w = 0; w < kWPL; ++w) mine[w] = 0u;
+            for (int w = 0; w < kWPL; ++w) bm[w * GS + g] = 0u;
             wave_sync();
             int next = INT_MAX;
             if (!big) {
@@ -481,7 +494,7 @@ k_union(UnionArgs a) {
                     for (int e = 0; e < kListLen; ++e) {
                         const int r = rows[u][e];
                         const int d = r - base;  // r = INT_MAX for empty slots: d >= kChunk
-                        if (d >= 0 && d < kChunk) atomicOr(&bm[d >> 5], 1u << (d & 31));
+                        if (d >= 0 && d < kChunk) atomicOr(&bm[slot(d >> 5)], 1u << (d & 31));
                         if (d >= kChunk) next = min(next, r);
                     }
             } else {
@@ -492,7 +505,7 @@ k_union(UnionArgs a) {
                     for (int f = f0; f < f1; ++f) {
                         const int r = a.Q_ri[f];
                         const int d = r - base;
-                        if (d >= 0 && d < kChunk) atomicOr(&bm[d >> 5], 1u << (d & 31));
+                        if (d >= 0 && d < kChunk) atomicOr(&bm[slot(d >> 5)], 1u << (d & 31));
                         if (d >= kChunk) next = min(next, r);
                     }
                 }
@@ -502,7 +515,7 @@ k_union(UnionArgs a) {
             int c = 0;
 #pragma unroll
             for (int w = 0; w < kWPL; ++w) {
-                wd[w] = mine[w];
+                wd[w] = bm[w * GS + g];
                 c += __popc(wd[w]);
             }
             const int pre = grp_excl_scan<GS>(c);
@@ -511,7 +524,7 @@ k_union(UnionArgs a) {
                 int run = running + pre;
 #pragma unroll
                 for (int w = 0; w < kWPL; ++w) {
-                    wpre[g * kWPL + w] = run;
+                    wpre[w * GS + g] = run;
                     run += __popc(wd[w]);
                 }
             }
@@ -538,7 +551,7 @@ k_union(UnionArgs a) {
                         for (int e = 0; e < kListLen; ++e) {
                             const int d = rows[u][e] - base;
                             if (d >= 0 && d < kChunk)
-                                pj[lofs[u] + e] = (unsigned char)min(chunk_rank(bm, wpre, d), 255);
+                                pj[lofs[u] + e] = (unsigned char)min(chunk_rank<GS, kWPL>(bm, wpre, d), 255);
                         }
                 } else {
                     int cy = 0;
@@ -552,15 +565,16 @@ k_union(UnionArgs a) {
                         const int off = cy + grp_excl_scan<GS>(ln);
                         for (int f = 0; f < ln; ++f) {
                             const int d = a.Q_ri[a.Q_cp[l] + f] - base;
-                            if (d >= 0 && d < kChunk) pj[off + f] = (unsigned char)min(chunk_rank(bm, wpre, d), 255);
+                            if (d >= 0 && d < kChunk)
+                                pj[off + f] = (unsigned char)min(chunk_rank<GS, kWPL>(bm, wpre, d), 255);
                         }
                         cy += grp_sum<GS>(ln);
                     }
                 }
                 for (int e = a.A0_cp[j] + g; e < a.A0_cp[j + 1]; e += GS) {
                     const int d = a.A0_ri[e] - base;
-                    if (d >= 0 && d < kChunk && ((bm[d >> 5] >> (d & 31)) & 1u))
-                        a.posB[e] = (unsigned char)min(chunk_rank(bm, wpre, d), 254);
+                    if (d >= 0 && d < kChunk && ((bm[slot(d >> 5)] >> (d & 31)) & 1u))
+                        a.posB[e] = (unsigned char)min(chunk_rank<GS, kWPL>(bm, wpre, d), 254);
                 }
             }
             running += tot;
