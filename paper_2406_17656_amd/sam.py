@@ -236,17 +236,19 @@ class Plan:
                                                   ctypes.byref(by)))
         return {"flops32": f32.value, "flops64": f64.value, "bytes": by.value}
 
-    def _outs(self, prec, M, cols, res2):
+    def _outs(self, prec, M, cols, res2, fro=True):
         dev = self.S_colptr.device
         if M is None:
             M = torch.empty(max(self.nnz_S, 1), dtype=_mdtype(prec), device=dev)
-        if res2 is None:
+        if res2 is None and fro:
             res2 = torch.empty(1, dtype=torch.float64, device=dev)
         return M, cols, res2
 
-    def build(self, Ak_val, A0_val, prec="f64", M=None, col_res2=None, res2=None):
+    def build(self, Ak_val, A0_val, prec="f64", M=None, col_res2=None, res2=None, fro=True):
+        """sam_build_planned.  fro=False (and no res2) leaves out the
+        Frobenius sum: the launches are then the numeric kernels alone."""
         p = _prec(prec)
-        M, col_res2, res2 = self._outs(p, M, col_res2, res2)
+        M, col_res2, res2 = self._outs(p, M, col_res2, res2, fro)
         self.ctx.check(self.ctx.lib.sam_build_planned(self.h, _ptr(Ak_val), _ptr(A0_val), p, _ptr(M),
                                                       _ptr(col_res2), _ptr(res2), self.ctx.stream()))
         return M[:self.nnz_S], col_res2, res2
