@@ -277,7 +277,8 @@ sam_status sam_apply(sam_ctx* ctx, int32_t n, const int32_t* T_rowptr, const int
  * source inside each run, sized to the unsparsified bound.  The first run
  * with a given set of pointers is captured into a HIP graph; later runs with
  * the same pointers replay it.  M_vals[k] must hold nnz_bound entries
- * (sam_sequence_info).  Synchronising (create). */
+ * (sam_sequence_info).  Errors: SAM_ERR_ARG also for n = 0 (nothing to
+ * map).  Synchronising (create). */
 sam_status sam_sequence_create(sam_ctx* ctx, const sam_csc* A0, const sam_csc* Ak_struct,
                                const sam_pattern_spec* spec, int32_t n_src, sam_precision prec,
                                int32_t replan_each_run, sam_seq** seq, sam_stream_t stream);

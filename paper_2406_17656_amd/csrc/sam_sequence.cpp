@@ -55,6 +55,29 @@ struct sam_seq {
 
 namespace {
 
+// Device-side buckets of replanning mode from the structural plan's: a
+// sparsified column only shrinks, so it lands in its structural bucket or an
+// earlier one, and the count of bucket b is at most the structural count of
+// buckets >= b (the grid bound).  Buckets past the last one with a nonzero
+// bound can receive no column and are left out of the table, which keeps the
+// per-run bucket kernels short.
+void bound_buckets(Combo& cb, const Combo& structural) {
+    cb.variants = structural.variants;
+    cb.tab = structural.tab;
+    const std::vector<int>& sc = structural.counts;
+    cb.counts.assign(sc.size(), 0);
+    int suffix = 0;
+    for (int b = (int)sc.size() - 1; b >= 0; --b) {
+        suffix += sc[b];
+        cb.counts[b] = suffix;
+    }
+    int live = (int)cb.counts.size();
+    while (live > 0 && cb.counts[(size_t)live - 1] == 0) --live;
+    cb.counts.resize((size_t)live);
+    cb.variants.resize(std::min(cb.variants.size(), (size_t)live));
+    cb.tab.nb = std::min(cb.tab.nb, live);
+}
+
 void drop_graph(sam_seq* q) {
     if (q->exec) (void)hipGraphExecDestroy(q->exec);
     if (q->graph) (void)hipGraphDestroy(q->graph);
@@ -132,6 +155,7 @@ sam_status sam_sequence_create(sam_ctx* ctx, const sam_csc* A0, const sam_csc* A
     if ((st = check_spec(ctx, spec))) return st;
     if (A0->n != Ak_struct->n) return fail(ctx, SAM_ERR_SHAPE, "A0 and Ak_struct differ in order");
     if (n_src < 1) return fail(ctx, SAM_ERR_ARG, "n_src must be >= 1 (got %d)", n_src);
+    if (A0->n == 0) return fail(ctx, SAM_ERR_ARG, "empty matrices (n = 0): nothing to map");
     if (!prec_ok(prec)) return fail(ctx, SAM_ERR_ARG, "unknown precision %d", (int)prec);
     if ((st = need_device(ctx))) return st;
     hipStream_t s = S(stream);
@@ -244,18 +268,8 @@ sam_status sam_sequence_create(sam_ctx* ctx, const sam_csc* A0, const sam_csc* A
         Combo& cb = d.combo[q->prec][0];
         cb.queue = cv.take<int>(n);
         cb.bstart = cv.take<int>(64);
-        cb.tab = menu_table(q->prec, 0, &cb.variants);
         cb.ok = true;
-        // Grid bounds per bucket: a sparsified column only shrinks, so it
-        // lands in its structural bucket or an earlier one; the count of
-        // bucket b is at most the structural count of buckets >= b.
-        const std::vector<int>& sc = q->plan->combo[q->prec][0].counts;
-        cb.counts.assign(sc.size(), 0);
-        int suffix = 0;
-        for (int b = (int)sc.size() - 1; b >= 0; --b) {
-            suffix += sc[b];
-            cb.counts[b] = suffix;
-        }
+        bound_buckets(cb, q->plan->combo[q->prec][0]);
         d.colbuf = cv.take<double>(n);
         d.rtemp = cv.take<char>(samk::reduce_temp_bytes(n));
         d.device_counts = true;
@@ -325,18 +339,7 @@ sam_status sam_sequence_select(sam_seq* q, const int32_t* order, int32_t count, 
     sam_status st = need_device(ctx);
     if (st) return st;
     if ((st = plan_select(q->plan, q->prec, vars, S(stream)))) return st;
-    if (q->replan) {
-        Combo& cb = q->dplan.combo[q->prec][0];
-        cb.variants = q->plan->combo[q->prec][0].variants;
-        cb.tab = q->plan->combo[q->prec][0].tab;
-        const std::vector<int>& sc = q->plan->combo[q->prec][0].counts;
-        cb.counts.assign(sc.size(), 0);
-        int suffix = 0;
-        for (int b = (int)sc.size() - 1; b >= 0; --b) {
-            suffix += sc[b];
-            cb.counts[b] = suffix;
-        }
-    }
+    if (q->replan) bound_buckets(q->dplan.combo[q->prec][0], q->plan->combo[q->prec][0]);
     drop_graph(q);  // the next run captures the new launches
     return SAM_OK;
 }

@@ -694,35 +694,44 @@ __device__ inline int bucket_of(int nI, int nJ, const BucketTable& tab) {
     return -1;
 }
 
-// The columns are cut into at most kBucketBlocks contiguous ranges (a
-// multiple of 256 columns each); pass 1 counts every range's columns per
+// The columns are cut into at most kBucketBlocks contiguous ranges of `len`
+// columns (a multiple of 256); pass 1 counts every range's columns per
 // bucket (hist is bucket-major: hist[b * nblk + blk]), pass 2 lets every
 // range sum the counts before it (all ranges of earlier buckets, earlier
-// ranges of its own bucket) and scatter its columns in column order.
+// ranges of its own bucket) and scatter its columns in column order.  With
+// one or two buckets the ranges are single chunks of 256 columns (many
+// blocks, cheap prefix sums); with more, at least 2048 columns.
 constexpr int kBucketBlocks = 1024;
 
-__host__ __device__ inline int64_t range_len(int n) {
+static int64_t range_len(int n, int nb) {
     const int64_t per = ((int64_t)n + kBucketBlocks * kBucketThreads - 1) / ((int64_t)kBucketBlocks * kBucketThreads);
-    return (per > 8 ? per : 8) * kBucketThreads;
+    const int64_t lo = nb <= 2 ? 1 : 8;
+    return (per > lo ? per : lo) * kBucketThreads;
 }
 
 __global__ void __launch_bounds__(kBucketThreads)
-k_bucket_hist(int n, const int* S_cp, const int* nI, BucketTable tab, int* hist, int* unfit,
+k_bucket_hist(int n, int64_t len, const int* S_cp, const int* nI, BucketTable tab, int* hist, int* unfit,
               unsigned long long* status) {
     __shared__ int h[kMaxBuckets];
     if (threadIdx.x < kMaxBuckets) h[threadIdx.x] = 0;
     __syncthreads();
-    const int64_t len = range_len(n);
     const int64_t j0 = (int64_t)blockIdx.x * len;
     const int64_t j1 = std::min<int64_t>(j0 + len, n);
-    for (int64_t jj = j0 + threadIdx.x; jj < j1; jj += kBucketThreads) {
-        const int j = (int)jj;
-        const int b = bucket_of(nI[j], S_cp[j + 1] - S_cp[j], tab);
-        if (b >= 0) {
-            atomicAdd(&h[b], 1);
-        } else {
-            if (unfit) atomicAdd(unfit, 1);
-            if (status) report(status, j, kStUnsupported);
+    for (int64_t c0 = j0; c0 < j1; c0 += kBucketThreads) {   // uniform trip count across the block
+        const int64_t jj = c0 + threadIdx.x;
+        int b = -2;
+        if (jj < j1) {
+            const int j = (int)jj;
+            b = bucket_of(nI[j], S_cp[j + 1] - S_cp[j], tab);
+            if (b < 0) {
+                if (unfit) atomicAdd(unfit, 1);
+                if (status) report(status, j, kStUnsupported);
+            }
+        }
+        // per-wave counts (one LDS atomic per wave and bucket, not per column)
+        for (int k = 0; k < tab.nb; ++k) {
+            const int c = __popcll(__ballot(b == k));
+            if (wave_lane() == 0 && c) atomicAdd(&h[k], c);
         }
     }
     __syncthreads();
@@ -730,25 +739,31 @@ k_bucket_hist(int n, const int* S_cp, const int* nI, BucketTable tab, int* hist,
 }
 
 __global__ void __launch_bounds__(kBucketThreads)
-k_bucket_scatter(int n, const int* S_cp, const int* nI, BucketTable tab, const int* hist, int* queue,
-                 int* bstart) {
+k_bucket_scatter(int n, int64_t len, const int* S_cp, const int* nI, BucketTable tab, const int* hist,
+                 int* queue, int* bstart) {
     __shared__ int tot[kMaxBuckets], pre[kMaxBuckets], base[kMaxBuckets + 1];
     __shared__ int wcount[kBucketThreads / 64][kMaxBuckets];
     const int nblk = gridDim.x;
     const int me = blockIdx.x;
     if (threadIdx.x < kMaxBuckets) tot[threadIdx.x] = pre[threadIdx.x] = 0;
     __syncthreads();
-    {
-        const int b = threadIdx.x % kMaxBuckets;
+    for (int b = 0; b < tab.nb; ++b) {   // every thread strides over the ranges of bucket b
         int t = 0, p = 0;
-        if (b < tab.nb)
-            for (int blk = threadIdx.x / kMaxBuckets; blk < nblk; blk += kBucketThreads / kMaxBuckets) {
-                const int c = hist[b * nblk + blk];
-                t += c;
-                p += blk < me ? c : 0;
-            }
-        if (t) atomicAdd(&tot[b], t);
-        if (p) atomicAdd(&pre[b], p);
+#pragma unroll 4
+        for (int blk = threadIdx.x; blk < nblk; blk += kBucketThreads) {
+            const int c = hist[b * nblk + blk];
+            t += c;
+            p += blk < me ? c : 0;
+        }
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) {
+            t += __shfl_xor(t, d, 64);
+            p += __shfl_xor(p, d, 64);
+        }
+        if (wave_lane() == 0) {   // one LDS atomic per wave
+            if (t) atomicAdd(&tot[b], t);
+            if (p) atomicAdd(&pre[b], p);
+        }
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -763,7 +778,6 @@ k_bucket_scatter(int n, const int* S_cp, const int* nI, BucketTable tab, const i
     __syncthreads();
     const int wv = threadIdx.x >> 6;
     const int lane = wave_lane();
-    const int64_t len = range_len(n);
     const int64_t j0 = (int64_t)me * len;
     const int64_t j1 = std::min<int64_t>(j0 + len, n);
     for (int64_t c0 = j0; c0 < j1; c0 += kBucketThreads) {
@@ -792,7 +806,6 @@ k_bucket_scatter(int n, const int* S_cp, const int* nI, BucketTable tab, const i
     }
 }
 
-static int bucket_blocks(int n) { return (int)ceil_div(std::max(n, 1), range_len(n)); }
 
 size_t bucket_temp_bytes(int n) {
     return (size_t)kBucketBlocks * kMaxBuckets * sizeof(int) + 512;
@@ -801,12 +814,13 @@ size_t bucket_temp_bytes(int n) {
 hipError_t bucket_sort(int n, const int* S_cp, const int* nI, BucketTable tab, int* queue, int* bstart,
                        int* unfit, unsigned long long* status, void* temp, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    const int nblk = bucket_blocks(n);
+    const int64_t len = range_len(n, tab.nb);
+    const int nblk = (int)ceil_div(n, len);
     int* hist = (int*)temp;
-    hipLaunchKernelGGL(k_bucket_hist, dim3(nblk), dim3(kBucketThreads), 0, s, n, S_cp, nI, tab, hist, unfit,
+    hipLaunchKernelGGL(k_bucket_hist, dim3(nblk), dim3(kBucketThreads), 0, s, n, len, S_cp, nI, tab, hist, unfit,
                        status);
-    hipLaunchKernelGGL(k_bucket_scatter, dim3(nblk), dim3(kBucketThreads), 0, s, n, S_cp, nI, tab, hist, queue,
-                       bstart);
+    hipLaunchKernelGGL(k_bucket_scatter, dim3(nblk), dim3(kBucketThreads), 0, s, n, len, S_cp, nI, tab, hist,
+                       queue, bstart);
     return hipGetLastError();
 }
 

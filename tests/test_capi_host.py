@@ -113,6 +113,16 @@ def test_empty_matrices_rejected(hctx):
     assert "stored entries" in lib.sam_last_error(h).decode()
 
 
+def test_empty_sequence_rejected(hctx):
+    lib, h = hctx
+    sq = ctypes.c_void_p()
+    a = csc(n=0, nnz=0)
+    spec = C.sam_pattern_spec(0, 2, 0.0, -1, 0.0, 1)
+    assert lib.sam_sequence_create(h, ctypes.byref(a), ctypes.byref(a), ctypes.byref(spec), 2, 1, 1,
+                                   ctypes.byref(sq), None) == 1
+    assert "empty" in lib.sam_last_error(h).decode()
+
+
 def test_menu_without_device():
     from paper_2406_17656_amd import autotune
     for prec in ("f32", "f64"):
