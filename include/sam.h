@@ -224,7 +224,10 @@ sam_status sam_plan_select(sam_plan* plan, sam_precision prec, const int32_t* or
  * NULL).  res2 (optional device scalar) receives sum_j rho_j =
  * ||A_k M - A_0||_F^2, summed in a fixed order (bitwise reproducible).
  * Ak_val and A0_val are the values matching the plan's structures.
- * Allocates nothing; safe to capture in a HIP graph.
+ * Allocates nothing; safe to capture in a HIP graph.  Calls on one plan
+ * (builds and sam_backward) must not overlap in time: they share the plan's
+ * scratch (column residuals when col_res2 is NULL, the residual sum's
+ * partials).
  * Async errors (sam_sync_status): SAM_ERR_RANK, SAM_ERR_NONFINITE. */
 sam_status sam_build_planned(sam_plan* plan, const double* Ak_val, const double* A0_val,
                              sam_precision prec, void* M_val, double* col_res2, double* res2,
