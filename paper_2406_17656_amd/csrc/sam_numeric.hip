@@ -652,6 +652,8 @@ const NumericVariant kMenu[] = {
     SAM_VARIANT(float, 1, 2, 8, 8, 4, 3, false),
     SAM_VARIANT(float, 1, 4, 7, 13, 2, 2, false),
     SAM_VARIANT(float, 1, 4, 8, 16, 2, 2, false),
+    SAM_VARIANT(float, 1, 8, 5, 20, 1, 2, false),   // ragged 9-point / thresholded blocks
+    SAM_VARIANT(float, 1, 8, 6, 24, 1, 2, false),
     SAM_VARIANT(float, 1, 16, 4, 25, 1, 1, false),
     SAM_VARIANT(float, 1, 32, 4, 32, 1, 1, false),
     SAM_VARIANT(float, 1, 1, 13, 5, 1, 5, false),   // one problem per lane, no reductions
