@@ -267,6 +267,7 @@ def main():
     variants = {"f32_level2_replanned": {"cols_per_s": value, "ms_per_step": wall * 1e3},
                 "f32_level2_numeric_build_us": build_ms * 1e3}
     eq = None
+    level_r2 = {}
     if not args.no_variants:
         plan.select(tuned_order("f64", 2), "f64")
         b64 = time_build("f64")
@@ -277,6 +278,8 @@ def main():
                 log(f"timing: static sequence {prec} level {power}")
                 w, e, r2 = time_sequence(prec, power, False, max(5, args.steps // 2), 2)
                 variants[f"{prec}_level{power}_static"] = {"cols_per_s": cols / w, "ms_per_step": w * 1e3}
+                if prec == "f32":
+                    level_r2[power] = r2
                 if prec == "f64" and power == 2:
                     r2_f64 = r2
         w, e, _ = time_sequence("f64", 2, True, max(5, args.steps // 2), 2)
@@ -292,6 +295,23 @@ def main():
             pl.close()
         torch.cuda.synchronize()
         variants["f32_level2_oneshot_api"] = {"cols_per_s": cols / (time.perf_counter() - t0)}
+        # adaptive patterns on the first source: level 1 plus, per column, the
+        # k level-2 candidates with the most negative dL/dw (weights 0.1)
+        from paper_2406_17656_amd.adaptive import adaptive_map
+        log("adaptive patterns: level 1 + top-k level-2 candidates by the adjoint")
+        ad = {"level1": {"nnz": None, "rel_res": float(np.sqrt(level_r2[1][0] / a02))},
+              "level2": {"nnz": None, "rel_res": float(np.sqrt(level_r2[2][0] / a02))}}
+        for p_, key in ((1, "level1"), (2, "level2")):
+            ad[key]["nnz"] = int(ctx.pattern(dAk[0], p_)[1].numel())
+        for kk in (1, 2, 4):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            cp, ri, M, r2a, _ = adaptive_map(ctx, dAk[0], dA0, kk, w_cand=0.1, prec="f32")
+            ctx.sync_status()
+            dt = time.perf_counter() - t0
+            ad[f"level1_plus_top{kk}"] = {"nnz": int(ri.numel()), "rel_res": float(np.sqrt(float(r2a.cpu()[0]) / a02)),
+                                          "ms_whole_pipeline": dt * 1e3}
+        variants["adaptive_map0"] = ad
     else:
         plan.close()
     rel_res = [float(np.sqrt(r / a02)) for r in r2_f32]

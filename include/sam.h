@@ -177,8 +177,8 @@ sam_status sam_plan_create(sam_ctx* ctx, const sam_csc* Ak, const sam_csc* A0,
                            const int32_t* S_colptr, const int32_t* S_rowind, int64_t nnz_S,
                            sam_plan** plan, sam_stream_t stream);
 
-/* Release a plan (NULL allowed).  Frees device memory: the caller must make
- * sure no enqueued work still uses it. */
+/* Release a plan (NULL allowed).  Synchronises the device first, so work
+ * still enqueued on the plan finishes before its memory is freed. */
 sam_status sam_plan_destroy(sam_plan* plan);
 
 /* Shape statistics of a plan (host outputs, any may be NULL): number of
@@ -339,6 +339,41 @@ sam_status sam_backward(sam_plan* plan, const double* Ak_val, const double* A0_v
                         const double* w, double mu, double dL, sam_precision prec,
                         double* gAk, double* gA0, double* gw, double* loss,
                         sam_stream_t stream);
+
+/* ------------------------------------------------------ adaptive patterns */
+
+/* The paper leaves adaptive patterns as future work (end of Section 2;
+ * Section 6).  These calls build one from the soft-weighted map's adjoint:
+ * weight the entries of a candidate pattern S (e.g. S(A_k^2)) that are not in
+ * a base pattern B (e.g. S(A_k)), take dL/dw from sam_backward, and keep per
+ * column the base entries plus the k candidates whose admission lowers the
+ * loss fastest. */
+
+/* w[e] (device, nnz_S entries, overwritten) = w_base where entry e of S is
+ * also in B (same column and row), w_cand elsewhere.  S and B are CSC
+ * patterns on the device with rows ascending per column.  Errors:
+ * SAM_ERR_ARG (NULL, negative sizes), SAM_ERR_SHAPE / SAM_ERR_UNSORTED (the
+ * column pointers, checked on the host), SAM_ERR_OVERFLOW.  Synchronising
+ * (the column-pointer check). */
+sam_status sam_candidate_weights(sam_ctx* ctx, int32_t n, const int32_t* S_colptr, const int32_t* S_rowind,
+                                 int64_t nnz_S, const int32_t* B_colptr, const int32_t* B_rowind, int64_t nnz_B,
+                                 double w_base, double w_cand, double* w, sam_stream_t stream);
+
+/* Top-k selection: column j of the output keeps, in S's (ascending) order,
+ * every entry of S(:, j) with w >= 1 and the k entries with w < 1 that have
+ * the smallest grad (NaN counts as +inf; ties go to the smaller row).  grad
+ * is typically sam_backward's gw (negative: admitting the entry lowers the
+ * loss).  out_colptr (n+1) and out_rowind (at most nnz_S entries) are device
+ * arrays of the caller; *nnz_out (host) receives the output size.  Errors as
+ * for sam_candidate_weights, and SAM_ERR_ARG for k < 0.  Synchronising. */
+sam_status sam_pattern_topk(sam_ctx* ctx, int32_t n, const int32_t* S_colptr, const int32_t* S_rowind,
+                            int64_t nnz_S, const double* w, const double* grad, int32_t k, int32_t* out_colptr,
+                            int32_t* out_rowind, int64_t* nnz_out, sam_stream_t stream);
+
+/* The penalty scale of the soft weights: *mu (host) = ||A_k||_F^2 / n, the
+ * mean squared column norm (a fixed scalar, not differentiated).  Errors:
+ * SAM_ERR_ARG (NULL, n = 0, no values).  Synchronising. */
+sam_status sam_penalty_scale(sam_ctx* ctx, const sam_csc* Ak, double* mu, sam_stream_t stream);
 
 #ifdef __cplusplus
 }

@@ -16,6 +16,10 @@ columns).  Each wrapper names the passage of the paper it follows:
 * ``apply``      -- y = M x (definition).
 * ``backward``   -- exact gradient of ||A_k M - A_0||_F^2 (not in the paper;
                     derived from the normal equations, see sam_oracle.c).
+* ``candidate_weights``, ``select_topk`` -- the adaptive-pattern step the
+                    paper leaves as future work (end of Section 2): weights
+                    over a candidate pattern, and per column the base entries
+                    plus the k candidates of smallest gradient (definitions).
 """
 from __future__ import annotations
 
@@ -197,3 +201,37 @@ def backward(Ak, A0, S: Pattern, weights=None, mu=0.0, dL=1.0):
     if st:
         raise OracleError(st, int(bad[0]))
     return gAk, gA0, gw, float(loss[0])
+
+
+def candidate_weights(S: Pattern, B: Pattern, w_base=1.0, w_cand=0.1) -> np.ndarray:
+    """w[e] = w_base when entry e of S (row, column) is also an entry of B,
+    w_cand otherwise (plain set membership per column)."""
+    w = np.full(S.nnz, float(w_cand))
+    for j in range(S.n):
+        base = set(int(r) for r in B.rowind[B.colptr[j]:B.colptr[j + 1]])
+        for e in range(S.colptr[j], S.colptr[j + 1]):
+            if int(S.rowind[e]) in base:
+                w[e] = float(w_base)
+    return w
+
+
+def select_topk(S: Pattern, w, grad, k: int) -> Pattern:
+    """Per column j: the entries of S(:, j) with w >= 1, and the k entries
+    with w < 1 ordered first by (grad ascending, NaN as +inf; row ascending);
+    kept in S's row order.  Vectorised: candidates sorted by (column, grad,
+    row); the rank of a candidate is its position within its column."""
+    w = np.asarray(w, dtype=np.float64)
+    g = np.asarray(grad, dtype=np.float64)
+    g = np.where(np.isnan(g), np.inf, g)
+    col = np.repeat(np.arange(S.n), np.diff(S.colptr))
+    row = np.asarray(S.rowind, dtype=np.int64)
+    keep = w >= 1.0
+    cand = np.flatnonzero(~keep)
+    order = cand[np.lexsort((row[cand], g[cand], col[cand]))]
+    ccol = col[order]
+    first = np.searchsorted(ccol, ccol, side="left")
+    rank = np.arange(order.size) - first
+    keep[order[rank < k]] = True
+    counts = np.bincount(col[keep], minlength=S.n)
+    colptr = np.concatenate([[0], np.cumsum(counts)]).astype(np.int32)
+    return Pattern(S.n, colptr, np.asarray(S.rowind)[keep].astype(np.int32))

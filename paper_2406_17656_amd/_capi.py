@@ -77,6 +77,9 @@ SIGNATURES = {
     "sam_sequence_run": (c_int32, [P, P, P, P, P]),
     "sam_build_weighted": (c_int32, [P, P, P, P, c_double, c_int32, P, P, P, P]),
     "sam_backward": (c_int32, [P, P, P, P, c_double, c_double, c_int32, P, P, P, P, P]),
+    "sam_candidate_weights": (c_int32, [P, c_int32, P, P, c_int64, P, P, c_int64, c_double, c_double, P, P]),
+    "sam_pattern_topk": (c_int32, [P, c_int32, P, P, c_int64, P, P, c_int32, P, P, ctypes.POINTER(c_int64), P]),
+    "sam_penalty_scale": (c_int32, [P, CSCP, ctypes.POINTER(c_double), P]),
 }
 
 

@@ -19,8 +19,8 @@ OBJDIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libsam_mi355x.so")
 ARCH = "gfx950"
 
-SOURCES = ["sam_symbolic.hip", "sam_numeric.hip", "sam_aux.hip", "sam_adjoint.hip", "sam_capi.cpp",
-           "sam_sequence.cpp", "sam_backward.cpp"]
+SOURCES = ["sam_symbolic.hip", "sam_numeric.hip", "sam_aux.hip", "sam_adjoint.hip", "sam_adaptive.hip", "sam_capi.cpp",
+           "sam_sequence.cpp", "sam_backward.cpp", "sam_adaptive_api.cpp"]
 HEADERS = ["sam_device.hpp", "sam_kernels.hpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -605,7 +605,10 @@ sam_status sam_plan_create(sam_ctx* ctx, const sam_csc* Ak, const sam_csc* A0, c
 
 sam_status sam_plan_destroy(sam_plan* plan) {
     if (!plan) return SAM_OK;
-    if (plan->ctx && plan->ctx->device != SAM_NO_DEVICE) (void)hipSetDevice(plan->ctx->device);
+    if (plan->ctx && plan->ctx->device != SAM_NO_DEVICE) {
+        (void)hipSetDevice(plan->ctx->device);
+        (void)hipDeviceSynchronize();   // no launch on the plan's memory is still running
+    }
     release(plan->mem);
     release(plan->bwd);
     delete plan;

@@ -172,4 +172,16 @@ hipError_t spmv_rows(int n, const int* rowptr, const int* colind, const int* per
 hipError_t backward_scatter(int n, const int* Ak_cp, const int* ST_rowptr, const int* ST_perm,
                             const int64_t* segoff, const double* contrib, double* gAk, hipStream_t s);
 
+// ------------------------------------------------------ adaptive patterns
+// w over S's entries: w_base where the entry is in B (same columns, rows
+// ascending), w_cand elsewhere.
+hipError_t candidate_weights(int n, const int* S_cp, const int* S_ri, const int* B_cp, const int* B_ri,
+                             double w_base, double w_cand, double* w, hipStream_t s);
+// Per column: the entries with w >= 1 and the k entries with w < 1 of
+// smallest grad (NaN last, ties to the smaller row), in S's order.
+hipError_t topk_count(int n, const int* S_cp, const int* S_ri, const double* w, const double* grad, int k,
+                      int* counts, hipStream_t s);
+hipError_t topk_fill(int n, const int* S_cp, const int* S_ri, const double* w, const double* grad, int k,
+                     const int* out_cp, int* out_ri, hipStream_t s);
+
 }  // namespace samk

@@ -183,6 +183,35 @@ class Context:
                                       _ptr(x), _ptr(y), self.stream()))
         return y
 
+    # -- adaptive patterns (future work of the paper, end of Section 2)
+    def candidate_weights(self, S_colptr, S_rowind, B_colptr, B_rowind, w_base=1.0, w_cand=0.1):
+        """sam_candidate_weights: w over S's entries, w_base on B's entries."""
+        n = S_colptr.numel() - 1
+        w = torch.empty(max(int(S_rowind.numel()), 1), dtype=torch.float64, device=S_colptr.device)
+        self.check(self.lib.sam_candidate_weights(self.h, n, _ptr(S_colptr), _ptr(S_rowind), int(S_rowind.numel()),
+                                                  _ptr(B_colptr), _ptr(B_rowind), int(B_rowind.numel()),
+                                                  float(w_base), float(w_cand), _ptr(w), self.stream()))
+        return w[:S_rowind.numel()]
+
+    def pattern_topk(self, S_colptr, S_rowind, w, grad, k):
+        """sam_pattern_topk: base entries (w >= 1) plus the k smallest-grad candidates per column."""
+        n = S_colptr.numel() - 1
+        nnz = int(S_rowind.numel())
+        dev = S_colptr.device
+        cp = torch.empty(n + 1, dtype=torch.int32, device=dev)
+        ri = torch.empty(max(nnz, 1), dtype=torch.int32, device=dev)
+        out = ctypes.c_int64()
+        self.check(self.lib.sam_pattern_topk(self.h, n, _ptr(S_colptr), _ptr(S_rowind), nnz, _ptr(w), _ptr(grad),
+                                             int(k), _ptr(cp), _ptr(ri), ctypes.byref(out), self.stream()))
+        return cp, ri[:out.value]
+
+    def penalty_scale(self, Ak: DeviceCSC) -> float:
+        """sam_penalty_scale: ||A_k||_F^2 / n."""
+        a = Ak.struct()
+        mu = ctypes.c_double()
+        self.check(self.lib.sam_penalty_scale(self.h, ctypes.byref(a), ctypes.byref(mu), self.stream()))
+        return mu.value
+
     # -- sequence
     def sequence(self, A0: DeviceCSC, Ak_struct: DeviceCSC, n_src: int, prec="f32", power=1,
                  kind="none", replan_each_run=False, **kw) -> "Sequence":
