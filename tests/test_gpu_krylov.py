@@ -1,0 +1,59 @@
+"""The map as a preconditioner update in GMRES, with the sparse products in
+the library: the exact map (S full, n = 25) makes A_k N_k = A_0, so GMRES on
+A_k with N_k P_0 takes the iterations of A_0 with P_0; on a 64 x 64 sequence
+the level-2 map and the frozen preconditioner both reach the tolerance."""
+import numpy as np
+import pytest
+import torch
+
+import pde_inputs as P
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2406_17656_amd import Context
+    c = Context(0)
+    yield c
+    torch.cuda.synchronize()
+    c.close()
+
+
+def dev(A):
+    from paper_2406_17656_amd import DeviceCSC
+    return DeviceCSC.from_host(A)
+
+
+def test_exact_map_gives_target_iterations(ctx):
+    from paper_2406_17656_amd.krylov import solve_with_map
+    A0h, Ash = P.config2(m=5, nmat=2)
+    A0, Ak = dev(A0h), dev(Ash[0])
+    n = A0h.n
+    cp = torch.arange(0, n * n + 1, n, dtype=torch.int32, device="cuda")
+    ri = torch.arange(n, dtype=torch.int32, device="cuda").repeat(n)
+    M, _, _ = ctx.build(Ak, A0, cp, ri, "f64")
+    ctx.sync_status()
+    b = torch.as_tensor(np.random.default_rng(0).standard_normal(n)).cuda()
+    _, its_map, _ = solve_with_map(ctx, Ak, A0, cp, ri, M, b, prec="f64", tol=1e-10, restart=30)
+    _, its_target, _ = solve_with_map(ctx, A0, A0, None, None, None, b, tol=1e-10, restart=30)
+    assert abs(its_map - its_target) <= 1, (its_map, its_target)
+
+
+def test_sequence_map_converges(ctx):
+    from paper_2406_17656_amd.krylov import solve_with_map
+    A0h, Ash = P.config2(m=64, nmat=3)
+    A0 = dev(A0h)
+    b = torch.as_tensor(np.random.default_rng(1).standard_normal(A0h.n)).cuda()
+    for Ah in Ash:
+        Ak = dev(Ah)
+        cp, ri = ctx.pattern(Ak, 2)
+        M, _, _ = ctx.build(Ak, A0, cp, ri, "f32")
+        ctx.sync_status()
+        for Mv in (M, None):
+            x, its, hist = solve_with_map(ctx, Ak, A0, cp, ri, Mv, b, prec="f32", tol=1e-8, restart=50,
+                                          maxiter=3000)
+            assert hist[-1] <= 1e-8 * 1.01, (its, hist[-1])   # the last entry is the true residual
+            from paper_2406_17656_amd.krylov import SparseOp
+            r = b - SparseOp(ctx, Ak.n, Ak.colptr, Ak.rowind, Ak.val)(x)
+            assert float(torch.linalg.vector_norm(r) / torch.linalg.vector_norm(b)) <= 1.01e-8
