@@ -210,9 +210,8 @@ k_numeric(NumericArgs a) {
             for (int s = 0; s < LPL; ++s) {
                 const bool ok = g + s * G < len;
                 const int p = ld_u8(rPA, po + s * G);
-                const double v = ld_f64(rAv, vo + s * G * 8);
                 pp[c][s] = ok ? p : trash;
-                pv[c][s] = ok ? v : 0.0;
+                pv[c][s] = ld_f64(rAv, vo + s * G * 8);   // masked entries land in the scratch row
             }
         }
         TQ A[R][NC];
@@ -265,7 +264,8 @@ k_numeric(NumericArgs a) {
 #pragma unroll
         for (int t = 0; t < R; ++t) bq[t] = (TQ)bsh[q * RS + t * G + g];
 
-        // ---- Householder QR (dgeqr2 conventions), applied to b as well
+        // ---- Householder QR (dgeqr2's sign convention, beta = -sign(alpha) ||x||),
+        //      applied to b as well
         TQ rdiag[NC], rinv[NC];
 #pragma unroll
         for (int k = 0; k < NC; ++k) {
@@ -286,8 +286,13 @@ k_numeric(NumericArgs a) {
             const TQ nrm = root<TQ>(alp * alp + sig);
             const TQ beta = zero ? alp : -copysign(nrm, alp);
             const TQ ib = recip<TQ>(beta);
-            const TQ tau = zero ? (TQ)0 : (beta - alp) * ib;
-            const TQ scal = zero ? (TQ)0 : recip<TQ>(alp - beta);
+            // H = I - sigma u u^T with the unnormalised vector u = x - beta e_k
+            // (u_k = alpha - beta, x below the diagonal): the reflector of the
+            // normalised form (v_k = 1, tau = (beta - alpha) / beta) without the
+            // scaling of v; sigma = 1 / (beta (beta - alpha)), 0 when x is
+            // already a multiple of e_k.  Entries below the diagonal are not
+            // read again.
+            const TQ sigma = zero ? (TQ)0 : recip<TQ>(beta * (beta - alp));
             rdiag[k] = beta;
             rinv[k] = ib;
             TQ v[R];
@@ -295,8 +300,8 @@ k_numeric(NumericArgs a) {
             for (int t = tk; t < R; ++t) {
                 const bool below = (t > tk) || (g > gk);
                 const bool diag = (t == tk) && (g == gk);
-                v[t] = below ? A[t][k] * scal : (diag ? (TQ)1 : (TQ)0);
-                A[t][k] = below ? v[t] : (diag ? beta : A[t][k]);
+                v[t] = below ? A[t][k] : (diag ? alp - beta : (TQ)0);
+                if (diag) A[t][k] = beta;
             }
             TQ w[NC + 1];
 #pragma unroll
@@ -310,8 +315,8 @@ k_numeric(NumericArgs a) {
 #pragma unroll
             for (int t = tk; t < R; ++t) wb += v[t] * bq[t];
 #pragma unroll
-            for (int c = k + 1; c < NC; ++c) w[c] = group_sum<G>(w[c]) * tau;
-            wb = group_sum<G>(wb) * tau;
+            for (int c = k + 1; c < NC; ++c) w[c] = group_sum<G>(w[c]) * sigma;
+            wb = group_sum<G>(wb) * sigma;
 #pragma unroll
             for (int c = k + 1; c < NC; ++c)
 #pragma unroll
@@ -477,19 +482,23 @@ k_numeric(NumericArgs a) {
             double rr_it = 0.0;
 #pragma unroll
             for (int it = 0; it < (WEIGHTED ? 2 : 1); ++it) {
-                reset(rsh, true);
+                // the plain map needs b no more after this step: r = b - A m
+                // is formed in place (scratch row cleared)
+                double* rv = (WEIGHTED || BACKWARD) ? rsh : bsh + q * RS;
+                if constexpr (WEIGHTED || BACKWARD) reset(rv, true);
+                else rv[trash] = 0.0;
                 load_entries();
                 wave_sync();
-                scatter(rsh, m64, -1.0);
+                scatter(rv, m64, -1.0);
                 double r2 = 0.0;
 #pragma unroll
                 for (int t = 0; t < R; ++t) {
-                    const double x = rsh[t * G + g];
+                    const double x = rv[t * G + g];
                     r2 += (t * G + g < nIj) ? x * x : 0.0;
                 }
                 rr_it = group_sum<G>(r2);
                 double gA[NC], gc[NC], dl[NC];
-                gather(rsh, gA);
+                gather(rv, gA);
 #pragma unroll
                 for (int c = 0; c < NC; ++c) gc[c] = WEIGHTED ? gA[c] - pen[c] * m64[c] : gA[c];
                 const double yy = solve_normal(gc, dl);
