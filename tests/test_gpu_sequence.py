@@ -61,6 +61,16 @@ def test_sequence_structural(ctx, prec, replan):
     seq.close()
 
 
+@pytest.mark.parametrize("power", [1, 3])
+def test_sequence_replanned_powers(ctx, power):
+    """Power 1 (B is the pattern: no fused pass) and power 3 (an
+    intermediate level, then the last level fused with the row sets)."""
+    A0, As = P.config2(m=24, nmat=3)
+    seq, dAs, Ms, res2 = run_seq(ctx, A0, As, "f32", replan=True, power=power)
+    check_maps(ctx, seq, A0, As, Ms, res2, "f32", power)
+    seq.close()
+
+
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 def test_sequence_thresholded(ctx, prec):
     """Value-dependent patterns: global threshold then level 2, replanned on
