@@ -187,7 +187,7 @@ sam_status compute_pattern(sam_ctx* ctx, const sam_csc* Ak, const sam_pattern_sp
         HIP_TRY(ctx, grow(ncp, (size_t)(n + 1) * 4));
         HIP_TRY(ctx, grow(nri, (size_t)std::max<int64_t>(tot, 1) * 4));
         HIP_TRY(ctx, samk::scan_counts(counts, n, off, (int*)ncp.p, flags, stemp, s));
-        HIP_TRY(ctx, samk::expand_fill(n, cur_cp, cur_ri, B_cp, B_ri, (int*)ncp.p, (int*)nri.p, cur_max, s));
+        HIP_TRY(ctx, samk::expand_fill(n, cur_cp, cur_ri, B_cp, B_ri, (int*)ncp.p, (int*)nri.p, cur_max, maxB, s));
         HIP_TRY(ctx, keep_level(lev, (const int*)ncp.p));
         cur_cp = (int*)ncp.p;
         cur_ri = (int*)nri.p;
@@ -526,10 +526,16 @@ sam_status sam_plan_create(sam_ctx* ctx, const sam_csc* Ak, const sam_csc* A0, c
     void* btemp = tw.take<char>(samk::bucket_temp_bytes(n));
     int* flags = tw.take<int>(4);
 
-    // S's column pointers are checked on the host before any kernel reads S
+    // S's column pointers are checked on the host before any kernel reads S;
+    // the longest column of A_k sizes the positions launch
     std::vector<int> hcp((size_t)n + 1, 0);
     int longest = 0;
     if (n > 0) {
+        std::vector<int> hak((size_t)n + 1);
+        if ((he = hipMemcpyAsync(hak.data(), Ak->colptr, hak.size() * 4, hipMemcpyDeviceToHost, s)) != hipSuccess ||
+            (he = hipStreamSynchronize(s)) != hipSuccess)
+            return bail(fail(ctx, SAM_ERR_HIP, "reading Ak colptr: %s", hipGetErrorString(he)));
+        for (int j = 0; j < n; ++j) pl->max_len_A = std::max(pl->max_len_A, hak[(size_t)j + 1] - hak[(size_t)j]);
         if ((he = hipMemcpyAsync(hcp.data(), S_colptr, (size_t)(n + 1) * 4, hipMemcpyDeviceToHost, s)) != hipSuccess ||
             (he = hipStreamSynchronize(s)) != hipSuccess)
             return bail(fail(ctx, SAM_ERR_HIP, "reading S_colptr: %s", hipGetErrorString(he)));
@@ -580,7 +586,8 @@ sam_status sam_plan_create(sam_ctx* ctx, const sam_csc* Ak, const sam_csc* A0, c
         std::vector<int> hnI(n);
         if ((he = hipMemcpyAsync(pl->eoff, off, (size_t)(n + 1) * 8, hipMemcpyDeviceToDevice, s)) != hipSuccess ||
             (he = samk::plan_positions(n, S_colptr, S_rowind, Ak->colptr, Ak->rowind, A0->colptr, A0->rowind,
-                                       pl->eoff, pl->nI, pl->posA, pl->posB, longest, s)) != hipSuccess)
+                                       pl->eoff, pl->nI, pl->posA, pl->posB, longest, pl->max_len_A, s)) !=
+                hipSuccess)
             return bail(fail(ctx, SAM_ERR_HIP, "plan positions: %s", hipGetErrorString(he)));
         if ((he = hipMemcpyAsync(hnI.data(), pl->nI, (size_t)n * 4, hipMemcpyDeviceToHost, s)) != hipSuccess ||
             (he = hipStreamSynchronize(s)) != hipSuccess)

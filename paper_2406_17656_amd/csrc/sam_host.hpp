@@ -52,6 +52,7 @@ struct sam_plan {
     int64_t nnzS = 0;
     const int *Ak_cp = nullptr, *Ak_ri = nullptr, *A0_cp = nullptr, *A0_ri = nullptr;
     const int *S_cp = nullptr, *S_ri = nullptr;
+    int max_len_A = 0;             // longest column of A_k
     DevBuf mem;          // nI, eoff, posA, posB, queues, colbuf, reduce temp
     int* nI = nullptr;
     int64_t* eoff = nullptr;

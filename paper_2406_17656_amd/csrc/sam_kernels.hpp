@@ -42,18 +42,19 @@ hipError_t sparsify_fill(int n, const int* cp, const int* ri, const double* v,
 hipError_t sparsify_slots(int n, const int* cp, const int* ri, const double* v, SparsifySpec sp,
                           double* dscratch, const int* slot_cp, int* slot_ri, int* counts, hipStream_t s);
 // out(:,j) = union of rows(Q(:,l)) over l in P(:,j); count then fill.
-// max_lists bounds the lists per column of P (<= 0: unknown); it only picks
-// how many lists the kernel holds in registers.
+// max_lists bounds the lists per column of P, max_len the entries per list
+// of Q (<= 0: unknown); they only pick how much the kernel holds in
+// registers.
 hipError_t expand_count(int n, const int* P_cp, const int* P_ri, const int* Q_cp, const int* Q_ri,
                         int* counts, int* bad, int max_lists, hipStream_t s);
 hipError_t expand_fill(int n, const int* P_cp, const int* P_ri, const int* Q_cp, const int* Q_ri,
-                       const int* out_cp, int* out_ri, int max_lists, hipStream_t s);
+                       const int* out_cp, int* out_ri, int max_lists, int max_len, hipStream_t s);
 // Slot form: P and Q given as (cp, cnt, ri) with list l at cp[l], length
 // cnt[l]; the union of column j goes to slot_ri[slot_cp[j]..], its length to
 // counts[j].  The slots must be large enough (the structural bound).
 hipError_t expand_slots(int n, const int* P_cp, const int* P_cnt, const int* P_ri, const int* Q_cp,
                         const int* Q_cnt, const int* Q_ri, const int* slot_cp, int* slot_ri, int* counts,
-                        int max_lists, hipStream_t s);
+                        int max_lists, int max_len, hipStream_t s);
 
 // ------------------------------------------------------------------ plan
 // Per column j: E_j = sum_{l in J_j} nnz(A_k(:,l)).
@@ -66,14 +67,14 @@ hipError_t plan_gather_count(int n, const int* S_cp, const int* S_ri, const int*
 hipError_t plan_positions(int n, const int* S_cp, const int* S_ri, const int* Ak_cp,
                           const int* Ak_ri, const int* A0_cp, const int* A0_ri,
                           const int64_t* eoff, int* nI, unsigned char* posA,
-                          unsigned char* posB, int max_lists, hipStream_t s);
+                          unsigned char* posB, int max_lists, int max_len, hipStream_t s);
 // Same with S in slots (S_cnt lengths); also writes the compact copy of S
 // (cS_ri at the offsets cS_cp) when cS_ri is given.  eoff may be any layout
 // whose column ranges hold the gathered entries (e.g. the structural one).
 hipError_t plan_positions_slots(int n, const int* S_cp, const int* S_cnt, const int* S_ri, const int* cS_cp,
                                 int* cS_ri, const int* Ak_cp, const int* Ak_ri, const int* A0_cp,
                                 const int* A0_ri, const int64_t* eoff, int* nI, unsigned char* posA,
-                                unsigned char* posB, int max_lists, hipStream_t s);
+                                unsigned char* posB, int max_lists, int max_len, hipStream_t s);
 
 constexpr int kMaxBuckets = 16;
 struct BucketTable {

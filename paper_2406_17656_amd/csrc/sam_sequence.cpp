@@ -111,7 +111,8 @@ sam_status enqueue_replanned(sam_seq* q, int k, const double* vals, void* M, dou
         int* dri = lev == p - 1 ? q->F_ri : q->L_ri[lev & 1];
         int* dcnt = lev == p - 1 ? q->F_cnt : q->L_cnt[lev & 1];
         HIP_TRY(ctx, samk::expand_slots(n, level_cp(lev - 1), cur_cnt, cur_ri, level_cp(0), q->B_cnt, q->B_ri,
-                                        level_cp(lev), dri, dcnt, q->levels.maxcol[(size_t)lev - 1], s));
+                                        level_cp(lev), dri, dcnt, q->levels.maxcol[(size_t)lev - 1],
+                                        q->levels.maxcol[0], s));
         cur_ri = dri;
         cur_cnt = dcnt;
     }
@@ -123,7 +124,7 @@ sam_status enqueue_replanned(sam_seq* q, int k, const double* vals, void* M, dou
     pl->S_ri = Sri;
     HIP_TRY(ctx, samk::plan_positions_slots(n, level_cp(p - 1), q->F_cnt, q->F_ri, Scp, Sri, q->Ak_cp, q->Ak_ri,
                                             q->A0_cp, q->A0_ri, pl->eoff, pl->nI, pl->posA, pl->posB,
-                                            q->plan->max_cols, s));
+                                            q->plan->max_cols, q->plan->max_len_A, s));
     Combo& cb = pl->combo[q->prec][0];
     HIP_TRY(ctx, samk::bucket_sort(n, Scp, pl->nI, cb.tab, cb.queue, cb.bstart, nullptr, ctx->d_status, q->btemp, s));
     return run_numeric(pl, vals, q->A0_val, nullptr, 0.0, q->prec, 0, M, nullptr, res2, s);

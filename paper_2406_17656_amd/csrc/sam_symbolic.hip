@@ -318,7 +318,6 @@ hipError_t sparsify_slots(int n, const int* cp, const int* ri, const double* v, 
 constexpr int kChunkWords = 128;
 constexpr int kChunk = kChunkWords * 32;  // 4096 rows
 constexpr int kSymThreads = 256;
-constexpr int kListLen = 8;               // entries per list held in registers
 
 template <int CTRL>
 __device__ inline int dppi(int v) { return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false); }
@@ -408,7 +407,7 @@ struct UnionArgs {
 
 // ROUNDS lists per lane (GS * ROUNDS per column) and their first kListLen
 // rows live in registers; longer columns or lists take the memory loops.
-template <int MODE, int GS, int ROUNDS>
+template <int MODE, int GS, int ROUNDS, int kListLen>
 __global__ void __launch_bounds__(kSymThreads)
 k_union(UnionArgs a) {
     constexpr int kGroups = kSymThreads / GS;
@@ -587,20 +586,30 @@ k_union(UnionArgs a) {
 
 // One list per lane while the columns allow (8 lanes per column up to 8
 // lists, 16 up to 16), then two per lane (32 lists in registers); beyond
-// that the memory loops.  max_lists <= 0: unknown.
-template <int MODE>
-static hipError_t launch_union(const UnionArgs& a, int max_lists, hipStream_t s) {
+// that the memory loops.  The rows held per list follow the longest list
+// (5, 8 or 12; longer lists take the memory loops).  Bounds <= 0: unknown.
+template <int MODE, int LEN>
+static hipError_t launch_union_len(const UnionArgs& a, int max_lists, hipStream_t s) {
     auto grid = [&](int gs) {
         return dim3((unsigned)std::min<int64_t>(ceil_div(a.n, kSymThreads / gs), 256 * 32));
     };
     const dim3 block(kSymThreads);
     if (max_lists > 0 && max_lists <= 8)
-        hipLaunchKernelGGL((k_union<MODE, 8, 1>), grid(8), block, 0, s, a);
+        hipLaunchKernelGGL((k_union<MODE, 8, 1, LEN>), grid(8), block, 0, s, a);
     else if (max_lists > 0 && max_lists <= 16)
-        hipLaunchKernelGGL((k_union<MODE, 16, 1>), grid(16), block, 0, s, a);
+        hipLaunchKernelGGL((k_union<MODE, 16, 1, LEN>), grid(16), block, 0, s, a);
     else
-        hipLaunchKernelGGL((k_union<MODE, 16, 2>), grid(16), block, 0, s, a);
+        hipLaunchKernelGGL((k_union<MODE, 16, 2, LEN>), grid(16), block, 0, s, a);
     return hipGetLastError();
+}
+
+template <int MODE>
+static hipError_t launch_union(const UnionArgs& a, int max_lists, int max_len, hipStream_t s) {
+    if constexpr (MODE != kModeCount) {   // the count pass (one-shot patterns) keeps 8 rows
+        if (max_len > 0 && max_len <= 5) return launch_union_len<MODE, 5>(a, max_lists, s);
+        if (max_len > 8) return launch_union_len<MODE, 12>(a, max_lists, s);
+    }
+    return launch_union_len<MODE, 8>(a, max_lists, s);
 }
 
 static UnionArgs union_args(int n) {
@@ -615,27 +624,27 @@ hipError_t expand_count(int n, const int* P_cp, const int* P_ri, const int* Q_cp
     UnionArgs a = union_args(n);
     a.P_cp = P_cp; a.P_ri = P_ri; a.Q_cp = Q_cp; a.Q_ri = Q_ri;
     a.counts = counts; a.bad = bad;
-    return launch_union<kModeCount>(a, max_lists, s);
+    return launch_union<kModeCount>(a, max_lists, 0, s);
 }
 
 hipError_t expand_fill(int n, const int* P_cp, const int* P_ri, const int* Q_cp, const int* Q_ri,
-                       const int* out_cp, int* out_ri, int max_lists, hipStream_t s) {
+                       const int* out_cp, int* out_ri, int max_lists, int max_len, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     UnionArgs a = union_args(n);
     a.P_cp = P_cp; a.P_ri = P_ri; a.Q_cp = Q_cp; a.Q_ri = Q_ri;
     a.out_cp = out_cp; a.out_ri = out_ri;
-    return launch_union<kModeFill>(a, max_lists, s);
+    return launch_union<kModeFill>(a, max_lists, max_len, s);
 }
 
 hipError_t expand_slots(int n, const int* P_cp, const int* P_cnt, const int* P_ri, const int* Q_cp,
                         const int* Q_cnt, const int* Q_ri, const int* slot_cp, int* slot_ri, int* counts,
-                        int max_lists, hipStream_t s) {
+                        int max_lists, int max_len, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     UnionArgs a = union_args(n);
     a.P_cp = P_cp; a.P_cnt = P_cnt; a.P_ri = P_ri;
     a.Q_cp = Q_cp; a.Q_cnt = Q_cnt; a.Q_ri = Q_ri;
     a.out_cp = slot_cp; a.out_ri = slot_ri; a.counts = counts;
-    return launch_union<kModeFill>(a, max_lists, s);
+    return launch_union<kModeFill>(a, max_lists, max_len, s);
 }
 
 // ------------------------------------------------------------------ plan
@@ -665,22 +674,22 @@ hipError_t plan_gather_count(int n, const int* S_cp, const int* S_ri, const int*
 // not in I_j).  nI[j] = |I_j|.
 hipError_t plan_positions(int n, const int* S_cp, const int* S_ri, const int* Ak_cp, const int* Ak_ri,
                           const int* A0_cp, const int* A0_ri, const int64_t* eoff, int* nI,
-                          unsigned char* posA, unsigned char* posB, int max_lists, hipStream_t s) {
+                          unsigned char* posA, unsigned char* posB, int max_lists, int max_len, hipStream_t s) {
     return plan_positions_slots(n, S_cp, nullptr, S_ri, nullptr, nullptr, Ak_cp, Ak_ri, A0_cp, A0_ri, eoff, nI,
-                                posA, posB, max_lists, s);
+                                posA, posB, max_lists, max_len, s);
 }
 
 hipError_t plan_positions_slots(int n, const int* S_cp, const int* S_cnt, const int* S_ri, const int* cS_cp,
                                 int* cS_ri, const int* Ak_cp, const int* Ak_ri, const int* A0_cp,
                                 const int* A0_ri, const int64_t* eoff, int* nI, unsigned char* posA,
-                                unsigned char* posB, int max_lists, hipStream_t s) {
+                                unsigned char* posB, int max_lists, int max_len, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     UnionArgs a = union_args(n);
     a.P_cp = S_cp; a.P_cnt = S_cnt; a.P_ri = S_ri;
     a.Q_cp = Ak_cp; a.Q_ri = Ak_ri;
     a.counts = nI; a.eoff = eoff; a.posA = posA; a.A0_cp = A0_cp; a.A0_ri = A0_ri; a.posB = posB;
     a.cP_cp = cS_cp; a.cP_ri = cS_ri;
-    return launch_union<kModePositions>(a, max_lists, s);
+    return launch_union<kModePositions>(a, max_lists, max_len, s);
 }
 
 // --------------------------------------------------------------- buckets
