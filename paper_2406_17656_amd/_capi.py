@@ -19,6 +19,8 @@ c_char_p = ctypes.c_char_p
 P = c_void_p
 
 SAM_OK = 0
+(SAM_ERR_ARG, SAM_ERR_SHAPE, SAM_ERR_UNSORTED, SAM_ERR_OVERFLOW, SAM_ERR_RANK, SAM_ERR_NONFINITE, SAM_ERR_HIP,
+ SAM_ERR_UNSUPPORTED, SAM_ERR_NOMEM) = range(1, 10)
 STATUS_NAMES = {
     0: "SAM_OK", 1: "SAM_ERR_ARG", 2: "SAM_ERR_SHAPE", 3: "SAM_ERR_UNSORTED",
     4: "SAM_ERR_OVERFLOW", 5: "SAM_ERR_RANK", 6: "SAM_ERR_NONFINITE", 7: "SAM_ERR_HIP",

@@ -141,3 +141,32 @@ def test_plan_select_validation(hctx):
     # no plan: argument error before anything else
     arr = (ctypes.c_int32 * 1)(0)
     assert lib.sam_plan_select(None, 1, arr, 1, None) == 1
+
+
+def test_adaptive_calls_validate_arguments(hctx):
+    """Argument checks of the adaptive-pattern calls come before any device
+    work: NULLs, negative sizes and k < 0 are SAM_ERR_ARG, oversized patterns
+    SAM_ERR_OVERFLOW; valid arguments on a context without a device reach
+    SAM_ERR_UNSUPPORTED."""
+    lib, h = hctx
+    out = ctypes.c_int64()
+    w = ctypes.c_double()
+    # sam_candidate_weights(ctx, n, S_cp, S_ri, nnz_S, B_cp, B_ri, nnz_B, w_base, w_cand, w, stream)
+    assert lib.sam_candidate_weights(h, -1, 1, 1, 4, 1, 1, 4, 1.0, 0.1, 1, None) == C.SAM_ERR_ARG
+    assert lib.sam_candidate_weights(h, 4, None, 1, 4, 1, 1, 4, 1.0, 0.1, 1, None) == C.SAM_ERR_ARG
+    assert lib.sam_candidate_weights(h, 4, 1, 1, 4, 1, 1, 4, 1.0, 0.1, None, None) == C.SAM_ERR_ARG
+    assert lib.sam_candidate_weights(h, 4, 1, 1, 2 ** 31, 1, 1, 4, 1.0, 0.1, 1, None) == C.SAM_ERR_OVERFLOW
+    assert lib.sam_candidate_weights(h, 4, 1, 1, 4, 1, 1, 4, 1.0, 0.1, 1, None) == C.SAM_ERR_UNSUPPORTED
+    # sam_pattern_topk(ctx, n, S_cp, S_ri, nnz_S, w, grad, k, out_cp, out_ri, nnz_out, stream)
+    assert lib.sam_pattern_topk(h, 4, 1, 1, 4, 1, 1, -1, 1, 1, ctypes.byref(out), None) == C.SAM_ERR_ARG
+    assert lib.sam_pattern_topk(h, 4, 1, 1, 4, None, 1, 2, 1, 1, ctypes.byref(out), None) == C.SAM_ERR_ARG
+    assert lib.sam_pattern_topk(h, 4, 1, 1, 4, 1, 1, 2, 1, 1, None, None) == C.SAM_ERR_ARG
+    assert lib.sam_pattern_topk(h, 4, 1, 1, 4, 1, 1, 2, 1, 1, ctypes.byref(out), None) == C.SAM_ERR_UNSUPPORTED
+    # sam_penalty_scale(ctx, Ak, mu, stream)
+    a = csc()
+    assert lib.sam_penalty_scale(h, ctypes.byref(a), None, None) == C.SAM_ERR_ARG
+    e = csc(n=0, nnz=0)
+    assert lib.sam_penalty_scale(h, ctypes.byref(e), ctypes.byref(w), None) == C.SAM_ERR_ARG
+    nv = C.sam_csc(4, 4, 1, 1, None)
+    assert lib.sam_penalty_scale(h, ctypes.byref(nv), ctypes.byref(w), None) == C.SAM_ERR_ARG
+    assert lib.sam_penalty_scale(h, ctypes.byref(a), ctypes.byref(w), None) == C.SAM_ERR_UNSUPPORTED
