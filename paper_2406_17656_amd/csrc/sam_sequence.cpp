@@ -37,17 +37,25 @@ struct sam_seq {
     // replanning mode: every level of the pattern is written into slots laid
     // out like the structural level (lev_cp, p arrays of n+1), with its
     // column lengths beside it; only the final S_k is compacted (Sk_cp/Sk_ri)
+    // Two sets of scratch and plan arrays: the symbolic work of source k+1
+    // (set (k+1) % 2) runs while the numeric build of source k (set k % 2)
+    // still reads its plan.
+    struct Scratch {
+        sam_plan dplan;            // views into dyn
+        int *B_ri = nullptr, *B_cnt = nullptr, *L_ri[2] = {nullptr, nullptr}, *L_cnt[2] = {nullptr, nullptr},
+            *F_ri = nullptr, *F_cnt = nullptr;
+        int64_t* off = nullptr;
+        void *stemp = nullptr, *btemp = nullptr;
+        double* D = nullptr;
+    };
     DevBuf dyn;
     DevBuf lev_cp;
-    sam_plan dplan;                // views into dyn
+    Scratch part[2];
     std::vector<int*> Sk_cp, Sk_ri;
-    int *B_ri = nullptr, *B_cnt = nullptr, *L_ri[2] = {nullptr, nullptr}, *L_cnt[2] = {nullptr, nullptr},
-        *F_ri = nullptr, *F_cnt = nullptr, *flags = nullptr;
-    int64_t* off = nullptr;
-    void *stemp = nullptr, *btemp = nullptr;
-    double* D = nullptr;
-    // graph
-    hipStream_t cap = nullptr;
+    // graph: the symbolic chain runs on the capture stream, the numeric chain
+    // on cap2, joined by events (a parallel branch of the graph)
+    hipStream_t cap = nullptr, cap2 = nullptr;
+    std::vector<hipEvent_t> ev;    // 2 n_src + 1: symbolic done, numeric done, fork
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     std::vector<const void*> key;
@@ -86,13 +94,14 @@ void drop_graph(sam_seq* q) {
     q->key.clear();
 }
 
-// Symbolic work for source k (replanning mode), then its numeric build.
-// A sparsified level is a subset of the structural one, column by column,
-// so each level is written straight into the structural layout (one launch
-// per level, no count pass); the final level is compacted by the positions
-// kernel after one scan of its lengths, and the gathered entries of column j
-// go to the structural offsets eoff[j] of the static plan.
-sam_status enqueue_replanned(sam_seq* q, int k, const double* vals, void* M, double* res2, hipStream_t s) {
+// Symbolic work for source k (replanning mode) into scratch set R: the
+// pattern, row sets, gather positions and buckets.  A sparsified level is a
+// subset of the structural one, column by column, so each level is written
+// straight into the structural layout (one launch per level, no count pass);
+// the final level is compacted by the positions kernel after one scan of its
+// lengths, and the gathered entries of column j go to the structural offsets
+// eoff[j] of the static plan.
+sam_status enqueue_symbolic(sam_seq* q, int k, sam_seq::Scratch& R, const double* vals, hipStream_t s) {
     sam_ctx* ctx = q->ctx;
     const int n = q->n;
     const samk::SparsifySpec sp = to_sp(&q->spec);
@@ -102,15 +111,15 @@ sam_status enqueue_replanned(sam_seq* q, int k, const double* vals, void* M, dou
     int* Scp = q->Sk_cp[k];
     int* Sri = q->Sk_ri[k];
     // B = S(A~_k) plus the diagonal, in the slots of the structural B
-    int* b_ri = p == 1 ? q->F_ri : q->B_ri;
-    int* b_cnt = p == 1 ? q->F_cnt : q->B_cnt;
-    HIP_TRY(ctx, samk::sparsify_slots(n, q->Ak_cp, q->Ak_ri, vals, sp, q->D, level_cp(0), b_ri, b_cnt, s));
+    int* b_ri = p == 1 ? R.F_ri : R.B_ri;
+    int* b_cnt = p == 1 ? R.F_cnt : R.B_cnt;
+    HIP_TRY(ctx, samk::sparsify_slots(n, q->Ak_cp, q->Ak_ri, vals, sp, R.D, level_cp(0), b_ri, b_cnt, s));
     const int* cur_ri = b_ri;
     const int* cur_cnt = b_cnt;
     for (int lev = 1; lev < p; ++lev) {
-        int* dri = lev == p - 1 ? q->F_ri : q->L_ri[lev & 1];
-        int* dcnt = lev == p - 1 ? q->F_cnt : q->L_cnt[lev & 1];
-        HIP_TRY(ctx, samk::expand_slots(n, level_cp(lev - 1), cur_cnt, cur_ri, level_cp(0), q->B_cnt, q->B_ri,
+        int* dri = lev == p - 1 ? R.F_ri : R.L_ri[lev & 1];
+        int* dcnt = lev == p - 1 ? R.F_cnt : R.L_cnt[lev & 1];
+        HIP_TRY(ctx, samk::expand_slots(n, level_cp(lev - 1), cur_cnt, cur_ri, level_cp(0), R.B_cnt, R.B_ri,
                                         level_cp(lev), dri, dcnt, q->levels.maxcol[(size_t)lev - 1],
                                         q->levels.maxcol[0], s));
         cur_ri = dri;
@@ -118,23 +127,50 @@ sam_status enqueue_replanned(sam_seq* q, int k, const double* vals, void* M, dou
     }
     // compact column pointers of S_k, then row sets, gather positions and the
     // compact S_k in one pass, then the size buckets
-    HIP_TRY(ctx, samk::scan_counts(q->F_cnt, n, q->off, Scp, nullptr, q->stemp, s));
-    sam_plan* pl = &q->dplan;
+    HIP_TRY(ctx, samk::scan_counts(R.F_cnt, n, R.off, Scp, nullptr, R.stemp, s));
+    sam_plan* pl = &R.dplan;
     pl->S_cp = Scp;
     pl->S_ri = Sri;
-    HIP_TRY(ctx, samk::plan_positions_slots(n, level_cp(p - 1), q->F_cnt, q->F_ri, Scp, Sri, q->Ak_cp, q->Ak_ri,
+    HIP_TRY(ctx, samk::plan_positions_slots(n, level_cp(p - 1), R.F_cnt, R.F_ri, Scp, Sri, q->Ak_cp, q->Ak_ri,
                                             q->A0_cp, q->A0_ri, pl->eoff, pl->nI, pl->posA, pl->posB,
                                             q->plan->max_cols, q->plan->max_len_A, s));
     Combo& cb = pl->combo[q->prec][0];
-    HIP_TRY(ctx, samk::bucket_sort(n, Scp, pl->nI, cb.tab, cb.queue, cb.bstart, nullptr, ctx->d_status, q->btemp, s));
-    return run_numeric(pl, vals, q->A0_val, nullptr, 0.0, q->prec, 0, M, nullptr, res2, s);
+    HIP_TRY(ctx, samk::bucket_sort(n, Scp, pl->nI, cb.tab, cb.queue, cb.bstart, nullptr, ctx->d_status, R.btemp, s));
+    return SAM_OK;
+}
+
+// Replanning mode: source k's symbolic work on `s` (the capture stream) and
+// its numeric build on cap2.  Edges: numeric k after symbolic k; symbolic k
+// after numeric k-2 (which used the same scratch set); the run ends when the
+// last numeric build has joined `s`.  Symbolic k+1 thus overlaps numeric k.
+sam_status enqueue_pipelined(sam_seq* q, const double* const* vals, void* const* M, double* res2, hipStream_t s) {
+    sam_ctx* ctx = q->ctx;
+    const int N = q->n_src;
+    hipEvent_t* ev_sym = q->ev.data();
+    hipEvent_t* ev_num = q->ev.data() + N;
+    hipEvent_t fork = q->ev[(size_t)2 * N];
+    HIP_TRY(ctx, hipEventRecord(fork, s));
+    HIP_TRY(ctx, hipStreamWaitEvent(q->cap2, fork, 0));
+    for (int k = 0; k < N; ++k) {
+        sam_seq::Scratch& R = q->part[k & 1];
+        if (k >= 2) HIP_TRY(ctx, hipStreamWaitEvent(s, ev_num[k - 2], 0));
+        sam_status st = enqueue_symbolic(q, k, R, vals[k], s);
+        if (st) return st;
+        HIP_TRY(ctx, hipEventRecord(ev_sym[k], s));
+        HIP_TRY(ctx, hipStreamWaitEvent(q->cap2, ev_sym[k], 0));
+        st = run_numeric(&R.dplan, vals[k], q->A0_val, nullptr, 0.0, q->prec, 0, M[k], nullptr, res2 + k, q->cap2);
+        if (st) return st;
+        HIP_TRY(ctx, hipEventRecord(ev_num[k], q->cap2));
+    }
+    HIP_TRY(ctx, hipStreamWaitEvent(s, ev_num[N - 1], 0));
+    return SAM_OK;
 }
 
 sam_status enqueue_run(sam_seq* q, const double* const* vals, void* const* M, double* res2, hipStream_t s) {
+    if (q->replan) return enqueue_pipelined(q, vals, M, res2, s);
     for (int k = 0; k < q->n_src; ++k) {
-        sam_status st = q->replan ? enqueue_replanned(q, k, vals[k], M[k], res2 + k, s)
-                                  : run_numeric(q->plan, vals[k], q->A0_val, nullptr, 0.0, q->prec, 0, M[k], nullptr,
-                                                res2 + k, s);
+        sam_status st = run_numeric(q->plan, vals[k], q->A0_val, nullptr, 0.0, q->prec, 0, M[k], nullptr,
+                                    res2 + k, s);
         if (st) return st;
     }
     return SAM_OK;
@@ -205,8 +241,8 @@ sam_status sam_sequence_create(sam_ctx* ctx, const sam_csc* A0, const sam_csc* A
         int64_t mid_max = 1;
         for (int lev = 1; lev + 1 < p; ++lev) mid_max = std::max(mid_max, lev_nnz(lev));
         const int64_t E = std::max<int64_t>(q->plan->E, 1);
-        size_t need = 0;
-        auto add = [&](size_t b) { need += align256(b); };
+        size_t need_set = 0;   // one scratch set
+        auto add = [&](size_t b) { need_set += align256(b); };
         add((size_t)(n + 1) * 8);                // off
         add(samk::scan_temp_bytes(n));           // stemp
         add(samk::bucket_temp_bytes(n));         // btemp
@@ -219,10 +255,6 @@ sam_status sam_sequence_create(sam_ctx* ctx, const sam_csc* A0, const sam_csc* A
         }
         add((size_t)lev_nnz(p - 1) * 4);         // final level slots
         add((size_t)n * 4);
-        for (int k = 0; k < n_src; ++k) {
-            add((size_t)(n + 1) * 4);
-            add((size_t)std::max<int64_t>(q->nnzS, 1) * 4);
-        }
         add((size_t)n * 4);                      // nI
         add((size_t)E);                          // posA
         add((size_t)std::max(q->nnzA0, 1));      // posB
@@ -230,51 +262,62 @@ sam_status sam_sequence_create(sam_ctx* ctx, const sam_csc* A0, const sam_csc* A
         add(64 * 4);                             // bstart
         add((size_t)n * 8);                      // colbuf
         add(samk::reduce_temp_bytes(n));
-        add(64);                                 // flags
+        const size_t need_src = (size_t)n_src * (align256((size_t)(n + 1) * 4) +
+                                                 align256((size_t)std::max<int64_t>(q->nnzS, 1) * 4));
+        const size_t need = 2 * need_set + need_src;
         hipError_t he = grow(q->dyn, need + 4096);
         if (he != hipSuccess) return bail(fail(ctx, SAM_ERR_NOMEM, "sequence buffers (%zu bytes): %s", need,
                                                hipGetErrorString(he)));
         Carve cv(q->dyn.p);
-        q->off = cv.take<int64_t>(n + 1);
-        q->stemp = cv.take<char>(samk::scan_temp_bytes(n));
-        q->btemp = cv.take<char>(samk::bucket_temp_bytes(n));
-        q->D = cv.take<double>(n);
-        q->B_ri = cv.take<int>((size_t)lev_nnz(0));
-        q->B_cnt = cv.take<int>(n);
-        for (int i = 0; i < 2; ++i) {
-            q->L_ri[i] = cv.take<int>((size_t)mid_max);
-            q->L_cnt[i] = cv.take<int>(n);
-        }
-        q->F_ri = cv.take<int>((size_t)lev_nnz(p - 1));
-        q->F_cnt = cv.take<int>(n);
         for (int k = 0; k < n_src; ++k) {
             q->Sk_cp.push_back(cv.take<int>(n + 1));
             q->Sk_ri.push_back(cv.take<int>((size_t)std::max<int64_t>(q->nnzS, 1)));
         }
-        sam_plan& d = q->dplan;
-        d.ctx = ctx;
-        d.n = n;
-        d.nnzA = q->nnzA;
-        d.nnzA0 = q->nnzA0;
-        d.nnzS = q->nnzS;
-        d.E = q->plan->E;
-        d.Ak_cp = q->Ak_cp;
-        d.Ak_ri = q->Ak_ri;
-        d.A0_cp = q->A0_cp;
-        d.A0_ri = q->A0_ri;
-        d.nI = cv.take<int>(n);
-        d.eoff = q->plan->eoff;   // structural offsets of the gathered entries
-        d.posA = cv.take<unsigned char>((size_t)E);
-        d.posB = cv.take<unsigned char>((size_t)std::max(q->nnzA0, 1));
-        Combo& cb = d.combo[q->prec][0];
-        cb.queue = cv.take<int>(n);
-        cb.bstart = cv.take<int>(64);
-        cb.ok = true;
-        bound_buckets(cb, q->plan->combo[q->prec][0]);
-        d.colbuf = cv.take<double>(n);
-        d.rtemp = cv.take<char>(samk::reduce_temp_bytes(n));
-        d.device_counts = true;
-        q->flags = cv.take<int>(16);
+        for (sam_seq::Scratch& R : q->part) {
+            R.off = cv.take<int64_t>(n + 1);
+            R.stemp = cv.take<char>(samk::scan_temp_bytes(n));
+            R.btemp = cv.take<char>(samk::bucket_temp_bytes(n));
+            R.D = cv.take<double>(n);
+            R.B_ri = cv.take<int>((size_t)lev_nnz(0));
+            R.B_cnt = cv.take<int>(n);
+            for (int i = 0; i < 2; ++i) {
+                R.L_ri[i] = cv.take<int>((size_t)mid_max);
+                R.L_cnt[i] = cv.take<int>(n);
+            }
+            R.F_ri = cv.take<int>((size_t)lev_nnz(p - 1));
+            R.F_cnt = cv.take<int>(n);
+            sam_plan& d = R.dplan;
+            d.ctx = ctx;
+            d.n = n;
+            d.nnzA = q->nnzA;
+            d.nnzA0 = q->nnzA0;
+            d.nnzS = q->nnzS;
+            d.E = q->plan->E;
+            d.max_cols = q->plan->max_cols;
+            d.max_len_A = q->plan->max_len_A;
+            d.Ak_cp = q->Ak_cp;
+            d.Ak_ri = q->Ak_ri;
+            d.A0_cp = q->A0_cp;
+            d.A0_ri = q->A0_ri;
+            d.nI = cv.take<int>(n);
+            d.eoff = q->plan->eoff;   // structural offsets of the gathered entries
+            d.posA = cv.take<unsigned char>((size_t)E);
+            d.posB = cv.take<unsigned char>((size_t)std::max(q->nnzA0, 1));
+            Combo& cb = d.combo[q->prec][0];
+            cb.queue = cv.take<int>(n);
+            cb.bstart = cv.take<int>(64);
+            cb.ok = true;
+            bound_buckets(cb, q->plan->combo[q->prec][0]);
+            d.colbuf = cv.take<double>(n);
+            d.rtemp = cv.take<char>(samk::reduce_temp_bytes(n));
+            d.device_counts = true;
+        }
+        if (hipStreamCreateWithFlags(&q->cap2, hipStreamNonBlocking) != hipSuccess)
+            return bail(fail(ctx, SAM_ERR_HIP, "stream creation failed"));
+        q->ev.assign((size_t)2 * n_src + 1, nullptr);
+        for (hipEvent_t& e : q->ev)
+            if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess)
+                return bail(fail(ctx, SAM_ERR_HIP, "event creation failed"));
     }
     if (hipStreamCreateWithFlags(&q->cap, hipStreamNonBlocking) != hipSuccess)
         return bail(fail(ctx, SAM_ERR_HIP, "stream creation failed"));
@@ -290,6 +333,9 @@ sam_status sam_sequence_destroy(sam_seq* q) {
     }
     drop_graph(q);
     if (q->cap) (void)hipStreamDestroy(q->cap);
+    if (q->cap2) (void)hipStreamDestroy(q->cap2);
+    for (hipEvent_t e : q->ev)
+        if (e) (void)hipEventDestroy(e);
     if (q->plan) sam_plan_destroy(q->plan);
     release(q->S_cp);
     release(q->S_ri);
@@ -340,7 +386,8 @@ sam_status sam_sequence_select(sam_seq* q, const int32_t* order, int32_t count, 
     sam_status st = need_device(ctx);
     if (st) return st;
     if ((st = plan_select(q->plan, q->prec, vars, S(stream)))) return st;
-    if (q->replan) bound_buckets(q->dplan.combo[q->prec][0], q->plan->combo[q->prec][0]);
+    if (q->replan)
+        for (sam_seq::Scratch& R : q->part) bound_buckets(R.dplan.combo[q->prec][0], q->plan->combo[q->prec][0]);
     drop_graph(q);  // the next run captures the new launches
     return SAM_OK;
 }
