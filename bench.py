@@ -34,7 +34,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK = {"hbm_GBs": 8000.0, "fp32_TFs": 157.3, "fp64_TFs": 78.6}
-KERNEL_SOURCES = ["sam_numeric.hip", "sam_device.hpp", "sam_kernels.hpp"]
+KERNEL_SOURCES = ["sam_numeric.hip", "sam_device.hpp", "sam_numeric_args.hpp"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_numeric_cfg2_512_level2.txt")
 
 
