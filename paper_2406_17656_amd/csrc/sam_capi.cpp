@@ -280,6 +280,16 @@ sam_status plan_combo_with(sam_plan* pl, int prec, int weighted, const std::vect
 }
 
 
+// Blocks of a numeric variant the GPU holds at once per CU (16 when the
+// occupancy query failed).
+int resident_blocks(const sam_ctx* ctx, const NumericVariant* v) {
+    int cnt = 0;
+    const NumericVariant* menu = samk::numeric_menu(&cnt);
+    const ptrdiff_t i = v - menu;
+    if (i >= 0 && i < (ptrdiff_t)ctx->resident.size() && ctx->resident[i] > 0) return ctx->resident[i];
+    return 16;
+}
+
 // Launch every non-empty bucket of a combination, then the column-residual sum.
 sam_status run_numeric(sam_plan* pl, const double* Ak_val, const double* A0_val, const double* w, double mu, int prec,
                        int weighted, void* M_val, double* col_res2, double* res2, hipStream_t s) {
@@ -317,8 +327,7 @@ sam_status run_numeric(sam_plan* pl, const double* Ak_val, const double* A0_val,
         const NumericVariant* v = cb.variants[b];
         a.bucket = (int)b;
         int groups = (cnt + v->per_wave() - 1) / v->per_wave();
-        int cap = ctx->CUs * 16;
-        int grid = std::min(groups, cap);
+        int grid = std::min(groups, ctx->CUs * resident_blocks(ctx, v));
         if (grid >= 64) grid = grid / 8 * 8;
         HIP_TRY(ctx, v->launch(a, grid, s));
     }
@@ -368,6 +377,12 @@ sam_status sam_create(sam_ctx** out, int device) {
         hipDeviceProp_t prop;
         if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
             ctx->CUs = prop.multiProcessorCount;
+        {
+            int cnt = 0;
+            const samk::NumericVariant* menu = samk::numeric_menu(&cnt);
+            ctx->resident.assign(cnt, 0);
+            for (int i = 0; i < cnt; ++i) ctx->resident[i] = menu[i].blocks_per_cu();
+        }
         if (hipMalloc(&ctx->d_status, sizeof(unsigned long long)) != hipSuccess) {
             delete ctx;
             return SAM_ERR_NOMEM;

@@ -104,7 +104,22 @@ __device__ inline T group_max(T v) {
 // the group: the other lanes contribute an exact zero to a group sum.
 template <int G, typename T>
 __device__ inline T group_bcast(T v, int g, int src) {
-    return group_sum<G>(g == src ? v : T(0));
+    // groups of 2 or 4 lanes: one quad_perm move; src is a constant once the
+    // caller's loop is unrolled, so the switch folds away
+    if constexpr (G == 1) {
+        return v;
+    } else if constexpr (G == 2) {
+        return (src & 1) ? dpp<0xF5>(v) : dpp<0xA0>(v);  // [1,1,3,3] / [0,0,2,2]
+    } else if constexpr (G == 4) {
+        switch (src & 3) {
+            case 0: return dpp<0x00>(v);  // [0,0,0,0]
+            case 1: return dpp<0x55>(v);  // [1,1,1,1]
+            case 2: return dpp<0xAA>(v);  // [2,2,2,2]
+            default: return dpp<0xFF>(v); // [3,3,3,3]
+        }
+    } else {
+        return group_sum<G>(g == src ? v : T(0));
+    }
 }
 
 __device__ inline int wave_lane() { return (int)(threadIdx.x & 63); }

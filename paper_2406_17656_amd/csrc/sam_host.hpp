@@ -31,6 +31,9 @@ struct sam_ctx {
     const double* key_val = nullptr;
     sam_pattern_spec key_spec{};
     int CUs = 256;
+    // resident blocks per CU of each numeric kernel variant (menu order),
+    // queried once on the context's device
+    std::vector<int> resident;
 };
 
 // One (precision, weighted) combination of a plan: the bucket order of the

@@ -61,6 +61,14 @@ __device__ inline int ld_u8(__amdgpu_buffer_rsrc_t r, uint32_t off) {
     return (int)__builtin_amdgcn_raw_buffer_load_b8(r, (int)off, 0, 0);
 }
 
+// vec[p] += x as an LDS atomic without return (ds_add_f64): no read-modify-
+// write round trip per entry.  The lanes of one instruction always target
+// distinct slots and a wave's LDS operations complete in issue order, so each
+// slot's sum is formed in program order, as with plain loads and stores.
+__device__ inline void lds_add(double* p, double x) {
+    __hip_atomic_fetch_add(p, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+}
+
 template <typename T>
 __device__ inline T recip(T x);
 template <>
@@ -114,10 +122,11 @@ k_numeric(NumericArgs a) {
     const int b0 = a.bstart[a.bucket];
     const int count = a.bstart[a.bucket + 1] - b0;
     const int ngroups = (count + P - 1) / P;
-    const int per_block = (ngroups + gridDim.x - 1) / gridDim.x;
+    // groups split evenly over the blocks (the launch sizes the grid to the
+    // blocks the GPU holds at once, so every block runs in one round)
     const int lb = logical_block();
-    const int grp_lo = lb * per_block;
-    const int grp_hi = min(ngroups, grp_lo + per_block);
+    const int grp_lo = (int)((int64_t)lb * ngroups / gridDim.x);
+    const int grp_hi = (int)((int64_t)(lb + 1) * ngroups / gridDim.x);
     const __amdgpu_buffer_rsrc_t rAv = buf_rsrc(a.Ak_v, a.nnzA * 8u);
     const __amdgpu_buffer_rsrc_t rA0 = buf_rsrc(a.A0_v, a.nnzA0 * 8u);
     const __amdgpu_buffer_rsrc_t rPA = buf_rsrc(a.posA, a.E);
@@ -210,8 +219,9 @@ k_numeric(NumericArgs a) {
             for (int s = 0; s < LPL; ++s) {
                 const bool ok = g + s * G < len;
                 const int p = ld_u8(rPA, po + s * G);
-                pp[c][s] = ok ? p : trash;
-                pv[c][s] = ld_f64(rAv, vo + s * G * 8);   // masked entries land in the scratch row
+                const double v = ld_f64(rAv, vo + s * G * 8);
+                pp[c][s] = ok ? p : trash;   // masked slots: zero into the lane's scratch row
+                pv[c][s] = ok ? v : 0.0;
             }
         }
         TQ A[R][NC];
@@ -269,8 +279,6 @@ k_numeric(NumericArgs a) {
         TQ rdiag[NC], rinv[NC];
 #pragma unroll
         for (int k = 0; k < NC; ++k) {
-            constexpr int dummy = 0;
-            (void)dummy;
             const int tk = k / G, gk = k % G;
             TQ sig = 0, alp = 0;
 #pragma unroll
@@ -358,7 +366,11 @@ k_numeric(NumericArgs a) {
         // distinct inside one column, so the lanes of a group never update
         // one LDS slot in the same instruction, and the wave's LDS operations
         // complete in program order from column to column.  The values are
-        // reloaded (L2-resident) with all loads issued first.
+        // reloaded (L2-resident) with all loads issued first.  A slot past
+        // the column's length loads its value from the first offset past the
+        // value array, which reads 0, and its row is clamped into the
+        // problem's own LDS rows: it adds exactly zero wherever it lands.
+        const uint32_t v_end = a.nnzA * 8u;
         auto load_entries = [&]() {
 #pragma unroll
             for (int c = 0; c < NC; ++c) {
@@ -369,9 +381,8 @@ k_numeric(NumericArgs a) {
                 for (int u = 0; u < LPL; ++u) {
                     const bool ok = g + u * G < len;
                     const int p = ld_u8(rPA, po + u * G);
-                    const double v = ld_f64(rAv, vo + u * G * 8);
-                    pp[c][u] = ok ? p : trash;
-                    pv[c][u] = ok ? v : 0.0;
+                    pv[c][u] = ld_f64(rAv, ok ? vo + u * G * 8 : v_end);
+                    pp[c][u] = min(p, trash);
                 }
             }
         };
@@ -381,7 +392,7 @@ k_numeric(NumericArgs a) {
             for (int c = 0; c < NC; ++c) {
                 const double xc = sgn * x[c];
 #pragma unroll
-                for (int u = 0; u < LPL; ++u) vec[pp[c][u]] += pv[c][u] * xc;
+                for (int u = 0; u < LPL; ++u) lds_add(&vec[pp[c][u]], pv[c][u] * xc);
             }
             if (longc) {  // long columns: the rest straight from memory
 #pragma unroll
@@ -389,7 +400,7 @@ k_numeric(NumericArgs a) {
                     const int len = cln[q][c];
                     const double xc = sgn * x[c];
                     const int e0 = cst[q][c], vb = vbs[q][c];
-                    for (int e = g + LPL * G; e < len; e += G) vec[a.posA[eo + e0 + e]] += a.Ak_v[vb + e] * xc;
+                    for (int e = g + LPL * G; e < len; e += G) lds_add(&vec[a.posA[eo + e0 + e]], a.Ak_v[vb + e] * xc);
                 }
             }
             wave_sync();
@@ -473,7 +484,129 @@ k_numeric(NumericArgs a) {
 
         double mfin[NC];
         double rr;
-        if constexpr (REFINE) {
+        if constexpr (REFINE && MODE == 0) {
+            // One seminormal refinement step, residual in FP64, taken in
+            // column chunks so that one chunk of entries at a time is held in
+            // registers:  r = b - A m (in place over b);  R^T y = A^T r, with
+            // each column's partial of A^T r folded into the forward solve's
+            // own FP64 group reduction;  R d = y;  m += d.  The new residual
+            // ||b - A(m + d)||^2 = ||r||^2 - 2 d^T A^T r + ||A d||^2, where
+            // d^T A^T r and ||A d||^2 both equal ||y||^2 up to rounding.
+            // Blocks of up to 16 columns keep the entries the gather loaded
+            // (held through the QR) for both passes; wider ones reload them
+            // three columns at a time (a whole block's entries would hold
+            // 3 * NC * LPL registers and cost a wave slot per SIMD).
+            constexpr int CH = NC <= 16 ? NC : 3;
+            constexpr bool ONE = CH >= NC;
+            double* rv = bsh + q * RS;
+            rv[trash] = 0.0;
+            auto load_chunk = [&](int c0, double (&cv)[CH][LPL], int (&cp)[CH][LPL]) {
+#pragma unroll
+                for (int cc = 0; cc < CH; ++cc) {
+                    const int c = c0 + cc;
+                    if (c < NC) {
+                        const int len = cln[q][c];
+                        const uint32_t po = (uint32_t)eo + (uint32_t)(cst[q][c] + g);
+                        const uint32_t vo = (uint32_t)(vbs[q][c] + g) * 8u;
+#pragma unroll
+                        for (int u = 0; u < LPL; ++u) {
+                            const bool ok = g + u * G < len;
+                            const int p = ld_u8(rPA, po + u * G);
+                            cv[cc][u] = ld_f64(rAv, ok ? vo + u * G * 8 : v_end);
+                            cp[cc][u] = min(p, trash);
+                        }
+                    }
+                }
+            };
+            double cv[CH][LPL];
+            int cp[CH][LPL];
+            if constexpr (ONE) {
+#pragma unroll
+                for (int c = 0; c < CH; ++c)
+#pragma unroll
+                    for (int u = 0; u < LPL; ++u) {
+                        cv[c][u] = pv[c][u];
+                        cp[c][u] = pp[c][u];
+                    }
+            }
+#pragma unroll
+            for (int c0 = 0; c0 < NC; c0 += CH) {
+                if constexpr (!ONE) load_chunk(c0, cv, cp);
+#pragma unroll
+                for (int cc = 0; cc < CH; ++cc) {
+                    const int c = c0 + cc;
+                    if (c < NC) {
+                        const double xc = -(double)m[c];
+#pragma unroll
+                        for (int u = 0; u < LPL; ++u) lds_add(&rv[cp[cc][u]], cv[cc][u] * xc);
+                        const int len = longc ? cln[q][c] : 0;
+                        if (len > LPL * G) {  // long columns: the rest straight from memory
+                            const int e0 = cst[q][c], vb = vbs[q][c];
+                            for (int e = g + LPL * G; e < len; e += G)
+                                lds_add(&rv[a.posA[eo + e0 + e]], a.Ak_v[vb + e] * xc);
+                        }
+                    }
+                }
+            }
+            wave_sync();
+            double r2 = 0.0;
+#pragma unroll
+            for (int t = 0; t < R; ++t) {
+                const double x = rv[t * G + g];  // rows past |I_j| hold zeros
+                r2 += x * x;
+            }
+            const double rr0 = group_sum<G>(r2);
+            TQ ydist[R];
+            TQ yrep[NC];
+#pragma unroll
+            for (int t = 0; t < R; ++t) ydist[t] = 0;
+#pragma unroll
+            for (int c0 = 0; c0 < NC; c0 += CH) {
+                if constexpr (!ONE) load_chunk(c0, cv, cp);
+#pragma unroll
+                for (int cc = 0; cc < CH; ++cc) {
+                    const int c = c0 + cc;
+                    if (c < NC) {
+                        double gp = 0.0;
+#pragma unroll
+                        for (int u = 0; u < LPL; ++u) gp += cv[cc][u] * rv[cp[cc][u]];
+                        const int len = longc ? cln[q][c] : 0;
+                        if (len > LPL * G) {
+                            const int e0 = cst[q][c], vb = vbs[q][c];
+                            for (int e = g + LPL * G; e < len; e += G) gp += a.Ak_v[vb + e] * rv[a.posA[eo + e0 + e]];
+                        }
+                        TQ part = 0;
+#pragma unroll
+                        for (int t = 0; t < R; ++t) {
+                            const int row = t * G + g;
+                            if (t * G < c) part += (row < c) ? A[t][c] * ydist[t] : (TQ)0;
+                        }
+                        const double sc = group_sum<G>(gp - (double)part);
+                        TQ yc = (TQ)sc * rinv[c];
+                        yc = (c < nJ) ? yc : (TQ)0;
+                        yrep[c] = yc;
+                        if (g == c % G) ydist[c / G] = yc;
+                    }
+                }
+            }
+            TQ dl[NC];
+#pragma unroll
+            for (int k = NC - 1; k >= 0; --k) {
+                const int tk = k / G, gk = k % G;
+                TQ sacc = yrep[k];
+#pragma unroll
+                for (int c = k + 1; c < NC; ++c) sacc -= A[tk][c] * dl[c];
+                const TQ dk = group_bcast<G>(sacc * rinv[k], g, gk);
+                dl[k] = (k < nJ) ? dk : (TQ)0;
+            }
+            double yy = 0.0;
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                yy += (double)yrep[c] * (double)yrep[c];
+                mfin[c] = (double)m[c] + (double)dl[c];
+            }
+            rr = rr0 - yy + outj;
+        } else if constexpr (REFINE) {
             // refinement on the normal equations (A^T A + P) m = A^T b with the
             // residual in FP64:  r = b - A m,  m += R^{-1} R^{-T} (A^T r - P m)
             double m64[NC];
@@ -571,13 +704,14 @@ k_numeric(NumericArgs a) {
 #pragma unroll
             for (int c = 0; c < NC; ++c) {
                 const int e0 = cst[q][c];
+                const int clen = cln[q][c];
 #pragma unroll
                 for (int u = 0; u < LPL; ++u) {
                     const int p = pp[c][u];
-                    if (p != trash)
+                    if (g + u * G < clen)
                         cj[e0 + g + u * G] = dL * (-2.0 * rsh[p] * mfin[c] + rsh[p] * lam[c] - al[p] * mfin[c]);
                 }
-                const int len = longc ? cln[q][c] : 0;
+                const int len = longc ? clen : 0;
                 if (len > LPL * G) {
                     for (int e = g + LPL * G; e < len; e += G) {
                         const int p = a.posA[eo + e0 + e];
@@ -634,6 +768,15 @@ hipError_t launch_numeric(const NumericArgs& args, int grid, hipStream_t s) {
     return hipGetLastError();
 }
 
+template <typename TQ, int G, int R, int NC, int TC, int LPL, int MODE>
+int numeric_blocks_per_cu() {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_numeric<TQ, G, R, NC, TC, LPL, MODE>, 64, 0) !=
+        hipSuccess)
+        return 0;
+    return nb;
+}
+
 // LPL: entries of one A_k column a lane moves with static indices (longer
 // columns fall back to a loop over memory), sized for 5- to 9-point stencils.
 using LaunchFn = hipError_t (*)(const NumericArgs&, int, hipStream_t);
@@ -647,7 +790,8 @@ constexpr LaunchFn backward_launcher() {
 
 #define SAM_VARIANT(TQ, PREC, G, R, NC, TC, LPL, W)                                                \
     NumericVariant{PREC, G, R, NC, W, TC, LPL, &launch_numeric<TQ, G, R, NC, TC, LPL, W ? 1 : 0>, \
-                   backward_launcher<TQ, G, R, NC, TC, LPL, W>()}
+                   backward_launcher<TQ, G, R, NC, TC, LPL, W>(),                             \
+                   &numeric_blocks_per_cu<TQ, G, R, NC, TC, LPL, W ? 1 : 0>}
 
 // Menu per precision, cheapest first.  Shapes of the workloads: 2D 5-point
 // level 1 (13 x 5), level 2 (25 x 13); 3D 7-point level 2 (63 x 25); 2D

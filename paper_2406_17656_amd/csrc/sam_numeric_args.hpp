@@ -52,6 +52,7 @@ struct NumericVariant {
     int LPL;         // entries per lane and column moved with static indices
     hipError_t (*launch)(const NumericArgs&, int grid, hipStream_t);
     hipError_t (*launch_backward)(const NumericArgs&, int grid, hipStream_t);  // weighted only
+    int (*blocks_per_cu)();  // resident one-wave blocks per CU of the forward kernel (0: unknown)
     int max_rows() const { return G * R; }
     int per_wave() const { return 64 / G; }
 };
