@@ -111,8 +111,9 @@ k_numeric(NumericArgs a) {
     TQ* tile = reinterpret_cast<TQ*>(lds_tile);
     __shared__ double bsh[P * RS];        // b = A_0(I_j, j)
     __shared__ int cst[P][NC + 1];        // entry offset of column c in the block
-    __shared__ int vbs[P][NC];            // start of A_k(:, J_j[c]) in the value array
-    __shared__ int cln[P][NC];            // nnz of A_k(:, J_j[c])
+    __shared__ int vbs2[2][P][NC];        // start of A_k(:, J_j[c]) in the value array
+    __shared__ int cln2[2][P][NC];        // nnz of A_k(:, J_j[c])
+    __shared__ int mta[P][9];             // next group: valid, j, scol, nJ, nIj, eo (2), a0, a1
     __shared__ double alsh[BACKWARD ? P * RS : 1];  // A lambda (adjoint)
 
     const int lane = threadIdx.x;
@@ -132,42 +133,119 @@ k_numeric(NumericArgs a) {
     const __amdgpu_buffer_rsrc_t rPA = buf_rsrc(a.posA, a.E);
     const __amdgpu_buffer_rsrc_t rPB = buf_rsrc(a.posB, a.nnzA0);
 
-    for (int grp = grp_lo; grp < grp_hi; ++grp) {
-        const int slot = grp * P + q;
-        const bool valid = slot < count;
-        const int j = valid ? a.queue[b0 + slot] : 0;
-        int nJ = 0, nIj = 0, scol = 0;
-        int64_t eo = 0;
-        if (valid) {
-            scol = a.S_cp[j];
-            nJ = a.S_cp[j + 1] - scol;
-            nIj = a.nI[j];
-            eo = a.eoff[j];
+    // Per-group metadata is software-pipelined: the dependent loads that
+    // locate group grp + 1 (its queue entry; its pattern and row-set data;
+    // its pattern columns; their extents in A_k) are issued in stages while
+    // group grp is solved and land in LDS (the column extents in the other
+    // half of a double buffer), so a group starts with only its value loads
+    // outstanding.  Lane g resolves columns g, g+G, ... of J_j.
+    // Blocks of 8 to 13 columns of the plain map prefetch; wider blocks and
+    // the weighted forms have no registers to spare (and the narrowest lose
+    // a wave slot per SIMD): they run the same stages for their own group at
+    // its top.
+    constexpr bool PIPE = NC >= 8 && NC <= 13 && MODE == 0;
+    constexpr int NCG = (NC + G - 1) / G;
+    bool n_valid = false;
+    int n_j = 0, n_cp0 = 0, n_cp1 = 0, n_nI = 0, n_a0 = 0, n_a1 = 0;
+    int64_t n_eo = 0;
+    int n_l[NCG], n_v0[NCG], n_v1[NCG];
+    auto stage1 = [&](int gr) {  // queue entry
+        const int slot = gr * P + q;
+        n_valid = gr < grp_hi && slot < count;
+        n_j = n_valid ? a.queue[b0 + slot] : 0;
+    };
+    auto stage2 = [&]() {  // pattern and row-set data of column j
+        n_cp0 = n_cp1 = n_nI = n_a0 = n_a1 = 0;
+        n_eo = 0;
+        if (n_valid) {
+            n_cp0 = a.S_cp[n_j];
+            n_cp1 = a.S_cp[n_j + 1];
+            n_nI = a.nI[n_j];
+            n_eo = a.eoff[n_j];
+            n_a0 = a.A0_cp[n_j];
+            n_a1 = a.A0_cp[n_j + 1];
         }
+    };
+    auto stage3 = [&]() {  // to LDS; then the pattern's columns
+        const int nj = n_cp1 - n_cp0;
+        mta[q][0] = n_valid;
+        mta[q][1] = n_j;
+        mta[q][2] = n_cp0;
+        mta[q][3] = nj;
+        mta[q][4] = n_nI;
+        mta[q][5] = (int)(uint32_t)(uint64_t)n_eo;
+        mta[q][6] = (int)((uint64_t)n_eo >> 32);
+        mta[q][7] = n_a0;
+        mta[q][8] = n_a1;
+#pragma unroll
+        for (int i = 0; i < NCG; ++i) {
+            const int c = g + i * G;
+            n_l[i] = c < nj ? a.S_ri[n_cp0 + c] : -1;
+        }
+    };
+    auto stage4 = [&]() {  // extents of the pattern's columns in A_k
+#pragma unroll
+        for (int i = 0; i < NCG; ++i) {
+            n_v0[i] = n_v1[i] = 0;
+            if (n_l[i] >= 0) {
+                n_v0[i] = a.Ak_cp[n_l[i]];
+                n_v1[i] = a.Ak_cp[n_l[i] + 1];
+            }
+        }
+    };
+    auto stage5 = [&](int nb) {  // to the other LDS buffer
+#pragma unroll
+        for (int i = 0; i < NCG; ++i) {
+            const int c = g + i * G;
+            if (c < NC) {
+                vbs2[nb][q][c] = n_v0[i];
+                cln2[nb][q][c] = n_v1[i] - n_v0[i];
+            }
+        }
+    };
+    if constexpr (PIPE) {
+        stage1(grp_lo);
+        stage2();
+        stage3();
+        stage4();
+        stage5(0);
+        wave_sync();
+    }
+
+    for (int grp = grp_lo; grp < grp_hi; ++grp) {
+        const int bi = PIPE ? (grp - grp_lo) & 1 : 0;
+        if constexpr (!PIPE) {
+            stage1(grp);
+            stage2();
+            stage3();
+            stage4();
+            stage5(0);
+            wave_sync();
+        }
+        int (&vbs)[P][NC] = vbs2[bi];
+        int (&cln)[P][NC] = cln2[bi];
+        const bool valid = mta[q][0] != 0;
+        const int j = mta[q][1];
+        const int scol = mta[q][2];
+        const int nJ = mta[q][3];
+        const int nIj = mta[q][4];
+        const int64_t eo = (int64_t)(((uint64_t)(uint32_t)mta[q][6] << 32) | (uint32_t)mta[q][5]);
+        const int a0 = mta[q][7];
+        const int a1 = mta[q][8];
         const int nrows = WEIGHTED ? nIj + nJ : nIj;
 
-        // ---- column metadata: lane g resolves columns g, g+G, ... of J_j;
-        //      longc (wave-uniform): some column needs the memory loops
+        // ---- longc (wave-uniform): some column needs the memory loops
         bool mylong = false;
 #pragma unroll
-        for (int c = g; c < NC; c += G) {
-            int vb = 0, len = 0;
-            if (c < nJ) {
-                const int l = a.S_ri[scol + c];
-                vb = a.Ak_cp[l];
-                len = a.Ak_cp[l + 1] - vb;
-            }
-            vbs[q][c] = vb;
-            cln[q][c] = len;
-            mylong |= len > LPL * G;
+        for (int i = 0; i < NCG; ++i) {
+            const int c = g + i * G;
+            if (c < NC) mylong |= cln[q][c] > LPL * G;
         }
         const bool longc = __ballot(mylong) != 0ull;
         // ---- b = A_0(I_j, j) and out_j (rows outside I_j)
 #pragma unroll
         for (int t = 0; t < R; ++t) bsh[q * RS + t * G + g] = 0.0;
         bsh[q * RS + trash] = 0.0;
-        const int a0 = valid ? a.A0_cp[j] : 0;
-        const int a1 = valid ? a.A0_cp[j + 1] : 0;
         int bp[LPL];
         double bv[LPL];
 #pragma unroll
@@ -224,6 +302,11 @@ k_numeric(NumericArgs a) {
                 pv[c][s] = ok ? v : 0.0;
             }
         }
+        if constexpr (PIPE) {
+            __builtin_amdgcn_sched_barrier(0);
+            stage1(grp + 1);
+            __builtin_amdgcn_sched_barrier(0);
+        }
         TQ A[R][NC];
 #pragma unroll
         for (int c0 = 0; c0 < NC; c0 += TC) {
@@ -273,12 +356,23 @@ k_numeric(NumericArgs a) {
         TQ bq[R];
 #pragma unroll
         for (int t = 0; t < R; ++t) bq[t] = (TQ)bsh[q * RS + t * G + g];
+        if constexpr (PIPE) {
+            __builtin_amdgcn_sched_barrier(0);
+            stage2();
+            __builtin_amdgcn_sched_barrier(0);
+        }
 
         // ---- Householder QR (dgeqr2's sign convention, beta = -sign(alpha) ||x||),
         //      applied to b as well
         TQ rdiag[NC], rinv[NC];
 #pragma unroll
         for (int k = 0; k < NC; ++k) {
+            if (PIPE && (k == NC / 3 || k == (2 * NC) / 3)) {
+                __builtin_amdgcn_sched_barrier(0);
+                if (k == NC / 3) stage3();
+                else stage4();
+                __builtin_amdgcn_sched_barrier(0);
+            }
             const int tk = k / G, gk = k % G;
             TQ sig = 0, alp = 0;
 #pragma unroll
@@ -331,6 +425,12 @@ k_numeric(NumericArgs a) {
                 for (int t = tk; t < R; ++t) A[t][c] -= w[c] * v[t];
 #pragma unroll
             for (int t = tk; t < R; ++t) bq[t] -= wb * v[t];
+        }
+
+        if constexpr (PIPE) {
+            __builtin_amdgcn_sched_barrier(0);
+            stage5(bi ^ 1);
+            __builtin_amdgcn_sched_barrier(0);
         }
 
         // ---- rank test: |R_kk| <= 10 * rows * eps * max |R_ii|
@@ -492,11 +592,11 @@ k_numeric(NumericArgs a) {
             // own FP64 group reduction;  R d = y;  m += d.  The new residual
             // ||b - A(m + d)||^2 = ||r||^2 - 2 d^T A^T r + ||A d||^2, where
             // d^T A^T r and ||A d||^2 both equal ||y||^2 up to rounding.
-            // Blocks of up to 16 columns keep the entries the gather loaded
+            // Blocks of up to 13 columns keep the entries the gather loaded
             // (held through the QR) for both passes; wider ones reload them
             // three columns at a time (a whole block's entries would hold
             // 3 * NC * LPL registers and cost a wave slot per SIMD).
-            constexpr int CH = NC <= 16 ? NC : 3;
+            constexpr int CH = NC <= 13 ? NC : 3;
             constexpr bool ONE = CH >= NC;
             double* rv = bsh + q * RS;
             rv[trash] = 0.0;
@@ -759,6 +859,7 @@ k_numeric(NumericArgs a) {
                 else if (nonfinite) report(a.status, j, kStNonfinite);
             }
         }
+        wave_sync();  // the next group's metadata is in LDS
     }
 }
 
