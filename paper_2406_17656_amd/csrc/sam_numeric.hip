@@ -896,17 +896,24 @@ constexpr LaunchFn backward_launcher() {
 
 // Menu per precision, cheapest first.  Shapes of the workloads: 2D 5-point
 // level 1 (13 x 5), level 2 (25 x 13); 3D 7-point level 2 (63 x 25); 2D
-// 9-point level 2 with thresholds (<= 49 x 24); weighted 3D (88 x 25).
-// The first fitting entry of a (precision, weighting) group serves a column
-// by default; later entries of the same shape class are alternatives the
-// autotuner can put in front (sam_plan_select).
+// 9-point level 2 with thresholds (ragged, mostly 20..45 x 5..20, at most
+// 49 x 24); weighted 3D (88 x 25).  The first fitting entry of a (precision,
+// weighting) group serves a column by default; later entries of the same
+// shape class are alternatives the autotuner can put in front
+// (sam_plan_select).  The FP32 classes between 36 x 10 and 48 x 24 follow the
+// ragged 9-point distribution: each halves the padded work of the columns
+// it takes from the next wider class.
 const NumericVariant kMenu[] = {
     // FP32 + refinement
     SAM_VARIANT(float, 1, 2, 8, 5, 4, 3, false),
     SAM_VARIANT(float, 1, 2, 8, 8, 4, 3, false),
+    SAM_VARIANT(float, 1, 4, 9, 10, 1, 2, false),   // ragged 9-point / thresholded blocks
+    SAM_VARIANT(float, 1, 4, 9, 12, 1, 2, false),
     SAM_VARIANT(float, 1, 4, 7, 13, 2, 2, false),
     SAM_VARIANT(float, 1, 4, 8, 16, 2, 2, false),
-    SAM_VARIANT(float, 1, 8, 5, 20, 1, 2, false),   // ragged 9-point / thresholded blocks
+    SAM_VARIANT(float, 1, 8, 5, 14, 1, 2, false),
+    SAM_VARIANT(float, 1, 8, 6, 16, 1, 2, false),
+    SAM_VARIANT(float, 1, 8, 5, 20, 1, 2, false),
     SAM_VARIANT(float, 1, 8, 6, 24, 1, 2, false),
     SAM_VARIANT(float, 1, 16, 4, 25, 1, 1, false),
     SAM_VARIANT(float, 1, 32, 4, 32, 1, 1, false),

@@ -28,10 +28,13 @@ def dev(A):
 
 def cases():
     A0, As = P.config2(m=40, nmat=2)
-    yield "cfg2-40-p1", A0, As[0], 1
-    yield "cfg2-40-p2", A0, As[0], 2
+    yield "cfg2-40-p1", A0, As[0], 1, {}
+    yield "cfg2-40-p2", A0, As[0], 2, {}
     A0, As = P.config3(m=10)
-    yield "cfg3-10-p2", A0, As[-1], 2
+    yield "cfg3-10-p2", A0, As[-1], 2, {}
+    # ragged blocks of every width from a few to ~20 columns
+    A0, As = P.config4(m=24, nmat=2)
+    yield "cfg4-24-glob-p2", A0, As[0], 2, {"kind": "global", "thresh": 0.1}
 
 
 CASES = list(cases())
@@ -41,8 +44,8 @@ CASES = list(cases())
 @pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
 def test_each_variant_first(ctx, case, prec):
     from paper_2406_17656_amd import SamError, autotune
-    _, A0, Ak, p = case
-    Sp = O.pattern(Ak, p)
+    _, A0, Ak, p, kw = case
+    Sp = O.pattern(Ak, p, **kw)
     Mo, rho, _, _ = O.sam_build(Ak, A0, Sp)
     dA0, dAk = dev(A0), dev(Ak)
     Scp, Sri = torch.as_tensor(Sp.colptr).cuda(), torch.as_tensor(Sp.rowind).cuda()
@@ -66,8 +69,8 @@ def test_each_variant_first(ctx, case, prec):
 def test_autotune_keeps_parity(ctx, tmp_path, monkeypatch):
     from paper_2406_17656_amd import autotune
     monkeypatch.setattr(autotune, "CACHE", str(tmp_path / "tune.json"))
-    _, A0, Ak, p = CASES[1]
-    Sp = O.pattern(Ak, p)
+    _, A0, Ak, p, kw = CASES[1]
+    Sp = O.pattern(Ak, p, **kw)
     dA0, dAk = dev(A0), dev(Ak)
     plan = ctx.plan(dAk, dA0, torch.as_tensor(Sp.colptr).cuda(), torch.as_tensor(Sp.rowind).cuda())
     res = autotune.tune(plan, dAk.val, dA0.val, "f32", reps=3)
