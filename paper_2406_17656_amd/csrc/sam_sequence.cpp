@@ -79,6 +79,14 @@ void bound_buckets(Combo& cb, const Combo& structural) {
         suffix += sc[b];
         cb.counts[b] = suffix;
     }
+    // a bucket whose class lies inside an earlier bucket's class never
+    // receives a column (the first fitting bucket takes it): no launch
+    for (int b = 1; b < (int)cb.counts.size(); ++b)
+        for (int e = 0; e < b; ++e)
+            if (cb.tab.max_rows[e] >= cb.tab.max_rows[b] && cb.tab.max_cols[e] >= cb.tab.max_cols[b]) {
+                cb.counts[b] = 0;
+                break;
+            }
     int live = (int)cb.counts.size();
     while (live > 0 && cb.counts[(size_t)live - 1] == 0) --live;
     cb.counts.resize((size_t)live);
