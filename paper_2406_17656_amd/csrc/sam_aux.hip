@@ -212,6 +212,21 @@ __global__ void k_spmv_rows(int n, const int* rowptr, const int* colind, const i
 
 }  // namespace
 
+__global__ void k_identity_queue(int n, int* queue, int* bstart) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) queue[i] = i;
+    if (i == 0) {
+        bstart[0] = 0;
+        bstart[1] = n;
+    }
+}
+
+hipError_t identity_queue(int n, int* queue, int* bstart, hipStream_t s) {
+    hipLaunchKernelGGL(k_identity_queue, dim3((unsigned)((std::max(n, 1) + 255) / 256)), dim3(256), 0, s, n, queue,
+                       bstart);
+    return hipGetLastError();
+}
+
 hipError_t transpose_count(int n, const int* cp, const int* ri, int64_t nnz, int* rowcount,
                            hipStream_t s) {
     (void)cp;

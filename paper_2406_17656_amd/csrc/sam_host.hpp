@@ -46,6 +46,9 @@ struct Combo {
     int* queue = nullptr;   // device n
     int* bstart = nullptr;  // device nb+1
     std::vector<int> counts;
+    // replanned sequences: one live bucket, so the queue is the identity and
+    // bstart = {0, n}, written once instead of sorting every run
+    bool identity = false;
 };
 
 struct sam_plan {

@@ -111,6 +111,8 @@ hipError_t residual_columns(int n, const int* Ak_cp, const int* Ak_ri, const dou
                             double* col_out, unsigned long long* status, hipStream_t s);
 
 // ----------------------------------------------------------------- apply
+// queue = 0..n-1 and bstart = {0, n}: every column in bucket 0
+hipError_t identity_queue(int n, int* queue, int* bstart, hipStream_t s);
 hipError_t transpose_count(int n, const int* cp, const int* ri, int64_t nnz, int* rowcount,
                            hipStream_t s);
 hipError_t transpose_fill(int n, const int* cp, const int* ri, const int* rowptr, int* cursor,

@@ -92,6 +92,21 @@ void bound_buckets(Combo& cb, const Combo& structural) {
     cb.counts.resize((size_t)live);
     cb.variants.resize(std::min(cb.variants.size(), (size_t)live));
     cb.tab.nb = std::min(cb.tab.nb, live);
+    // every structural column fits the first class, and a sparsified column
+    // only shrinks: no sort needed
+    cb.identity = live == 1;
+}
+
+// Bucket bounds of both scratch sets from the structural combination; the
+// identity queue is written here (outside any capture) when one bucket lives.
+sam_status set_bounds(sam_seq* q, hipStream_t s) {
+    for (sam_seq::Scratch& R : q->part) {
+        Combo& cb = R.dplan.combo[q->prec][0];
+        bound_buckets(cb, q->plan->combo[q->prec][0]);
+        if (cb.identity) HIP_TRY(q->ctx, samk::identity_queue(q->n, cb.queue, cb.bstart, s));
+    }
+    HIP_TRY(q->ctx, hipStreamSynchronize(s));
+    return SAM_OK;
 }
 
 void drop_graph(sam_seq* q) {
@@ -143,7 +158,9 @@ sam_status enqueue_symbolic(sam_seq* q, int k, sam_seq::Scratch& R, const double
                                             q->A0_cp, q->A0_ri, pl->eoff, pl->nI, pl->posA, pl->posB,
                                             q->plan->max_cols, q->plan->max_len_A, s));
     Combo& cb = pl->combo[q->prec][0];
-    HIP_TRY(ctx, samk::bucket_sort(n, Scp, pl->nI, cb.tab, cb.queue, cb.bstart, nullptr, ctx->d_status, R.btemp, s));
+    if (!cb.identity)
+        HIP_TRY(ctx, samk::bucket_sort(n, Scp, pl->nI, cb.tab, cb.queue, cb.bstart, nullptr, ctx->d_status, R.btemp,
+                                       s));
     return SAM_OK;
 }
 
@@ -315,7 +332,6 @@ sam_status sam_sequence_create(sam_ctx* ctx, const sam_csc* A0, const sam_csc* A
             cb.queue = cv.take<int>(n);
             cb.bstart = cv.take<int>(64);
             cb.ok = true;
-            bound_buckets(cb, q->plan->combo[q->prec][0]);
             d.colbuf = cv.take<double>(n);
             d.rtemp = cv.take<char>(samk::reduce_temp_bytes(n));
             d.device_counts = true;
@@ -329,6 +345,10 @@ sam_status sam_sequence_create(sam_ctx* ctx, const sam_csc* A0, const sam_csc* A
     }
     if (hipStreamCreateWithFlags(&q->cap, hipStreamNonBlocking) != hipSuccess)
         return bail(fail(ctx, SAM_ERR_HIP, "stream creation failed"));
+    if (q->replan) {
+        sam_status st = set_bounds(q, q->cap);
+        if (st) return bail(st);
+    }
     *out = q;
     return SAM_OK;
 }
@@ -394,8 +414,7 @@ sam_status sam_sequence_select(sam_seq* q, const int32_t* order, int32_t count, 
     sam_status st = need_device(ctx);
     if (st) return st;
     if ((st = plan_select(q->plan, q->prec, vars, S(stream)))) return st;
-    if (q->replan)
-        for (sam_seq::Scratch& R : q->part) bound_buckets(R.dplan.combo[q->prec][0], q->plan->combo[q->prec][0]);
+    if (q->replan && (st = set_bounds(q, S(stream)))) return st;
     drop_graph(q);  // the next run captures the new launches
     return SAM_OK;
 }

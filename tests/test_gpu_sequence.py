@@ -131,3 +131,34 @@ def test_pointer_change_recaptures(ctx):
         assert torch.equal(a, b)
     assert torch.equal(res2, res2b)
     seq.close()
+
+
+@pytest.mark.parametrize("case", ["structural", "thresholded"])
+def test_sequence_replanned_orders(ctx, case):
+    """Replanned sequences under an order whose first class holds every column
+    (one live bucket: the identity queue, no sort), under the default order
+    (sorted buckets), and back, on one sequence."""
+    from paper_2406_17656_amd import autotune
+    if case == "structural":
+        A0, As = P.config2(m=24, nmat=3)
+        kw = dict(kind="none")
+    else:
+        A0, As = P.config4(m=24, nmat=3)
+        kw = dict(kind="global", thresh=0.1)
+    dA0 = dev(A0)
+    dAs = [dev(A) for A in As]
+    seq = ctx.sequence(dA0, dAs[0], len(As), prec="f32", power=2, replan_each_run=True, **kw)
+    menu = autotune.menu("f32")
+    wide = max(range(len(menu)), key=lambda i: (menu[i]["G"] * menu[i]["R"], menu[i]["NC"]))
+    default = list(range(len(menu)))
+    first_wide = [wide] + [i for i in default if i != wide]
+    for order in (first_wide, default, first_wide):
+        seq.select(order)
+        Ms = seq.alloc_maps()
+        for m in Ms:
+            m.fill_(float("nan"))
+        res2 = torch.full((len(As),), float("nan"), dtype=torch.float64, device="cuda")
+        seq.run([d.val for d in dAs], Ms, res2)
+        ctx.sync_status()
+        check_maps(ctx, seq, A0, As, Ms, res2, "f32", 2, **kw)
+    seq.close()
