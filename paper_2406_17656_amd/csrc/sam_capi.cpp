@@ -290,6 +290,12 @@ int resident_blocks(const sam_ctx* ctx, const NumericVariant* v) {
     return 16;
 }
 
+int partial_capacity(const sam_ctx* ctx) {
+    int most = 16;
+    for (int r : ctx->resident) most = std::max(most, r);
+    return samk::kMaxBuckets * ctx->CUs * most;
+}
+
 // Launch every non-empty bucket of a combination, then the column-residual sum.
 sam_status run_numeric(sam_plan* pl, const double* Ak_val, const double* A0_val, const double* w, double mu, int prec,
                        int weighted, void* M_val, double* col_res2, double* res2, hipStream_t s) {
@@ -314,11 +320,14 @@ sam_status run_numeric(sam_plan* pl, const double* Ak_val, const double* A0_val,
     a.queue = cb.queue;
     a.bstart = cb.bstart;
     a.M = M_val;
-    double* cols = col_res2 ? col_res2 : pl->colbuf;
-    a.col_res2 = cols;
+    // the column residuals go to the caller's array when asked for; the
+    // Frobenius sum comes from the blocks' partial sums
+    a.col_res2 = col_res2;
+    a.part = res2 ? pl->partbuf : nullptr;
     a.status = ctx->d_status;
     a.w = w;
     a.mu = mu;
+    int parts = 0;
     for (size_t b = 0; b < cb.variants.size(); ++b) {
         // bucket sizes: exact (plan) or an upper bound (replanned sequence,
         // where the kernel reads the actual count from bstart on the device)
@@ -329,10 +338,14 @@ sam_status run_numeric(sam_plan* pl, const double* Ak_val, const double* A0_val,
         int groups = (cnt + v->per_wave() - 1) / v->per_wave();
         int grid = std::min(groups, ctx->CUs * resident_blocks(ctx, v));
         if (grid >= 64) grid = grid / 8 * 8;
+        if (res2 && parts + grid > pl->partcap)
+            return fail(ctx, SAM_ERR_HIP, "partial-sum buffer too small (%d blocks)", parts + grid);
+        a.part_base = parts;
         HIP_TRY(ctx, v->launch(a, grid, s));
+        parts += grid;
     }
-    if (res2 && pl->n > 0) HIP_TRY(ctx, samk::reduce_sum(cols, pl->n, res2, pl->rtemp, s));
-    if (res2 && pl->n == 0) HIP_TRY(ctx, hipMemsetAsync(res2, 0, sizeof(double), s));
+    if (res2 && parts > 0) HIP_TRY(ctx, samk::reduce_sum(pl->partbuf, parts, res2, pl->rtemp, s));
+    if (res2 && parts == 0) HIP_TRY(ctx, hipMemsetAsync(res2, 0, sizeof(double), s));
     return SAM_OK;
 }
 
@@ -581,7 +594,8 @@ sam_status sam_plan_create(sam_ctx* ctx, const sam_csc* Ak, const sam_csc* A0, c
                          Ak->nnz, A0->nnz, (long long)E));
     size_t mem = align256((size_t)n * 4) + align256((size_t)(n + 1) * 8) + align256((size_t)std::max<int64_t>(E, 1)) +
                  align256((size_t)std::max(A0->nnz, 1)) + 4 * (align256((size_t)n * 4) + align256(64 * 4)) +
-                 align256((size_t)n * 8) + align256(samk::reduce_temp_bytes(n)) + 1024;
+                 align256((size_t)n * 8) + align256((size_t)partial_capacity(ctx) * 8) +
+                 align256(samk::reduce_temp_bytes(std::max(n, partial_capacity(ctx)))) + 1024;
     if ((he = grow(pl->mem, mem)) != hipSuccess)
         return bail(fail(ctx, SAM_ERR_NOMEM, "plan memory (%zu bytes): %s", mem, hipGetErrorString(he)));
     Carve cv(pl->mem.p);
@@ -595,7 +609,9 @@ sam_status sam_plan_create(sam_ctx* ctx, const sam_csc* Ak, const sam_csc* A0, c
             pl->combo[p][w].bstart = cv.take<int>(64);
         }
     pl->colbuf = cv.take<double>(n);
-    pl->rtemp = cv.take<char>(samk::reduce_temp_bytes(n));
+    pl->partcap = partial_capacity(ctx);
+    pl->partbuf = cv.take<double>((size_t)pl->partcap);
+    pl->rtemp = cv.take<char>(samk::reduce_temp_bytes(std::max(n, pl->partcap)));
 
     if (n > 0) {
         std::vector<int> hnI(n);

@@ -65,7 +65,9 @@ struct sam_plan {
     unsigned char* posA = nullptr;
     unsigned char* posB = nullptr;
     double* colbuf = nullptr;
-    void* rtemp = nullptr;
+    void* rtemp = nullptr;  // reduction temp for max(n, partcap) values
+    double* partbuf = nullptr;  // per-block partial sums of the column residuals
+    int partcap = 0;
     int64_t E = 0;
     int max_rows = 0, max_cols = 0;
     // algorithmic flop counts of one build (dense column blocks)
@@ -150,6 +152,9 @@ std::vector<const samk::NumericVariant*> menu_subset(int prec, int weighted, con
                                                      bool* ok);
 // Re-bucket a plan's plain builds over a selected variant order (synchronising).
 sam_status plan_select(sam_plan* pl, int prec, const std::vector<const samk::NumericVariant*>& vars, hipStream_t s);
+// Capacity of a plan's partial-sum buffer: every bucket's launch at the
+// largest resident grid of the menu.
+int partial_capacity(const sam_ctx* ctx);
 sam_status run_numeric(sam_plan* pl, const double* Ak_val, const double* A0_val, const double* w, double mu, int prec,
                        int weighted, void* M_val, double* col_res2, double* res2, hipStream_t s);
 

@@ -28,6 +28,10 @@ struct NumericArgs {
     int bucket;           // which bucket this launch serves
     void* M;
     double* col_res2;     // n or nullptr
+    // per-block partial sums of the column residuals (the launch's blocks
+    // write part[part_base + block]); nullptr: none
+    double* part;
+    int part_base;
     unsigned long long* status;
     // soft weights (nullptr for the plain map)
     const double* w;

@@ -286,7 +286,8 @@ sam_status sam_sequence_create(sam_ctx* ctx, const sam_csc* A0, const sam_csc* A
         add((size_t)n * 4);                      // queue
         add(64 * 4);                             // bstart
         add((size_t)n * 8);                      // colbuf
-        add(samk::reduce_temp_bytes(n));
+        add((size_t)partial_capacity(ctx) * 8);  // partial sums
+        add(samk::reduce_temp_bytes(std::max(n, partial_capacity(ctx))));
         const size_t need_src = (size_t)n_src * (align256((size_t)(n + 1) * 4) +
                                                  align256((size_t)std::max<int64_t>(q->nnzS, 1) * 4));
         const size_t need = 2 * need_set + need_src;
@@ -333,7 +334,9 @@ sam_status sam_sequence_create(sam_ctx* ctx, const sam_csc* A0, const sam_csc* A
             cb.bstart = cv.take<int>(64);
             cb.ok = true;
             d.colbuf = cv.take<double>(n);
-            d.rtemp = cv.take<char>(samk::reduce_temp_bytes(n));
+            d.partcap = partial_capacity(ctx);
+            d.partbuf = cv.take<double>((size_t)d.partcap);
+            d.rtemp = cv.take<char>(samk::reduce_temp_bytes(std::max(n, d.partcap)));
             d.device_counts = true;
         }
         if (hipStreamCreateWithFlags(&q->cap2, hipStreamNonBlocking) != hipSuccess)
