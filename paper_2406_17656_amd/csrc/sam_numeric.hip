@@ -115,7 +115,7 @@ k_numeric(NumericArgs a) {
     __shared__ int cln2[2][P][NC];        // nnz of A_k(:, J_j[c])
     __shared__ int mta[P][9];             // next group: valid, j, scol, nJ, nIj, eo (2), a0, a1
     __shared__ double alsh[BACKWARD ? P * RS : 1];  // A lambda (adjoint)
-    __shared__ double rsum[P + 1];        // column residuals of the group; [P]: the block's running sum
+    __shared__ double racc;               // the block's running sum of column residuals
 
     const int lane = threadIdx.x;
     const int g = lane % G;
@@ -204,7 +204,7 @@ k_numeric(NumericArgs a) {
             }
         }
     };
-    if (lane == 0) rsum[P] = 0.0;  // this block's sum of column residuals, in group order
+    if (lane == 0) racc = 0.0;  // this block's sum of column residuals, group by group
     if constexpr (PIPE) {
         stage1(grp_lo);
         stage2();
@@ -861,19 +861,13 @@ k_numeric(NumericArgs a) {
                 else if (nonfinite) report(a.status, j, kStNonfinite);
             }
         }
-        if (a.part) {  // the group's residuals, added in problem order
-            if (g == 0) rsum[q] = valid ? rr : 0.0;
-            wave_sync();
-            if (lane == 0) {
-                double acc = rsum[P];
-#pragma unroll
-                for (int i = 0; i < P; ++i) acc += rsum[i];
-                rsum[P] = acc;
-            }
+        if (a.part) {  // the group's residuals, summed by a fixed wave-wide tree
+            const double gs = group_sum<64>((g == 0 && valid) ? rr : 0.0);
+            if (lane == 0) racc += gs;
         }
         wave_sync();  // the next group's metadata is in LDS
     }
-    if (a.part && lane == 0) a.part[a.part_base + (int)blockIdx.x] = rsum[P];
+    if (a.part && lane == 0) a.part[a.part_base + (int)blockIdx.x] = racc;
 }
 
 template <typename TQ, int G, int R, int NC, int TC, int LPL, int MODE>
