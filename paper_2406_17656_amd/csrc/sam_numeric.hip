@@ -449,18 +449,37 @@ k_numeric(NumericArgs a) {
             for (int k = 0; k < NC; ++k) bad_rank |= (k < nJ) && !(fabs(rdiag[k]) > tol);
         }
 
-        // ---- back substitution R m = c1: the lane owning row k computes, then
-        //      the value is broadcast inside the group
-        TQ m[NC];
+        // ||c2||^2 = rows nJ.. of Q^T b, before the back substitution consumes b
+        double c2sq = 0.0;
+        if constexpr (!REFINE) {
+            double r2 = 0.0;
 #pragma unroll
-        for (int k = NC - 1; k >= 0; --k) {
-            const int tk = k / G, gk = k % G;
-            TQ s = bq[tk];
-#pragma unroll
-            for (int c = k + 1; c < NC; ++c) s -= A[tk][c] * m[c];
-            const TQ mk = group_bcast<G>(s * rinv[k], g, gk);
-            m[k] = (k < nJ) ? mk : (TQ)0;
+            for (int t = 0; t < R; ++t) {
+                const double x = (double)bq[t];
+                r2 += (t * G + g >= nJ) ? x * x : 0.0;
+            }
+            c2sq = group_sum<G>(r2);
         }
+
+        // Back substitution x = R^{-1} z, column by column: z holds the right
+        // side distributed like the rows (z[t]: row t*G + g) and is consumed.
+        // x_k comes from the lane owning row k and is broadcast; then every
+        // lane takes x_k times column k off its rows in blocks t <= k / G.
+        // Rows at or below k are done by then, so the entries below the
+        // diagonal (Householder vectors) only touch finished rows.
+        auto back_solve = [&](TQ (&z)[R], TQ (&x)[NC]) {
+#pragma unroll
+            for (int k = NC - 1; k >= 0; --k) {
+                const int tk = k / G, gk = k % G;
+                const TQ xk = group_bcast<G>(z[tk] * rinv[k], g, gk);
+                x[k] = (k < nJ) ? xk : (TQ)0;
+#pragma unroll
+                for (int t = 0; t <= tk; ++t) z[t] -= A[t][k] * x[k];
+            }
+        };
+        // ---- R m = c1
+        TQ m[NC];
+        back_solve(bq, m);
 
         double* rsh = lds_tile + q * RS;  // residual vector (the tile is free now)
 
@@ -551,15 +570,7 @@ k_numeric(NumericArgs a) {
                 if (g == c % G) ydist[c / G] = yc;
             }
             TQ dl[NC];
-#pragma unroll
-            for (int k = NC - 1; k >= 0; --k) {
-                const int tk = k / G, gk = k % G;
-                TQ sacc = yrep[k];
-#pragma unroll
-                for (int c = k + 1; c < NC; ++c) sacc -= A[tk][c] * dl[c];
-                const TQ dk = group_bcast<G>(sacc * rinv[k], g, gk);
-                dl[k] = (k < nJ) ? dk : (TQ)0;
-            }
+            back_solve(ydist, dl);
             double yy = 0.0;
 #pragma unroll
             for (int c = 0; c < NC; ++c) {
@@ -692,15 +703,7 @@ k_numeric(NumericArgs a) {
                 }
             }
             TQ dl[NC];
-#pragma unroll
-            for (int k = NC - 1; k >= 0; --k) {
-                const int tk = k / G, gk = k % G;
-                TQ sacc = yrep[k];
-#pragma unroll
-                for (int c = k + 1; c < NC; ++c) sacc -= A[tk][c] * dl[c];
-                const TQ dk = group_bcast<G>(sacc * rinv[k], g, gk);
-                dl[k] = (k < nJ) ? dk : (TQ)0;
-            }
+            back_solve(ydist, dl);
             double yy = 0.0;
 #pragma unroll
             for (int c = 0; c < NC; ++c) {
@@ -754,14 +757,8 @@ k_numeric(NumericArgs a) {
         } else {
 #pragma unroll
             for (int c = 0; c < NC; ++c) mfin[c] = (double)m[c];
-            // ||c2||^2: rows nJ.. of Q^T b (the stacked form adds m^T P m)
-            double r2 = 0.0;
-#pragma unroll
-            for (int t = 0; t < R; ++t) {
-                const double x = (double)bq[t];
-                r2 += (t * G + g >= nJ) ? x * x : 0.0;
-            }
-            rr = group_sum<G>(r2);
+            // ||c2||^2 (the stacked form adds m^T P m)
+            rr = c2sq;
             if constexpr (WEIGHTED) {
 #pragma unroll
                 for (int c = 0; c < NC; ++c) rr -= pen[c] * mfin[c] * mfin[c];

@@ -111,12 +111,14 @@ def test_graph_replays_bitwise(ctx, replan):
         for a, b in zip(first, Ms):
             assert torch.equal(a, b), rep
         assert torch.equal(r_first, res2), rep
-    # same numbers as the one-shot path
+    # same map as the one-shot path; the residual sum is formed per launch
+    # block, and the replanned launches size their grids from bucket bounds,
+    # so the two sums may differ in rounding only
     for k, d in enumerate(dAs):
         cp, ri = seq.pattern(k)
         M1, _, r1 = ctx.build(d, dev(A0), cp, ri, "f32")
         assert torch.equal(M1, Ms[k][:ri.numel()])
-        assert torch.equal(r1[0], res2[k])
+        assert torch.isclose(r1[0], res2[k], rtol=1e-13, atol=0.0)
     seq.close()
 
 
