@@ -312,6 +312,35 @@ def main():
             ad[f"level1_plus_top{kk}"] = {"nnz": int(ri.numel()), "rel_res": float(np.sqrt(float(r2a.cpu()[0]) / a02)),
                                           "ms_whole_pipeline": dt * 1e3}
         variants["adaptive_map0"] = ad
+        # the adjoint: 48^3 7-point diffusion with lognormal coefficients,
+        # soft weights on the level-2 candidates (1 on S(A) and the diagonal)
+        log("timing: adjoint, 48^3 diffusion, weighted forward and backward")
+        A0c, A1c = P.config5()
+        dA0c, dA1c = DeviceCSC.from_host(A0c), DeviceCSC.from_host(A1c)
+        cp5, ri5 = ctx.pattern(dA1c, 2)
+        w5 = torch.as_tensor(P.candidate_weights(A1c.n, cp5.cpu().numpy(), ri5.cpu().numpy(), A1c),
+                             dtype=torch.float64, device="cuda")
+        mu5 = P.penalty_scale(A1c)
+        pl5 = ctx.plan(dA1c, dA0c, cp5, ri5)
+        timing = {}
+        for name, call in (("forward", lambda: pl5.build_weighted(dA1c.val, dA0c.val, w5, mu5, "f32")),
+                           ("backward", lambda: pl5.backward(dA1c.val, dA0c.val, w5, mu5, 1.0, "f32"))):
+            call()
+            ctx.sync_status()
+            torch.cuda.synchronize()
+            reps = 5
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                call()
+            torch.cuda.synchronize()
+            timing[name] = (time.perf_counter() - t0) / reps
+        ctx.sync_status()
+        pl5.close()
+        variants["adjoint_48cubed"] = {"n": A1c.n, "nnz_S": int(ri5.numel()),
+                                       "forward_cols_per_s": A1c.n / timing["forward"],
+                                       "backward_cols_per_s": A1c.n / timing["backward"],
+                                       "forward_ms": timing["forward"] * 1e3,
+                                       "backward_ms": timing["backward"] * 1e3}
     else:
         plan.close()
     rel_res = [float(np.sqrt(r / a02)) for r in r2_f32]
