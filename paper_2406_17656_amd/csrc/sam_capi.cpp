@@ -223,7 +223,7 @@ BucketTable menu_table(int prec, int weighted, std::vector<const NumericVariant*
     const NumericVariant* menu = samk::numeric_menu(&cnt);
     BucketTable tab{};
     tab.nb = 0;
-    tab.rows_plus_cols = weighted;
+    tab.penalty_rows = weighted;
     for (int i = 0; i < cnt && tab.nb < samk::kMaxBuckets; ++i) {
         if (menu[i].prec != prec || menu[i].weighted != weighted) continue;
         tab.max_rows[tab.nb] = menu[i].max_rows();
@@ -237,7 +237,7 @@ BucketTable menu_table(int prec, int weighted, std::vector<const NumericVariant*
 BucketTable table_of(const std::vector<const NumericVariant*>& vars, int weighted) {
     BucketTable tab{};
     tab.nb = (int)std::min<size_t>(vars.size(), samk::kMaxBuckets);
-    tab.rows_plus_cols = weighted;
+    tab.penalty_rows = weighted;
     for (int b = 0; b < tab.nb; ++b) {
         tab.max_rows[b] = vars[b]->max_rows();
         tab.max_cols[b] = vars[b]->NC;

@@ -81,7 +81,7 @@ hipError_t plan_positions_slots(int n, const int* S_cp, const int* S_cnt, const 
 constexpr int kMaxBuckets = 16;
 struct BucketTable {
     int nb;
-    int rows_plus_cols;   // 1: a column needs |I_j| + |J_j| rows (penalty rows)
+    int penalty_rows;     // 1: a column needs max(|I_j|, 2|J_j|) rows (two-stage QR with penalty rows)
     int max_rows[kMaxBuckets];
     int max_cols[kMaxBuckets];
 };

@@ -24,8 +24,9 @@
 // reported column residual is always recomputed in FP64 from the final m.
 //
 // Soft weights (WEIGHTED): the block is extended by the rows diag(sqrt(p_l)),
-// p_l = mu (1/w_l - 1), which the QR sees as extra rows |I_j| .. |I_j|+|J_j|-1
-// (so a variant must have G*R >= |I_j| + |J_j|); the residual excludes them.
+// p_l = mu (1/w_l - 1); the QR of the stacked matrix is taken in two stages
+// (A, then R_1 on the penalty rows), so a variant must have
+// G*R >= max(|I_j|, 2|J_j|); the residual excludes the penalty.
 #include "sam_device.hpp"
 #include "sam_kernels.hpp"
 
@@ -341,20 +342,6 @@ k_numeric(NumericArgs a) {
                     if (c0 + cc < NC) A[t][c0 + cc] = tile[(q * RS + t * G + g) * TC + cc];
             wave_sync();
         }
-        // penalty rows: row nIj + c holds sqrt(p_c) in column c
-        if constexpr (WEIGHTED) {
-#pragma unroll
-            for (int t = 0; t < R; ++t) {
-                const int row = t * G + g;
-#pragma unroll
-                for (int c = 0; c < NC; ++c) {
-                    if (valid && c < nJ && row == nIj + c) {
-                        const double wl = a.w[scol + c];
-                        A[t][c] = (TQ)sqrt(a.mu * (1.0 / wl - 1.0));
-                    }
-                }
-            }
-        }
         TQ bq[R];
 #pragma unroll
         for (int t = 0; t < R; ++t) bq[t] = (TQ)bsh[q * RS + t * G + g];
@@ -367,66 +354,109 @@ k_numeric(NumericArgs a) {
         // ---- Householder QR (dgeqr2's sign convention, beta = -sign(alpha) ||x||),
         //      applied to b as well
         TQ rdiag[NC], rinv[NC];
+        auto householder = [&]() __attribute__((always_inline)) {
 #pragma unroll
-        for (int k = 0; k < NC; ++k) {
-            if (PIPE && (k == NC / 3 || k == (2 * NC) / 3)) {
-                __builtin_amdgcn_sched_barrier(0);
-                if (k == NC / 3) stage3();
-                else stage4();
-                __builtin_amdgcn_sched_barrier(0);
+            for (int k = 0; k < NC; ++k) {
+                if (PIPE && (k == NC / 3 || k == (2 * NC) / 3)) {
+                    __builtin_amdgcn_sched_barrier(0);
+                    if (k == NC / 3) stage3();
+                    else stage4();
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+                const int tk = k / G, gk = k % G;
+                TQ sig = 0, alp = 0;
+#pragma unroll
+                for (int t = tk; t < R; ++t) {
+                    const TQ x = A[t][k];
+                    const bool below = (t > tk) || (g > gk);
+                    sig += below ? x * x : (TQ)0;
+                    if (t == tk) alp = (g == gk) ? x : (TQ)0;
+                }
+                sig = group_sum<G>(sig);
+                alp = group_sum<G>(alp);
+                const bool zero = !(sig > (TQ)0);
+                const TQ nrm = root<TQ>(alp * alp + sig);
+                const TQ beta = zero ? alp : -copysign(nrm, alp);
+                const TQ ib = recip<TQ>(beta);
+                // H = I - sigma u u^T with the unnormalised vector u = x - beta e_k
+                // (u_k = alpha - beta, x below the diagonal): the reflector of the
+                // normalised form (v_k = 1, tau = (beta - alpha) / beta) without the
+                // scaling of v; sigma = 1 / (beta (beta - alpha)), 0 when x is
+                // already a multiple of e_k.  Entries below the diagonal are not
+                // read again.
+                const TQ sigma = zero ? (TQ)0 : recip<TQ>(beta * (beta - alp));
+                rdiag[k] = beta;
+                rinv[k] = ib;
+                TQ v[R];
+#pragma unroll
+                for (int t = tk; t < R; ++t) {
+                    const bool below = (t > tk) || (g > gk);
+                    const bool diag = (t == tk) && (g == gk);
+                    v[t] = below ? A[t][k] : (diag ? alp - beta : (TQ)0);
+                    if (diag) A[t][k] = beta;
+                }
+                TQ w[NC + 1];
+#pragma unroll
+                for (int c = k + 1; c < NC; ++c) {
+                    TQ s = 0;
+#pragma unroll
+                    for (int t = tk; t < R; ++t) s += v[t] * A[t][c];
+                    w[c] = s;
+                }
+                TQ wb = 0;
+#pragma unroll
+                for (int t = tk; t < R; ++t) wb += v[t] * bq[t];
+#pragma unroll
+                for (int c = k + 1; c < NC; ++c) w[c] = group_sum<G>(w[c]) * sigma;
+                wb = group_sum<G>(wb) * sigma;
+#pragma unroll
+                for (int c = k + 1; c < NC; ++c)
+#pragma unroll
+                    for (int t = tk; t < R; ++t) A[t][c] -= w[c] * v[t];
+#pragma unroll
+                for (int t = tk; t < R; ++t) bq[t] -= wb * v[t];
             }
-            const int tk = k / G, gk = k % G;
-            TQ sig = 0, alp = 0;
+        };
+        householder();
+        // Soft weights: the penalised problem min ||A m - b||^2 + m^T P m is
+        // the least-squares problem of the stacked [A; diag(sqrt p)].  Its QR
+        // is taken in two stages: the QR of A above, then the QR of
+        // [R_1; diag(sqrt p)] (rows 0..|J_j|-1: R_1 without the reflectors
+        // below its diagonal; rows |J_j|..2|J_j|-1: the penalty rows), so a
+        // block needs max(|I_j|, 2|J_j|) rows, not |I_j| + |J_j|.  The right
+        // side keeps c_1 and drops c_2, whose norm is the first stage's share
+        // of the penalised residual.
+        double c2s1 = 0.0;
+        if constexpr (WEIGHTED) {
+            double r2 = 0.0;
 #pragma unroll
-            for (int t = tk; t < R; ++t) {
-                const TQ x = A[t][k];
-                const bool below = (t > tk) || (g > gk);
-                sig += below ? x * x : (TQ)0;
-                if (t == tk) alp = (g == gk) ? x : (TQ)0;
+            for (int t = 0; t < R; ++t) {
+                const int row = t * G + g;
+                const double x = (double)bq[t];
+                r2 += row >= nJ ? x * x : 0.0;
+                if (row >= nJ) bq[t] = (TQ)0;
             }
-            sig = group_sum<G>(sig);
-            alp = group_sum<G>(alp);
-            const bool zero = !(sig > (TQ)0);
-            const TQ nrm = root<TQ>(alp * alp + sig);
-            const TQ beta = zero ? alp : -copysign(nrm, alp);
-            const TQ ib = recip<TQ>(beta);
-            // H = I - sigma u u^T with the unnormalised vector u = x - beta e_k
-            // (u_k = alpha - beta, x below the diagonal): the reflector of the
-            // normalised form (v_k = 1, tau = (beta - alpha) / beta) without the
-            // scaling of v; sigma = 1 / (beta (beta - alpha)), 0 when x is
-            // already a multiple of e_k.  Entries below the diagonal are not
-            // read again.
-            const TQ sigma = zero ? (TQ)0 : recip<TQ>(beta * (beta - alp));
-            rdiag[k] = beta;
-            rinv[k] = ib;
-            TQ v[R];
+            c2s1 = group_sum<G>(r2);
+            // sqrt(p_c) through the (now free) LDS tile: lane g computes the
+            // columns g, g+G, ...; a lane reads the one its penalty row needs
+            TQ* sp = tile + q * RS * TC;
 #pragma unroll
-            for (int t = tk; t < R; ++t) {
-                const bool below = (t > tk) || (g > gk);
-                const bool diag = (t == tk) && (g == gk);
-                v[t] = below ? A[t][k] : (diag ? alp - beta : (TQ)0);
-                if (diag) A[t][k] = beta;
+            for (int c = g; c < NC; c += G)
+                sp[c] = (valid && c < nJ) ? (TQ)sqrt(a.mu * (1.0 / a.w[scol + c] - 1.0)) : (TQ)0;
+            wave_sync();
+#pragma unroll
+            for (int t = 0; t < R; ++t) {
+                const int row = t * G + g;
+                const int pc = row - nJ;  // penalty row of column pc
+                const TQ pv_t = (pc >= 0 && pc < nJ) ? sp[pc] : (TQ)0;
+#pragma unroll
+                for (int c = 0; c < NC; ++c) {
+                    const TQ keep = row <= c ? A[t][c] : (TQ)0;
+                    A[t][c] = row < nJ ? keep : (pc == c ? pv_t : (TQ)0);
+                }
             }
-            TQ w[NC + 1];
-#pragma unroll
-            for (int c = k + 1; c < NC; ++c) {
-                TQ s = 0;
-#pragma unroll
-                for (int t = tk; t < R; ++t) s += v[t] * A[t][c];
-                w[c] = s;
-            }
-            TQ wb = 0;
-#pragma unroll
-            for (int t = tk; t < R; ++t) wb += v[t] * bq[t];
-#pragma unroll
-            for (int c = k + 1; c < NC; ++c) w[c] = group_sum<G>(w[c]) * sigma;
-            wb = group_sum<G>(wb) * sigma;
-#pragma unroll
-            for (int c = k + 1; c < NC; ++c)
-#pragma unroll
-                for (int t = tk; t < R; ++t) A[t][c] -= w[c] * v[t];
-#pragma unroll
-            for (int t = tk; t < R; ++t) bq[t] -= wb * v[t];
+            wave_sync();
+            householder();
         }
 
         if constexpr (PIPE) {
@@ -458,7 +488,7 @@ k_numeric(NumericArgs a) {
                 const double x = (double)bq[t];
                 r2 += (t * G + g >= nJ) ? x * x : 0.0;
             }
-            c2sq = group_sum<G>(r2);
+            c2sq = group_sum<G>(r2) + c2s1;
         }
 
         // Back substitution x = R^{-1} z, column by column: z holds the right
@@ -901,7 +931,7 @@ constexpr LaunchFn backward_launcher() {
 // Menu per precision, cheapest first.  Shapes of the workloads: 2D 5-point
 // level 1 (13 x 5), level 2 (25 x 13); 3D 7-point level 2 (63 x 25); 2D
 // 9-point level 2 with thresholds (ragged, mostly 20..45 x 5..20, at most
-// 49 x 24); weighted 3D (88 x 25).  The first fitting entry of a (precision,
+// 49 x 24); weighted 3D (63 x 25 with 25 penalty rows: 64 rows in two stages).  The first fitting entry of a (precision,
 // weighting) group serves a column by default; later entries of the same
 // shape class are alternatives the autotuner can put in front
 // (sam_plan_select).  The FP32 classes between 36 x 10 and 48 x 24 follow the
@@ -935,7 +965,8 @@ const NumericVariant kMenu[] = {
     SAM_VARIANT(double, 0, 1, 13, 5, 1, 5, false),
     SAM_VARIANT(double, 0, 8, 4, 13, 2, 1, false),
     // soft-weighted (stacked penalty rows)
-    SAM_VARIANT(float, 1, 4, 8, 13, 2, 2, true),
+    SAM_VARIANT(float, 1, 4, 7, 13, 2, 2, true),
+    SAM_VARIANT(float, 1, 16, 4, 25, 1, 1, true),
     SAM_VARIANT(float, 1, 32, 3, 25, 1, 1, true),
     SAM_VARIANT(float, 1, 64, 2, 32, 1, 1, true),
     SAM_VARIANT(double, 0, 4, 8, 13, 2, 2, true),

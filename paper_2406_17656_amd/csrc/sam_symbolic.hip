@@ -697,7 +697,7 @@ hipError_t plan_positions_slots(int n, const int* S_cp, const int* S_cnt, const 
 constexpr int kBucketThreads = 256;
 
 __device__ inline int bucket_of(int nI, int nJ, const BucketTable& tab) {
-    const int rows = tab.rows_plus_cols ? nI + nJ : nI;
+    const int rows = tab.penalty_rows ? max(nI, 2 * nJ) : nI;
     for (int b = 0; b < tab.nb; ++b)
         if (rows <= tab.max_rows[b] && nJ <= tab.max_cols[b]) return b;
     return -1;
