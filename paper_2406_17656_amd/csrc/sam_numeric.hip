@@ -117,6 +117,7 @@ k_numeric(NumericArgs a) {
     __shared__ int mta[P][9];             // next group: valid, j, scol, nJ, nIj, eo (2), a0, a1
     __shared__ double alsh[BACKWARD ? P * RS : 1];  // A lambda (adjoint)
     __shared__ double racc;               // the block's running sum of column residuals
+    __shared__ double pen_sh[WEIGHTED ? P * NC : 1];  // penalties p_c of the group's problems
 
     const int lane = threadIdx.x;
     const int g = lane % G;
@@ -616,13 +617,13 @@ k_numeric(NumericArgs a) {
         };
 
         // penalty p_c = mu (1/w_c - 1) on the map's entries
-        double pen[NC];
-#pragma unroll
-        for (int c = 0; c < NC; ++c) pen[c] = 0.0;
+        // penalties p_c in LDS (read by every lane of the group, so they
+        // hold no registers across the refinement and the adjoint)
+        double* pen = pen_sh + q * NC;
         if constexpr (WEIGHTED) {
 #pragma unroll
-            for (int c = 0; c < NC; ++c)
-                if (valid && c < nJ) pen[c] = a.mu * (1.0 / a.w[scol + c] - 1.0);
+            for (int c = g; c < NC; c += G) pen[c] = (valid && c < nJ) ? a.mu * (1.0 / a.w[scol + c] - 1.0) : 0.0;
+            wave_sync();
         }
 
         double mfin[NC];
@@ -815,10 +816,10 @@ k_numeric(NumericArgs a) {
                     reset(al, false);
                     wave_sync();
                     scatter(al, lam, 1.0);
-                    double qv[NC], res[NC], dl[NC];
-                    gather(al, qv);
+                    double res[NC], dl[NC];
+                    gather(al, res);
 #pragma unroll
-                    for (int c = 0; c < NC; ++c) res[c] = h[c] - qv[c] - pen[c] * lam[c];
+                    for (int c = 0; c < NC; ++c) res[c] = h[c] - res[c] - pen[c] * lam[c];
                     solve_normal(res, dl);
 #pragma unroll
                     for (int c = 0; c < NC; ++c) lam[c] += dl[c];
