@@ -355,7 +355,47 @@ k_numeric(NumericArgs a) {
         // ---- Householder QR (dgeqr2's sign convention, beta = -sign(alpha) ||x||),
         //      applied to b as well
         TQ rdiag[NC], rinv[NC];
-        auto householder = [&]() __attribute__((always_inline)) {
+        // Soft weights: the penalised problem min ||A m - b||^2 + m^T P m is
+        // the least-squares problem of the stacked [A; diag(sqrt p)].  Its QR
+        // is taken in two stages: the QR of A, then the QR of
+        // [R_1; diag(sqrt p)] (rows 0..|J_j|-1: R_1 without the reflectors
+        // below its diagonal; rows |J_j|..2|J_j|-1: the penalty rows), so a
+        // block needs max(|I_j|, 2|J_j|) rows, not |I_j| + |J_j|.  The right
+        // side keeps c_1 and drops c_2, whose norm is the first stage's share
+        // of the penalised residual.
+        double c2s1 = 0.0;
+#pragma unroll
+        for (int stage = 0; stage < (WEIGHTED ? 2 : 1); ++stage) {
+            if (stage == 1) {
+                double r2 = 0.0;
+#pragma unroll
+                for (int t = 0; t < R; ++t) {
+                    const int row = t * G + g;
+                    const double x = (double)bq[t];
+                    r2 += row >= nJ ? x * x : 0.0;
+                    if (row >= nJ) bq[t] = (TQ)0;
+                }
+                c2s1 = group_sum<G>(r2);
+                // sqrt(p_c) through the (now free) LDS tile: lane g computes the
+                // columns g, g+G, ...; a lane reads the one its penalty row needs
+                TQ* sp = tile + q * RS * TC;
+#pragma unroll
+                for (int c = g; c < NC; c += G)
+                    sp[c] = (valid && c < nJ) ? (TQ)sqrt(a.mu * (1.0 / a.w[scol + c] - 1.0)) : (TQ)0;
+                wave_sync();
+#pragma unroll
+                for (int t = 0; t < R; ++t) {
+                    const int row = t * G + g;
+                    const int pc = row - nJ;  // penalty row of column pc
+                    const TQ pv_t = (pc >= 0 && pc < nJ) ? sp[pc] : (TQ)0;
+#pragma unroll
+                    for (int c = 0; c < NC; ++c) {
+                        const TQ keep = row <= c ? A[t][c] : (TQ)0;
+                        A[t][c] = row < nJ ? keep : (pc == c ? pv_t : (TQ)0);
+                    }
+                }
+                wave_sync();
+            }
 #pragma unroll
             for (int k = 0; k < NC; ++k) {
                 if (PIPE && (k == NC / 3 || k == (2 * NC) / 3)) {
@@ -417,47 +457,6 @@ k_numeric(NumericArgs a) {
 #pragma unroll
                 for (int t = tk; t < R; ++t) bq[t] -= wb * v[t];
             }
-        };
-        householder();
-        // Soft weights: the penalised problem min ||A m - b||^2 + m^T P m is
-        // the least-squares problem of the stacked [A; diag(sqrt p)].  Its QR
-        // is taken in two stages: the QR of A above, then the QR of
-        // [R_1; diag(sqrt p)] (rows 0..|J_j|-1: R_1 without the reflectors
-        // below its diagonal; rows |J_j|..2|J_j|-1: the penalty rows), so a
-        // block needs max(|I_j|, 2|J_j|) rows, not |I_j| + |J_j|.  The right
-        // side keeps c_1 and drops c_2, whose norm is the first stage's share
-        // of the penalised residual.
-        double c2s1 = 0.0;
-        if constexpr (WEIGHTED) {
-            double r2 = 0.0;
-#pragma unroll
-            for (int t = 0; t < R; ++t) {
-                const int row = t * G + g;
-                const double x = (double)bq[t];
-                r2 += row >= nJ ? x * x : 0.0;
-                if (row >= nJ) bq[t] = (TQ)0;
-            }
-            c2s1 = group_sum<G>(r2);
-            // sqrt(p_c) through the (now free) LDS tile: lane g computes the
-            // columns g, g+G, ...; a lane reads the one its penalty row needs
-            TQ* sp = tile + q * RS * TC;
-#pragma unroll
-            for (int c = g; c < NC; c += G)
-                sp[c] = (valid && c < nJ) ? (TQ)sqrt(a.mu * (1.0 / a.w[scol + c] - 1.0)) : (TQ)0;
-            wave_sync();
-#pragma unroll
-            for (int t = 0; t < R; ++t) {
-                const int row = t * G + g;
-                const int pc = row - nJ;  // penalty row of column pc
-                const TQ pv_t = (pc >= 0 && pc < nJ) ? sp[pc] : (TQ)0;
-#pragma unroll
-                for (int c = 0; c < NC; ++c) {
-                    const TQ keep = row <= c ? A[t][c] : (TQ)0;
-                    A[t][c] = row < nJ ? keep : (pc == c ? pv_t : (TQ)0);
-                }
-            }
-            wave_sync();
-            householder();
         }
 
         if constexpr (PIPE) {
