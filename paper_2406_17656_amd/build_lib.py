@@ -7,7 +7,9 @@ script or call ``build(force=True)``.
 from __future__ import annotations
 
 import concurrent.futures as cf
+import json
 import os
+import re
 import subprocess
 import sys
 
@@ -40,15 +42,39 @@ def _stale(obj: str, src: str) -> bool:
     return any(os.path.getmtime(d) > t for d in deps)
 
 
+_REMARK = re.compile(r"remark: +(Function Name|VGPRs|AGPRs|ScratchSize \[bytes/lane\]|"
+                     r"Occupancy \[waves/SIMD\]|LDS Size \[bytes/block\]): (\S+) \[-Rpass-analysis")
+
+
+def _resources(stderr: str) -> dict:
+    """Per-kernel register, scratch, occupancy and LDS figures from the
+    compiler's kernel-resource-usage remarks."""
+    out, cur = {}, None
+    for m in _REMARK.finditer(stderr):
+        key, val = m.group(1), m.group(2)
+        if key == "Function Name":
+            cur = out.setdefault(val, {})
+        elif cur is not None:
+            cur[key.split(" [")[0]] = int(val) if val.isdigit() else val
+    return out
+
+
+def resource_file(src: str) -> str:
+    return os.path.join(OBJDIR, os.path.splitext(src)[0] + ".resources.json")
+
+
 def _compile(src: str, force: bool) -> str:
     path = os.path.join(CSRC, src)
     obj = os.path.join(OBJDIR, os.path.splitext(src)[0] + ".o")
     if force or _stale(obj, path):
-        cmd = [HIPCC] + CFLAGS + ["-x", "hip", "-c", path, "-o", obj + ".tmp"]
+        cmd = [HIPCC] + CFLAGS + ["-Rpass-analysis=kernel-resource-usage", "-x", "hip", "-c", path,
+                                  "-o", obj + ".tmp"]
         r = subprocess.run(cmd, capture_output=True, text=True)
         if r.returncode != 0:
             raise RuntimeError(f"hipcc failed for {src}:\n{r.stdout}\n{r.stderr}")
         os.replace(obj + ".tmp", obj)
+        with open(resource_file(src), "w") as f:
+            json.dump(_resources(r.stderr), f, indent=0, sort_keys=True)
     return obj
 
 

@@ -943,7 +943,7 @@ const NumericVariant kMenu[] = {
     SAM_VARIANT(float, 1, 2, 8, 8, 4, 3, false),
     SAM_VARIANT(float, 1, 4, 9, 10, 1, 2, false),   // ragged 9-point / thresholded blocks
     SAM_VARIANT(float, 1, 4, 9, 12, 1, 2, false),
-    SAM_VARIANT(float, 1, 4, 7, 13, 2, 2, false),
+    SAM_VARIANT(float, 1, 4, 7, 13, 1, 2, false),
     SAM_VARIANT(float, 1, 4, 8, 16, 2, 2, false),
     SAM_VARIANT(float, 1, 8, 5, 14, 1, 2, false),
     SAM_VARIANT(float, 1, 8, 6, 16, 1, 2, false),
@@ -952,7 +952,6 @@ const NumericVariant kMenu[] = {
     SAM_VARIANT(float, 1, 16, 4, 25, 1, 1, false),
     SAM_VARIANT(float, 1, 32, 4, 32, 1, 1, false),
     SAM_VARIANT(float, 1, 1, 13, 5, 1, 5, false),   // one problem per lane, no reductions
-    SAM_VARIANT(float, 1, 4, 7, 13, 1, 2, false),
     SAM_VARIANT(float, 1, 8, 4, 13, 2, 1, false),
     SAM_VARIANT(float, 1, 32, 2, 25, 1, 1, false),
     // FP64
