@@ -615,9 +615,9 @@ k_numeric(NumericArgs a) {
             vec[trash] = 0.0;
         };
 
-        // penalty p_c = mu (1/w_c - 1) on the map's entries
-        // penalties p_c in LDS (read by every lane of the group, so they
-        // hold no registers across the refinement and the adjoint)
+        // penalties p_c = mu (1/w_c - 1) in LDS (read by every lane of the
+        // group, so they hold no registers across the refinement and the
+        // adjoint)
         double* pen = pen_sh + q * NC;
         if constexpr (WEIGHTED) {
 #pragma unroll
