@@ -21,7 +21,8 @@
 //     r = b - A m (FP64),  g = A^T r (FP64),  m += R^{-1} R^{-T} g,
 // with r and g accumulated in FP64 straight from the FP64 values (sparse
 // passes over the block's entries, through the LDS residual vector).  The
-// reported column residual is always recomputed in FP64 from the final m.
+// column residual is then ||r||^2 (FP64) less the update's second-order
+// term; in FP64 mode it is ||c_2||^2 of Q^T b.
 //
 // Soft weights (WEIGHTED): the block is extended by the rows diag(sqrt(p_l)),
 // p_l = mu (1/w_l - 1); the QR of the stacked matrix is taken in two stages
