@@ -284,6 +284,29 @@ def main():
                     r2_f64 = r2
         w, e, _ = time_sequence("f64", 2, True, max(5, args.steps // 2), 2)
         variants["f64_level2_replanned"] = {"cols_per_s": cols / w, "ms_per_step": w * 1e3}
+        # level 1 (13 x 5 blocks) is the case that HBM could bound: the
+        # numeric launches of one map alone (no Frobenius sum), tuned order
+        log("timing: level-1 numeric build alone")
+        cp1, ri1 = ctx.pattern(dAk[0], 1, **spec)
+        pl1 = ctx.plan(dAk[0], dA0, cp1, ri1)
+        pl1.select(tuned_order("f32", 1), "f32")
+        M1 = torch.empty(max(ri1.numel(), 1), dtype=torch.float32, device="cuda")
+        for _ in range(3):
+            pl1.build(dAk[0].val, dA0.val, "f32", M=M1, fro=False)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(20):
+            pl1.build(dAk[0].val, dA0.val, "f32", M=M1, fro=False)
+        e1.record()
+        torch.cuda.synchronize()
+        us1 = e0.elapsed_time(e1) / 20 * 1e3
+        by1 = pl1.cost("f32")["bytes"]
+        variants["f32_level1_numeric_build"] = {"us": us1, "algorithmic_bytes": by1,
+                                                "hbm_GBs": by1 / us1 / 1e3,
+                                                "hbm_frac": by1 / us1 / 1e3 / PEAK["hbm_GBs"]}
+        pl1.close()
         eq = float(max(abs(a - b) / b for a, b in zip(r2_f32, r2_f64)))
         # the one-shot API (pattern, plan with host syncs and allocation, build) per map
         log("timing: one-shot API per map")
