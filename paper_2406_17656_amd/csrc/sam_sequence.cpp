@@ -52,10 +52,10 @@ struct sam_seq {
     DevBuf lev_cp;
     Scratch part[2];
     std::vector<int*> Sk_cp, Sk_ri;
-    // graph: the symbolic chain runs on the capture stream, the numeric chain
-    // on cap2, joined by events (a parallel branch of the graph)
+    // graph: sources of even index run on the capture stream, odd ones on
+    // cap2 (two parallel branches of the graph, forked and joined by events)
     hipStream_t cap = nullptr, cap2 = nullptr;
-    std::vector<hipEvent_t> ev;    // 2 n_src + 1: symbolic done, numeric done, fork
+    std::vector<hipEvent_t> ev;    // fork, join
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     std::vector<const void*> key;
@@ -164,30 +164,31 @@ sam_status enqueue_symbolic(sam_seq* q, int k, sam_seq::Scratch& R, const double
     return SAM_OK;
 }
 
-// Replanning mode: source k's symbolic work on `s` (the capture stream) and
-// its numeric build on cap2.  Edges: numeric k after symbolic k; symbolic k
-// after numeric k-2 (which used the same scratch set); the run ends when the
-// last numeric build has joined `s`.  Symbolic k+1 thus overlaps numeric k.
+// Replanning mode: source k's symbolic work and numeric build, in that order,
+// on one of two streams chosen by the parity of k, which also picks the
+// scratch set: the capture stream for even k, cap2 for odd k.  Every edge
+// between the work of two sources is then an order within one stream
+// (symbolic k after numeric k-2, which used the same set), and the graph's
+// two branches meet only at the fork and the join.  While one branch runs a
+// numeric build (which holds most of the GPU's registers), the other branch's
+// symbolic chain takes whatever the build leaves free, and a symbolic chain's
+// last kernel hands over to its build with no edge between branches.
 sam_status enqueue_pipelined(sam_seq* q, const double* const* vals, void* const* M, double* res2, hipStream_t s) {
     sam_ctx* ctx = q->ctx;
     const int N = q->n_src;
-    hipEvent_t* ev_sym = q->ev.data();
-    hipEvent_t* ev_num = q->ev.data() + N;
-    hipEvent_t fork = q->ev[(size_t)2 * N];
+    hipEvent_t fork = q->ev[0], join = q->ev[1];
     HIP_TRY(ctx, hipEventRecord(fork, s));
     HIP_TRY(ctx, hipStreamWaitEvent(q->cap2, fork, 0));
     for (int k = 0; k < N; ++k) {
         sam_seq::Scratch& R = q->part[k & 1];
-        if (k >= 2) HIP_TRY(ctx, hipStreamWaitEvent(s, ev_num[k - 2], 0));
-        sam_status st = enqueue_symbolic(q, k, R, vals[k], s);
+        hipStream_t x = (k & 1) ? q->cap2 : s;
+        sam_status st = enqueue_symbolic(q, k, R, vals[k], x);
         if (st) return st;
-        HIP_TRY(ctx, hipEventRecord(ev_sym[k], s));
-        HIP_TRY(ctx, hipStreamWaitEvent(q->cap2, ev_sym[k], 0));
-        st = run_numeric(&R.dplan, vals[k], q->A0_val, nullptr, 0.0, q->prec, 0, M[k], nullptr, res2 + k, q->cap2);
+        st = run_numeric(&R.dplan, vals[k], q->A0_val, nullptr, 0.0, q->prec, 0, M[k], nullptr, res2 + k, x);
         if (st) return st;
-        HIP_TRY(ctx, hipEventRecord(ev_num[k], q->cap2));
     }
-    HIP_TRY(ctx, hipStreamWaitEvent(s, ev_num[N - 1], 0));
+    HIP_TRY(ctx, hipEventRecord(join, q->cap2));
+    HIP_TRY(ctx, hipStreamWaitEvent(s, join, 0));
     return SAM_OK;
 }
 
@@ -341,7 +342,7 @@ sam_status sam_sequence_create(sam_ctx* ctx, const sam_csc* A0, const sam_csc* A
         }
         if (hipStreamCreateWithFlags(&q->cap2, hipStreamNonBlocking) != hipSuccess)
             return bail(fail(ctx, SAM_ERR_HIP, "stream creation failed"));
-        q->ev.assign((size_t)2 * n_src + 1, nullptr);
+        q->ev.assign(2, nullptr);
         for (hipEvent_t& e : q->ev)
             if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess)
                 return bail(fail(ctx, SAM_ERR_HIP, "event creation failed"));

@@ -379,9 +379,13 @@ __device__ inline int word_slot(int wi) {
     return ((wi & (WPL - 1)) * GS) | (wi / WPL);
 }
 
-// Rank of row d (relative to the chunk base) inside the chunk's bitmap.
+// Rank of row d (relative to the chunk base) inside the chunk's bitmap.  The
+// word prefixes are kept as bytes saturated at 255: every rank is stored
+// clamped to 255 (254 for A_0's entries), and min(min(p, 255) + c, 255) =
+// min(p + c, 255), so the clamp is exact while the column's LDS shrinks from
+// eight bytes per word to five.
 template <int GS, int WPL>
-__device__ inline int chunk_rank(const unsigned* bm, const int* wpre, int d) {
+__device__ inline int chunk_rank(const unsigned* bm, const unsigned char* wpre, int d) {
     const int p = word_slot<GS, WPL>(d >> 5);
     return wpre[p] + __popc(bm[p] & ((1u << (d & 31)) - 1u));
 }
@@ -415,12 +419,12 @@ k_union(UnionArgs a) {
     // group stride padded by GS words: the groups of a wave start on
     // different banks
     __shared__ unsigned bm_all[kGroups][kChunkWords + GS];
-    __shared__ int pre_all[kGroups][kChunkWords + GS];
+    __shared__ unsigned char pre_all[kGroups][kChunkWords + GS];
     const int n = a.n;
     const int grp = threadIdx.x / GS;
     const int g = threadIdx.x % GS;
     unsigned* bm = bm_all[grp];
-    int* wpre = pre_all[grp];
+    unsigned char* wpre = pre_all[grp];
     auto slot = [](int wi) { return word_slot<GS, kWPL>(wi); };
     const int stride = gridDim.x * kGroups;
     auto q_len = [&](int l) { return a.Q_cnt ? a.Q_cnt[l] : a.Q_cp[l + 1] - a.Q_cp[l]; };
@@ -523,7 +527,7 @@ k_union(UnionArgs a) {
                 int run = running + pre;
 #pragma unroll
                 for (int w = 0; w < kWPL; ++w) {
-                    wpre[w * GS + g] = run;
+                    wpre[w * GS + g] = (unsigned char)min(run, 255);
                     run += __popc(wd[w]);
                 }
             }
@@ -584,9 +588,10 @@ k_union(UnionArgs a) {
     }
 }
 
-// One list per lane while the columns allow (8 lanes per column up to 8
-// lists, 16 up to 16), then two per lane (32 lists in registers); beyond
-// that the memory loops.  The rows held per list follow the longest list
+// Eight lanes per column: one list per lane up to 8 lists, two up to 16 (eight
+// columns per wave either way, the most a CU's LDS holds at once); then 16
+// lanes with two lists each (32 lists in registers); beyond that the memory
+// loops.  The rows held per list follow the longest list
 // (5, 8 or 12; longer lists take the memory loops).  Bounds <= 0: unknown.
 template <int MODE, int LEN>
 static hipError_t launch_union_len(const UnionArgs& a, int max_lists, hipStream_t s) {
@@ -597,7 +602,7 @@ static hipError_t launch_union_len(const UnionArgs& a, int max_lists, hipStream_
     if (max_lists > 0 && max_lists <= 8)
         hipLaunchKernelGGL((k_union<MODE, 8, 1, LEN>), grid(8), block, 0, s, a);
     else if (max_lists > 0 && max_lists <= 16)
-        hipLaunchKernelGGL((k_union<MODE, 16, 1, LEN>), grid(16), block, 0, s, a);
+        hipLaunchKernelGGL((k_union<MODE, 8, 2, LEN>), grid(8), block, 0, s, a);
     else
         hipLaunchKernelGGL((k_union<MODE, 16, 2, LEN>), grid(16), block, 0, s, a);
     return hipGetLastError();
