@@ -431,9 +431,24 @@ k_union(UnionArgs a) {
     for (int j = blockIdx.x * kGroups + grp; j < n; j += stride) {
         const int pa = a.P_cp[j];
         const int pb = a.P_cnt ? pa + a.P_cnt[j] : a.P_cp[j + 1];
+        // The column's output operands are loaded here, beside the list
+        // loads: a store through a byte or int pointer may alias them, so a
+        // load issued after the first store would wait for every store before
+        // it, one more memory round trip per column.  a0r: the A_0 entry
+        // a0a + g, the first this lane handles.
+        int a0a = 0, a0b = 0, a0r = 0, oc = 0, ob = 0;
+        int64_t eo = 0;
+        if (MODE == kModePositions) {
+            a0a = a.A0_cp[j];
+            a0b = a.A0_cp[j + 1];
+            eo = a.eoff[j];
+            if (a.cP_ri) oc = a.cP_cp[j] - pa;
+            if (a0a + g < a0b) a0r = a.A0_ri[a0a + g];
+        }
+        if (MODE == kModeFill) ob = a.out_cp[j];
         // lists t = pa + g + GS u of this lane (all loads independent); `big`
         // marks columns that need the memory loops
-        int qa[ROUNDS], len[ROUNDS], lofs[ROUNDS];
+        int qa[ROUNDS], len[ROUNDS], lofs[ROUNDS], lraw[ROUNDS];
         int rows[ROUNDS][kListLen];
         int big = (pb - pa > GS * ROUNDS) ? 1 : 0;
         int lo = INT_MAX, carry = 0;
@@ -441,8 +456,9 @@ k_union(UnionArgs a) {
         for (int u = 0; u < ROUNDS; ++u) {
             const int t = pa + g + u * GS;
             int l = -1;
+            lraw[u] = 0;
             if (t < pb) {
-                l = a.P_ri[t];
+                l = lraw[u] = a.P_ri[t];
                 if (l < 0 || l >= n) {
                     if (a.bad) atomicMin(a.bad, j);
                     l = -1;
@@ -477,10 +493,12 @@ k_union(UnionArgs a) {
         }
         lo = grp_min<GS>(lo);
         if (MODE == kModePositions) {
-            for (int e = a.A0_cp[j] + g; e < a.A0_cp[j + 1]; e += GS) a.posB[e] = 0xFF;
+            for (int e = a0a + g; e < a0b; e += GS) a.posB[e] = 0xFF;
             if (a.cP_ri) {
-                const int oc = a.cP_cp[j] - pa;
-                for (int t = pa + g; t < pb; t += GS) a.cP_ri[oc + t] = a.P_ri[t];
+#pragma unroll
+                for (int u = 0; u < ROUNDS; ++u)
+                    if (pa + g + u * GS < pb) a.cP_ri[oc + pa + g + u * GS] = lraw[u];
+                for (int t = pa + g + ROUNDS * GS; t < pb; t += GS) a.cP_ri[oc + t] = a.P_ri[t];
             }
         }
         int running = 0;
@@ -532,7 +550,7 @@ k_union(UnionArgs a) {
                 }
             }
             if (MODE == kModeFill) {
-                int o = a.out_cp[j] + running + pre;
+                int o = ob + running + pre;
 #pragma unroll
                 for (int w = 0; w < kWPL; ++w) {
                     unsigned x = wd[w];
@@ -546,7 +564,7 @@ k_union(UnionArgs a) {
             if (MODE == kModePositions) {
                 wave_sync();
                 // ranks of the gathered A_k entries, in the order of the lists
-                unsigned char* pj = a.posA + a.eoff[j];
+                unsigned char* pj = a.posA + eo;
                 if (!big) {
 #pragma unroll
                     for (int u = 0; u < ROUNDS; ++u)
@@ -574,8 +592,8 @@ k_union(UnionArgs a) {
                         cy += grp_sum<GS>(ln);
                     }
                 }
-                for (int e = a.A0_cp[j] + g; e < a.A0_cp[j + 1]; e += GS) {
-                    const int d = a.A0_ri[e] - base;
+                for (int e = a0a + g; e < a0b; e += GS) {
+                    const int d = (e == a0a + g ? a0r : a.A0_ri[e]) - base;
                     if (d >= 0 && d < kChunk && ((bm[slot(d >> 5)] >> (d & 31)) & 1u))
                         a.posB[e] = (unsigned char)min(chunk_rank<GS, kWPL>(bm, wpre, d), 254);
                 }
