@@ -236,26 +236,42 @@ __device__ inline int lfil_rank(int j, int a, int b, int e, const int* ri, const
     return rank;
 }
 
+// The first kSpReg entries of a column are loaded before anything is
+// stored: a store through out_ri may alias ri, so a load issued after it
+// would wait for the store before it, one memory round trip per entry.
+constexpr int kSpReg = 8;
+
 template <bool FILL>
 __global__ void k_sparsify(int n, const int* cp, const int* ri, const double* v, SparsifySpec sp,
                            const double* D, int* counts, const int* out_cp, int* out_ri) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= n) return;
     const int a = cp[j], b = cp[j + 1];
+    const int o = FILL ? out_cp[j] : 0;
+    int rr[kSpReg];
+    double vr[kSpReg];
+#pragma unroll
+    for (int u = 0; u < kSpReg; ++u) {
+        const bool ok = a + u < b;
+        rr[u] = ok ? ri[a + u] : 0;
+        vr[u] = (ok && v) ? v[a + u] : 0.0;
+    }
     double colmax = 0.0;
-    if (sp.kind == 2)
-        for (int e = a; e < b; ++e) colmax = fmax(colmax, fabs(v[e]));
+    if (sp.kind == 2) {
+#pragma unroll
+        for (int u = 0; u < kSpReg; ++u)
+            if (a + u < b) colmax = fmax(colmax, fabs(vr[u]));
+        for (int e = a + kSpReg; e < b; ++e) colmax = fmax(colmax, fabs(v[e]));
+    }
     int cnt = 0;
     bool diag_done = false;
-    int o = FILL ? out_cp[j] : 0;
-    for (int e = a; e < b; ++e) {
-        const int i = ri[e];
+    auto visit = [&](int e, int i, double x) {
         bool keep;
         if (i == j) {
             keep = true;
         } else {
             int rk = sp.kind == 3 ? lfil_rank(j, a, b, e, ri, v) : 0;
-            keep = keep_entry(j, i, v ? v[e] : 0.0, sp, D, colmax, rk);
+            keep = keep_entry(j, i, x, sp, D, colmax, rk);
         }
         if (!diag_done && i > j) {  // diagonal not stored: insert before
             if (FILL) out_ri[o + cnt] = j;
@@ -267,7 +283,11 @@ __global__ void k_sparsify(int n, const int* cp, const int* ri, const double* v,
             if (FILL) out_ri[o + cnt] = i;
             ++cnt;
         }
-    }
+    };
+#pragma unroll
+    for (int u = 0; u < kSpReg; ++u)
+        if (a + u < b) visit(a + u, rr[u], vr[u]);
+    for (int e = a + kSpReg; e < b; ++e) visit(e, ri[e], v ? v[e] : 0.0);
     if (!diag_done) {
         if (FILL) out_ri[o + cnt] = j;
         ++cnt;
