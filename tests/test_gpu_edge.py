@@ -110,3 +110,33 @@ def test_small_replanned_sequence(ctx):
         assert wc <= TOL["f32"], (k, wc)
         assert np.isclose(float(host(res2)[k]), rho.sum(), rtol=1e-9, atol=1e-300)
     seq.close()
+
+
+@pytest.mark.parametrize("nsrc", [1, 2, 5])
+def test_replanned_source_counts(ctx, nsrc):
+    """Replanned sequences of one, two and five sources: the sources are
+    split over two graph branches by parity, so these cover an empty second
+    branch, one source per branch and unequal branches.  Every map against
+    the oracle, and a second replay bit for bit equal to the first."""
+    A0, As = P.config2(m=20, nmat=nsrc + 1)   # the target and nsrc sources
+    assert len(As) == nsrc
+    dA0 = dev(A0)
+    dAs = [dev(A) for A in As]
+    seq = ctx.sequence(dA0, dAs[0], nsrc, prec="f32", power=2, replan_each_run=True)
+    Ms = seq.alloc_maps()
+    res2 = torch.zeros(nsrc, dtype=torch.float64, device="cuda")
+    seq.run([d.val for d in dAs], Ms, res2)
+    ctx.sync_status()
+    first = [host(M).copy() for M in Ms]
+    r_first = host(res2).copy()
+    seq.run([d.val for d in dAs], Ms, res2)
+    ctx.sync_status()
+    for k, Ak in enumerate(As):
+        assert np.array_equal(host(Ms[k]), first[k]), k
+        Sp = O.pattern(Ak, 2)
+        Mo, rho, _, _ = O.sam_build(Ak, A0, Sp)
+        wc, _ = colmax_rel(host(Ms[k][:Sp.nnz]).astype(np.float64), Mo, Sp.colptr)
+        assert wc <= TOL["f32"], (k, wc)
+        assert np.isclose(float(host(res2)[k]), rho.sum(), rtol=1e-9, atol=1e-300)
+    assert np.array_equal(host(res2), r_first)
+    seq.close()
