@@ -18,6 +18,9 @@
 
 using namespace samh;
 
+// Replanning sequences: graph branches, each with its own scratch set.
+constexpr int kBranches = 3;
+
 struct sam_seq {
     sam_ctx* ctx = nullptr;
     int n = 0;
@@ -50,12 +53,14 @@ struct sam_seq {
     };
     DevBuf dyn;
     DevBuf lev_cp;
-    Scratch part[2];
+    Scratch part[kBranches];
     std::vector<int*> Sk_cp, Sk_ri;
-    // graph: sources of even index run on the capture stream, odd ones on
-    // cap2 (two parallel branches of the graph, forked and joined by events)
-    hipStream_t cap = nullptr, cap2 = nullptr;
-    std::vector<hipEvent_t> ev;    // fork, join
+    // graph: source k runs on branch k mod kBranches, branch 0 being the
+    // capture stream and the others side[] (parallel branches of the graph,
+    // forked and joined by events)
+    hipStream_t cap = nullptr;
+    hipStream_t side[kBranches - 1] = {};
+    std::vector<hipEvent_t> ev;    // fork, then one join per side stream
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     std::vector<const void*> key;
@@ -165,30 +170,33 @@ sam_status enqueue_symbolic(sam_seq* q, int k, sam_seq::Scratch& R, const double
 }
 
 // Replanning mode: source k's symbolic work and numeric build, in that order,
-// on one of two streams chosen by the parity of k, which also picks the
-// scratch set: the capture stream for even k, cap2 for odd k.  Every edge
-// between the work of two sources is then an order within one stream
-// (symbolic k after numeric k-2, which used the same set), and the graph's
-// two branches meet only at the fork and the join.  While one branch runs a
-// numeric build (which holds most of the GPU's registers), the other branch's
-// symbolic chain takes whatever the build leaves free, and a symbolic chain's
-// last kernel hands over to its build with no edge between branches.
+// on branch k mod kBranches, which also picks the scratch set: the capture
+// stream for branch 0, side[b - 1] for branch b.  Every edge between the work
+// of two sources is then an order within one stream (symbolic k after numeric
+// k - kBranches, which used the same set), and the branches meet only at the
+// fork and the join.  While one branch runs a numeric build (which holds most
+// of the GPU's registers), the others' symbolic chains take whatever the
+// build leaves free, and a symbolic chain's last kernel hands over to its
+// build with no edge between branches.
 sam_status enqueue_pipelined(sam_seq* q, const double* const* vals, void* const* M, double* res2, hipStream_t s) {
     sam_ctx* ctx = q->ctx;
     const int N = q->n_src;
-    hipEvent_t fork = q->ev[0], join = q->ev[1];
+    hipEvent_t fork = q->ev[0];
     HIP_TRY(ctx, hipEventRecord(fork, s));
-    HIP_TRY(ctx, hipStreamWaitEvent(q->cap2, fork, 0));
+    for (hipStream_t x : q->side) HIP_TRY(ctx, hipStreamWaitEvent(x, fork, 0));
     for (int k = 0; k < N; ++k) {
-        sam_seq::Scratch& R = q->part[k & 1];
-        hipStream_t x = (k & 1) ? q->cap2 : s;
+        const int b = k % kBranches;
+        sam_seq::Scratch& R = q->part[b];
+        hipStream_t x = b == 0 ? s : q->side[b - 1];
         sam_status st = enqueue_symbolic(q, k, R, vals[k], x);
         if (st) return st;
         st = run_numeric(&R.dplan, vals[k], q->A0_val, nullptr, 0.0, q->prec, 0, M[k], nullptr, res2 + k, x);
         if (st) return st;
     }
-    HIP_TRY(ctx, hipEventRecord(join, q->cap2));
-    HIP_TRY(ctx, hipStreamWaitEvent(s, join, 0));
+    for (int b = 1; b < kBranches; ++b) {
+        HIP_TRY(ctx, hipEventRecord(q->ev[b], q->side[b - 1]));
+        HIP_TRY(ctx, hipStreamWaitEvent(s, q->ev[b], 0));
+    }
     return SAM_OK;
 }
 
@@ -291,7 +299,7 @@ sam_status sam_sequence_create(sam_ctx* ctx, const sam_csc* A0, const sam_csc* A
         add(samk::reduce_temp_bytes(std::max(n, partial_capacity(ctx))));
         const size_t need_src = (size_t)n_src * (align256((size_t)(n + 1) * 4) +
                                                  align256((size_t)std::max<int64_t>(q->nnzS, 1) * 4));
-        const size_t need = 2 * need_set + need_src;
+        const size_t need = kBranches * need_set + need_src;
         hipError_t he = grow(q->dyn, need + 4096);
         if (he != hipSuccess) return bail(fail(ctx, SAM_ERR_NOMEM, "sequence buffers (%zu bytes): %s", need,
                                                hipGetErrorString(he)));
@@ -340,9 +348,10 @@ sam_status sam_sequence_create(sam_ctx* ctx, const sam_csc* A0, const sam_csc* A
             d.rtemp = cv.take<char>(samk::reduce_temp_bytes(std::max(n, d.partcap)));
             d.device_counts = true;
         }
-        if (hipStreamCreateWithFlags(&q->cap2, hipStreamNonBlocking) != hipSuccess)
-            return bail(fail(ctx, SAM_ERR_HIP, "stream creation failed"));
-        q->ev.assign(2, nullptr);
+        for (hipStream_t& x : q->side)
+            if (hipStreamCreateWithFlags(&x, hipStreamNonBlocking) != hipSuccess)
+                return bail(fail(ctx, SAM_ERR_HIP, "stream creation failed"));
+        q->ev.assign(kBranches, nullptr);
         for (hipEvent_t& e : q->ev)
             if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess)
                 return bail(fail(ctx, SAM_ERR_HIP, "event creation failed"));
@@ -365,7 +374,8 @@ sam_status sam_sequence_destroy(sam_seq* q) {
     }
     drop_graph(q);
     if (q->cap) (void)hipStreamDestroy(q->cap);
-    if (q->cap2) (void)hipStreamDestroy(q->cap2);
+    for (hipStream_t x : q->side)
+        if (x) (void)hipStreamDestroy(x);
     for (hipEvent_t e : q->ev)
         if (e) (void)hipEventDestroy(e);
     if (q->plan) sam_plan_destroy(q->plan);

@@ -114,10 +114,10 @@ def test_small_replanned_sequence(ctx):
 
 @pytest.mark.parametrize("nsrc", [1, 2, 5])
 def test_replanned_source_counts(ctx, nsrc):
-    """Replanned sequences of one, two and five sources: the sources are
-    split over two graph branches by parity, so these cover an empty second
-    branch, one source per branch and unequal branches.  Every map against
-    the oracle, and a second replay bit for bit equal to the first."""
+    """Replanned sequences of one, two and five sources: the sources rotate
+    over three graph branches, so these cover two empty branches, one empty
+    branch, and branches of unequal length.  Every map against the oracle, and
+    a second replay bit for bit equal to the first."""
     A0, As = P.config2(m=20, nmat=nsrc + 1)   # the target and nsrc sources
     assert len(As) == nsrc
     dA0 = dev(A0)
