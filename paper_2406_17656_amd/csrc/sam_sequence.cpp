@@ -102,7 +102,7 @@ void bound_buckets(Combo& cb, const Combo& structural) {
     cb.identity = live == 1;
 }
 
-// Bucket bounds of both scratch sets from the structural combination; the
+// Bucket bounds of every scratch set from the structural combination; the
 // identity queue is written here (outside any capture) when one bucket lives.
 sam_status set_bounds(sam_seq* q, hipStream_t s) {
     for (sam_seq::Scratch& R : q->part) {
