@@ -106,15 +106,21 @@ k_numeric(NumericArgs a) {
     constexpr int RS = RX + (((G - RX) % 16) + 16) % 16;
     constexpr bool REFINE = std::is_same<TQ, float>::value;
     static_assert(TC >= 1, "tile chunk");
-    // gather staging in the QR's precision; afterwards the same memory holds
-    // the FP64 residual vector (P * RS doubles)
+    // Per-group metadata is software-pipelined for blocks of 8 to 13 columns
+    // of the plain map (see the stages below); only they double-buffer the
+    // column extents.
+    constexpr bool PIPE = NC >= 8 && NC <= 13 && MODE == 0;
+    // gather staging in the QR's precision; afterwards the weighted and
+    // adjoint forms reuse the same memory for the FP64 residual vector
+    // (P * RS doubles; the plain map forms its residual over b instead)
     constexpr int kTileD = (P * RS * TC * (int)sizeof(TQ) + 7) / 8;
-    __shared__ double lds_tile[kTileD > P * RS ? kTileD : P * RS];
+    constexpr int kResD = (WEIGHTED || BACKWARD) ? P * RS : 1;
+    __shared__ double lds_tile[kTileD > kResD ? kTileD : kResD];
     TQ* tile = reinterpret_cast<TQ*>(lds_tile);
     __shared__ double bsh[P * RS];        // b = A_0(I_j, j)
     __shared__ int cst[P][NC + 1];        // entry offset of column c in the block
-    __shared__ int vbs2[2][P][NC];        // start of A_k(:, J_j[c]) in the value array
-    __shared__ int cln2[2][P][NC];        // nnz of A_k(:, J_j[c])
+    __shared__ int vbs2[PIPE ? 2 : 1][P][NC];  // start of A_k(:, J_j[c]) in the value array
+    __shared__ int cln2[PIPE ? 2 : 1][P][NC];  // nnz of A_k(:, J_j[c])
     __shared__ int mta[P][9];             // next group: valid, j, scol, nJ, nIj, eo (2), a0, a1
     __shared__ double alsh[BACKWARD ? P * RS : 1];  // A lambda (adjoint)
     __shared__ double racc;               // the block's running sum of column residuals
@@ -137,7 +143,7 @@ k_numeric(NumericArgs a) {
     const __amdgpu_buffer_rsrc_t rPA = buf_rsrc(a.posA, a.E);
     const __amdgpu_buffer_rsrc_t rPB = buf_rsrc(a.posB, a.nnzA0);
 
-    // Per-group metadata is software-pipelined: the dependent loads that
+    // Per-group metadata pipelining: the dependent loads that
     // locate group grp + 1 (its queue entry; its pattern and row-set data;
     // its pattern columns; their extents in A_k) are issued in stages while
     // group grp is solved and land in LDS (the column extents in the other
@@ -147,7 +153,6 @@ k_numeric(NumericArgs a) {
     // the weighted forms have no registers to spare (and the narrowest lose
     // a wave slot per SIMD): they run the same stages for their own group at
     // its top.
-    constexpr bool PIPE = NC >= 8 && NC <= 13 && MODE == 0;
     constexpr int NCG = (NC + G - 1) / G;
     bool n_valid = false;
     int n_j = 0, n_cp0 = 0, n_cp1 = 0, n_nI = 0, n_a0 = 0, n_a1 = 0;
