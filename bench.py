@@ -122,9 +122,9 @@ def main():
     ap.add_argument("--workload", choices=sorted(WORKLOADS), default="diffusion2d")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the column problems "
-              "would shard across GPUs by contiguous column ranges with one halo exchange, which "
-              "this build does not run.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): sharding the column "
+              "problems across GPUs (contiguous column ranges, one halo exchange of A_k columns) "
+              "is not implemented.", file=sys.stderr)
         sys.exit(2)
     if args.copy_calibration:
         copy_calibration()
