@@ -302,10 +302,38 @@ def main():
         e1.record()
         torch.cuda.synchronize()
         us1 = e0.elapsed_time(e1) / 20 * 1e3
+        # The map's 47 MB fit in the 256 MB last-level cache (MALL), so the
+        # repeated launches above read much of it from there.  Cold: a 1 GiB
+        # write before each launch evicts L2 and the MALL, and each launch is
+        # timed alone, so its bytes come from HBM.
+        # The same one-launch bracket without the flush gives the bracket's own
+        # overhead (warm_single_us against us); cold_kernel_us takes it off.
+        flush = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+        cold = warm1 = 0.0
+        for flushed in (True, False):
+            for _ in range(10):
+                if flushed:
+                    flush.fill_(1.0)
+                e0.record()
+                pl1.build(dAk[0].val, dA0.val, "f32", M=M1, fro=False)
+                e1.record()
+                torch.cuda.synchronize()
+                if flushed:
+                    cold += e0.elapsed_time(e1)
+                else:
+                    warm1 += e0.elapsed_time(e1)
+        del flush
+        us1c = cold / 10 * 1e3
+        us1k = us1c - (warm1 / 10 * 1e3 - us1)
         by1 = pl1.cost("f32")["bytes"]
         variants["f32_level1_numeric_build"] = {"us": us1, "algorithmic_bytes": by1,
                                                 "hbm_GBs": by1 / us1 / 1e3,
-                                                "hbm_frac": by1 / us1 / 1e3 / PEAK["hbm_GBs"]}
+                                                "hbm_frac": by1 / us1 / 1e3 / PEAK["hbm_GBs"],
+                                                "cold_us": us1c,
+                                                "warm_single_us": warm1 / 10 * 1e3,
+                                                "cold_kernel_us": us1k,
+                                                "cold_hbm_GBs": by1 / us1k / 1e3,
+                                                "cold_hbm_frac": by1 / us1k / 1e3 / PEAK["hbm_GBs"]}
         pl1.close()
         eq = float(max(abs(a - b) / b for a, b in zip(r2_f32, r2_f64)))
         # the one-shot API (pattern, plan with host syncs and allocation, build) per map
