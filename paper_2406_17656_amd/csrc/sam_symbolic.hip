@@ -18,8 +18,8 @@ namespace samk {
 namespace {
 
 constexpr int kScanThreads = 256;
-constexpr int kScanItems = 8;
-constexpr int kScanTile = kScanThreads * kScanItems;   // 2048 values per tile
+constexpr int kScanItems = 4;
+constexpr int kScanTile = kScanThreads * kScanItems;   // 1024 values per tile
 
 int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
@@ -122,7 +122,7 @@ k_scan_apply(const Tin* src, int64_t n_in, int64_t N, const int64_t* tile_sum, c
     if (overflow && big) atomicOr(overflow, 1);
 }
 
-constexpr int64_t kDirectTiles = 1024;   // tiles summed directly by pass 2
+constexpr int64_t kDirectTiles = 2048;   // tiles summed directly by pass 2
 
 int64_t scan_tiles(int64_t N) { return std::max<int64_t>(ceil_div(N, kScanTile), 1); }
 
