@@ -83,12 +83,31 @@ WORKLOADS = {
 }
 
 
-def make_inputs(P, name, grid):
+def make_inputs(P, name, grid=512):
     if name == "diffusion2d":
         return P.config2(m=grid, nmat=8)
     if name.startswith("convdiff3d"):
         return P.config3()
     return P.config4()
+
+
+def tune_order(ctx, dAk0, dA0, prec, power, spec, reps=5):
+    """The autotuner's variant order for a (precision, pattern) pair, timed
+    on the first source's plan on this GPU (not cached)."""
+    from paper_2406_17656_amd import autotune
+    cp, ri = ctx.pattern(dAk0, power, **spec)
+    pl = ctx.plan(dAk0, dA0, cp, ri)
+    res = autotune.tune(pl, dAk0.val, dA0.val, prec, reps=reps, use_cache=False)
+    pl.close()
+    return res
+
+
+def step_sequence(ctx, dA0, dAk0, nmaps, prec, power, spec, order, replan=True):
+    """The timed step: every source's pattern, plan, build and residual in
+    one graph-captured sequence, with the given variant order."""
+    seq = ctx.sequence(dA0, dAk0, nmaps, prec=prec, power=power, replan_each_run=replan, **spec)
+    seq.select(order)
+    return seq
 
 
 def log(*a):
@@ -161,18 +180,14 @@ def main():
 
     def tuned_order(prec, power):
         if (prec, power) not in tuned:
-            cp, ri = ctx.pattern(dAk[0], power, **spec)
-            pl = ctx.plan(dAk[0], dA0, cp, ri)
-            res = autotune.tune(pl, dAk[0].val, dA0.val, prec, reps=5, use_cache=False)
-            pl.close()
+            res = tune_order(ctx, dAk[0], dA0, prec, power, spec)
             tuned[(prec, power)] = res
             log(f"autotune {prec} level {power}: order {res['order'][:3]}..., {res['us']:.1f} us/map")
         return tuned[(prec, power)]["order"]
 
     def time_sequence(prec, power, replan, steps, warmup):
         order = tuned_order(prec, power)
-        seq = ctx.sequence(dA0, dAk[0], nmaps, prec=prec, power=power, replan_each_run=replan, **spec)
-        seq.select(order)
+        seq = step_sequence(ctx, dA0, dAk[0], nmaps, prec, power, spec, order, replan)
         Ms = seq.alloc_maps()
         res2 = torch.zeros(nmaps, dtype=torch.float64, device="cuda")
         for _ in range(warmup):

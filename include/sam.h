@@ -67,9 +67,12 @@ typedef enum {
 /* Arithmetic of the least-squares solves.
  * SAM_PREC_F64: Householder QR, solve and residual in FP64; M values FP64.
  * SAM_PREC_F32_REFINE: Householder QR and triangular solves in FP32, then one
- *   seminormal refinement step m += R^{-1} R^{-T} A^T (b - A m) whose residual
- *   and A^T r are accumulated in FP64 from the FP64 inputs; the per-column
- *   residual is recomputed in FP64 from the refined m; M values stored FP32. */
+ *   seminormal refinement step m += d, d = R^{-1} y, R^T y = A^T (b - A m),
+ *   whose residual r = b - A m and A^T r are accumulated in FP64 from the
+ *   FP64 inputs; the per-column residual is ||r||^2 - ||y||^2 (+ the A_0
+ *   entries outside I_j), the FP64 residual of the unrefined m less the
+ *   step's decrease (exact up to rounding in the FP32 factor R); M values
+ *   stored FP32. */
 typedef enum { SAM_PREC_F64 = 0, SAM_PREC_F32_REFINE = 1 } sam_precision;
 
 /* Sparsification of A_k before the level expansion (Section 4).  The

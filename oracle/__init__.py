@@ -13,6 +13,8 @@ columns).  Each wrapper names the passage of the paper it follows:
 * ``row_sets``   -- Section 2, the rows touched by the columns J_j.
 * ``sam_build``  -- Section 2, eq. (approx_map) split into column problems.
 * ``residual``   -- Section 2, eq. (res), Frobenius norm used in Section 5.
+* ``frobenius_sq`` -- Section 2, eq. (res): ||R||_F^2 as the sum of the
+                    column residuals, correctly rounded (math.fsum).
 * ``apply``      -- y = M x (definition).
 * ``backward``   -- exact gradient of ||A_k M - A_0||_F^2 (not in the paper;
                     derived from the normal equations, see sam_oracle.c).
@@ -24,6 +26,7 @@ columns).  Each wrapper names the passage of the paper it follows:
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 import subprocess
 from dataclasses import dataclass
@@ -164,6 +167,13 @@ def sam_build(Ak, A0, S: Pattern, cols=None, weights=None, mu=0.0, raise_on_erro
     if st and raise_on_error:
         raise OracleError(st, int(bad[0]))
     return M, rho, int(st), int(bad[0])
+
+
+def frobenius_sq(rho) -> float:
+    """||R||_F^2 = sum_j rho_j (Section 2, eq. res: the squared Frobenius
+    norm is the sum of the squared column norms).  math.fsum returns the
+    correctly rounded sum, so no summation order is implied."""
+    return math.fsum(float(x) for x in np.asarray(rho, dtype=np.float64))
 
 
 def residual(Ak, A0, S: Pattern, M_val):

@@ -40,9 +40,9 @@ struct sam_seq {
     // replanning mode: every level of the pattern is written into slots laid
     // out like the structural level (lev_cp, p arrays of n+1), with its
     // column lengths beside it; only the final S_k is compacted (Sk_cp/Sk_ri)
-    // Two sets of scratch and plan arrays: the symbolic work of source k+1
-    // (set (k+1) % 2) runs while the numeric build of source k (set k % 2)
-    // still reads its plan.
+    // kBranches sets of scratch and plan arrays: the symbolic work of the
+    // next sources (set (k+1) % kBranches, ...) runs while the numeric build
+    // of source k (set k % kBranches) still reads its plan.
     struct Scratch {
         sam_plan dplan;            // views into dyn
         int *B_ri = nullptr, *B_cnt = nullptr, *L_ri[2] = {nullptr, nullptr}, *L_cnt[2] = {nullptr, nullptr},

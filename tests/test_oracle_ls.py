@@ -268,3 +268,19 @@ def test_near_diagonal_blocks_stable():
     M, rho, _, _ = O.sam_build(Ak, A0, S)
     Ml, rl = lstsq_map(Ak, A0, S)
     assert colmax_rel(M, Ml, S) < 1e-10
+
+
+def test_frobenius_sum_is_exactly_rounded():
+    """The oracle's ||R||_F^2 (sum of column residuals) equals the exact
+    rational sum of the same doubles, rounded once, also where plain
+    left-to-right summation loses the small terms."""
+    rng = np.random.default_rng(7)
+    rho = np.concatenate([[1e16], rng.uniform(0, 1, 5000), [-1e16]])
+    exact = float(sum(Fraction(float(x)) for x in rho))
+    assert O.frobenius_sq(rho) == exact
+    naive = 0.0
+    for x in rho:
+        naive += x
+    assert naive != exact          # the case does separate the two sums
+    r = rng.uniform(0, 1, 1000)
+    assert O.frobenius_sq(r) == float(sum(Fraction(float(x)) for x in r))
