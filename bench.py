@@ -352,15 +352,30 @@ def main():
         pl1.close()
         eq = float(max(abs(a - b) / b for a, b in zip(r2_f32, r2_f64)))
         # the one-shot API (pattern, plan with host syncs and allocation, build) per map
-        log("timing: one-shot API per map")
-        t0 = time.perf_counter()
-        for k, A in enumerate(dAk):
-            cp, ri = ctx.pattern(A, 2)
-            pl = ctx.plan(A, dA0, cp, ri)
-            pl.build(A.val, dA0.val, "f32")
-            pl.close()
-        torch.cuda.synchronize()
-        variants["f32_level2_oneshot_api"] = {"cols_per_s": cols / (time.perf_counter() - t0)}
+        # the plain GPU build: per map the pattern, the plan (host
+        # synchronisation, default variant order) and the build, one launch
+        # after the other with no graph, in FP64 and in FP32 + refinement
+        for prec in ("f64", "f32"):
+            log(f"timing: plain per-map build ({prec})")
+            for rep in range(2):       # the first pass warms the allocator
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for k, A in enumerate(dAk):
+                    cp, ri = ctx.pattern(A, 2)
+                    pl = ctx.plan(A, dA0, cp, ri)
+                    pl.build(A.val, dA0.val, prec)
+                    pl.close()
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t0
+            variants[f"{prec}_level2_plain_per_map"] = {"cols_per_s": cols / dt, "ms_per_step": dt * 1e3}
+        f64_plain = variants["f64_level2_plain_per_map"]["cols_per_s"]
+        variants["ratios"] = {
+            "f32_replanned_graph_vs_f64_plain_per_map": value / f64_plain,
+            "f32_vs_f64_replanned_graph_same_batching": value / variants["f64_level2_replanned"]["cols_per_s"],
+            "f32_vs_f64_numeric_build_same_batching": variants["f64_level2_numeric_build_us"] / (build_ms * 1e3),
+            "f32_vs_f64_static_same_batching": variants["f32_level2_static"]["cols_per_s"] /
+            variants["f64_level2_static"]["cols_per_s"],
+        }
         # adaptive patterns on the first source: level 1 plus, per column, the
         # k level-2 candidates with the most negative dL/dw (weights 0.1)
         from paper_2406_17656_amd.adaptive import adaptive_map
@@ -414,23 +429,39 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         import oracle as O
-        log("cpu baseline: oracle on the same sequence")
+
+        def oracle_rate(seconds):
+            t0 = time.perf_counter()
+            done = 0
+            while time.perf_counter() - t0 < seconds:
+                for A in Ash:
+                    S = O.pattern(A, 2, **spec)
+                    O.sam_build(A, A0h, S)
+                    done += n
+                    if time.perf_counter() - t0 > seconds:
+                        break
+            tc = time.perf_counter() - t0
+            return done / tc, done // n, tc
+
         nthreads = O.num_threads()
-        t0 = time.perf_counter()
-        done = 0
-        while True:
-            for A in Ash:
-                S = O.pattern(A, 2, **spec)
-                O.sam_build(A, A0h, S)
-                done += n
-                if time.perf_counter() - t0 > 10.0:
-                    break
-            if time.perf_counter() - t0 > 10.0:   # a bounded sample of about 10-15 s
-                break
-        tc = time.perf_counter() - t0
-        cpu = {"value": done / tc, "unit": "columns/s", "cores": nthreads, "kind": "oracle",
-               "sample": f"{done // n} maps of the same sequence ({nmaps} sources, cycled): pattern + FP64 "
-                         f"Householder build of every column, {tc:.1f} s"}
+        log(f"cpu baseline: oracle on the same sequence, {nthreads} threads")
+        v_all, maps_all, t_all = oracle_rate(10.0)
+        log("cpu baseline: oracle, 1 thread")
+        O.set_num_threads(1)
+        v_one, maps_one, t_one = oracle_rate(8.0)
+        O.set_num_threads(nthreads)
+        model = ""
+        try:
+            with open("/proc/cpuinfo") as f:
+                model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
+        except OSError:
+            pass
+        cpu = {"value": v_all, "unit": "columns/s", "cores": nthreads, "kind": "oracle",
+               "sample": f"{maps_all} maps of the same sequence ({nmaps} sources, cycled): pattern + FP64 "
+                         f"Householder build of every column, {t_all:.1f} s",
+               "value_1thread": v_one,
+               "sample_1thread": f"{maps_one} maps, {t_one:.1f} s, 1 thread",
+               "host": {"nproc": os.cpu_count(), "affinity": len(os.sched_getaffinity(0)), "cpu_model": model}}
 
     out = {
         "metric": "SAM columns/sec (whole path per map: level-2 pattern, plan, FP32+FP64-refine build, residual)",

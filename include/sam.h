@@ -33,9 +33,26 @@
  *   column block, a non-finite value, an out-of-range index read from caller
  *   data) are recorded in a per-context device status word and reported by
  *   sam_sync_status().  Argument errors are returned immediately.
- * - The library allocates device memory only inside a context (workspace) and
- *   inside plan / sequence objects, always before any work is enqueued; the
- *   calls that run kernels on an existing plan or sequence allocate nothing.
+ * - Device memory is the caller's.  The library allocates none itself except
+ *   the 256-byte status block of a context (sam_create).  Every other device
+ *   buffer a call needs is passed in: pattern workspaces, plan and sequence
+ *   memory, and the scratch of the residual, the row views, the top-k
+ *   selection, the penalty scale and the adjoint.  Each is sized by the
+ *   matching *_size / *_workspace_size query and must be 256-byte aligned
+ *   (any torch allocation is).  The library never frees caller memory.
+ *   Memory given to a plan or sequence belongs to it until it is destroyed.
+ *   A workspace is free again once the stream has passed the call's kernels.
+ * - Concurrency: calls on one context may run on several streams at once if
+ *   each uses its own workspace, plan and sequence.  Only the status word is
+ *   shared; failures merge into it with an atomic minimum.  Calls that share
+ *   a plan must not overlap in time (see sam_build_planned).  The synchronising
+ *   calls use the context's status block and its last-error text, so at most
+ *   one host thread may call into a context at a time.
+ * - Caller structures are checked on the device before any other kernel reads
+ *   their indices, in the calls that first receive them: sam_pattern_count,
+ *   sam_plan_size / sam_plan_create (A_k, A_0 and S), sam_sequence_size /
+ *   sam_sequence_create and sam_apply_prepare.  A bad structure returns
+ *   SAM_ERR_UNSORTED with the first bad column in the message.
  * - No call throws; every call returns a sam_status.  sam_last_error() gives a
  *   human-readable message for the last failing call on a context.
  */
@@ -115,13 +132,17 @@ typedef struct sam_seq sam_seq;
 
 /* ---------------------------------------------------------------- context */
 
-/* Create a context bound to HIP device `device`.  device = SAM_NO_DEVICE
- * gives a host-only context on which every call validates its arguments and
- * then returns SAM_ERR_UNSUPPORTED instead of touching a GPU.
- * Errors: SAM_ERR_ARG (ctx NULL), SAM_ERR_HIP (device not usable). */
+/* Create a context bound to HIP device `device`: allocates its 256-byte
+ * device status block (the status word of the kernels' failures and the flags
+ * of the structure checks).  device = SAM_NO_DEVICE gives a host-only
+ * context on which every call validates its arguments and then returns
+ * SAM_ERR_UNSUPPORTED instead of touching a GPU.
+ * Errors: SAM_ERR_ARG (ctx NULL), SAM_ERR_HIP (device not usable),
+ * SAM_ERR_NOMEM. */
 sam_status sam_create(sam_ctx** ctx, int device);
 
-/* Release the context, its workspace and status word.  ctx may be NULL. */
+/* Release the context and its status block (synchronises the device first).
+ * ctx may be NULL. */
 sam_status sam_destroy(sam_ctx* ctx);
 
 /* Message of the last failing call on ctx (static storage owned by ctx;
@@ -148,40 +169,67 @@ sam_status sam_check_csc(sam_ctx* ctx, const sam_csc* A, sam_stream_t stream);
 
 /* ---------------------------------------------------------------- pattern */
 
+/* Bytes of the workspace sam_pattern_count / sam_pattern_fill need for this
+ * A_k structure and spec->power (host output).  B = S(A~_k) needs
+ * nnz(A_k) + n entries.  An intermediate level of power q (p >= 3) needs at
+ * most n min(n, (1 + longest column)^q) entries.  Synchronising: reads
+ * colptr to the host and checks it.  Errors: as sam_pattern_count, and
+ * SAM_ERR_UNSORTED for a bad colptr. */
+sam_status sam_pattern_workspace_size(sam_ctx* ctx, const sam_csc* Ak, const sam_pattern_spec* spec,
+                                      size_t* bytes, sam_stream_t stream);
+
 /* Sections 3-4: S = S((I + B)^p), B = S(A~_k) plus the diagonal, with A~_k
  * given by spec->kind.  Column j of S is the set of vertices with a path of
- * length <= p to j in G(B), rows ascending.  Computes the pattern into the
- * context and returns nnz(S) in *nnz_S (host).  Synchronising (the count is
- * needed on the host to size S).  A_k values are read only for the
- * value-dependent rules.  Errors: SAM_ERR_ARG (power < 1, tau outside [0,1],
- * lfil < 1, bad kind), SAM_ERR_OVERFLOW (nnz(S) >= 2^31). */
-sam_status sam_pattern_count(sam_ctx* ctx, const sam_csc* Ak, const sam_pattern_spec* spec,
-                             int64_t* nnz_S, sam_stream_t stream);
+ * length <= p to j in G(B), rows ascending.  First checks A_k's structure.
+ * Then counts the pattern in the workspace `ws` (ws_bytes >=
+ * sam_pattern_workspace_size): B and the intermediate levels are stored
+ * there, the last level is counted.  Returns nnz(S) in *nnz_S (host).
+ * Synchronising (the count sizes S on the host).  A_k values are read only
+ * for the value-dependent rules.  Errors: SAM_ERR_ARG (power < 1, tau
+ * outside [0,1], lfil < 1, bad kind, workspace too small or unaligned),
+ * SAM_ERR_UNSORTED (bad structure), SAM_ERR_OVERFLOW (nnz(S) >= 2^31). */
+sam_status sam_pattern_count(sam_ctx* ctx, const sam_csc* Ak, const sam_pattern_spec* spec, void* ws,
+                             size_t ws_bytes, int64_t* nnz_S, sam_stream_t stream);
 
-/* Copy the pattern of the last sam_pattern_count on ctx into caller arrays
- * S_colptr (n+1) and S_rowind (nnz_S).  Ak and spec must be the ones passed
- * to that count (same pointers and values), else SAM_ERR_ARG. */
-sam_status sam_pattern_fill(sam_ctx* ctx, const sam_csc* Ak, const sam_pattern_spec* spec,
-                            int32_t* S_colptr, int32_t* S_rowind, sam_stream_t stream);
+/* Write the pattern counted by the last sam_pattern_count on ctx into caller
+ * arrays S_colptr (n+1) and S_rowind (nnz_S).  Ak, spec and ws must be the
+ * ones passed to that count, with ws unchanged since; otherwise SAM_ERR_ARG.
+ * Asynchronous. */
+sam_status sam_pattern_fill(sam_ctx* ctx, const sam_csc* Ak, const sam_pattern_spec* spec, void* ws,
+                            size_t ws_bytes, int32_t* S_colptr, int32_t* S_rowind, sam_stream_t stream);
 
 /* ------------------------------------------------------------------ build */
+
+/* Bytes of plan memory for sam_plan_create on these structures (host
+ * output).  The size depends on the gathered entries
+ * E = sum_j sum_{l in J_j} nnz(A_k(:,l)), one position byte each, which a
+ * kernel counts.  Checks A_k and S first.  Synchronising.  Errors as
+ * sam_plan_create. */
+sam_status sam_plan_size(sam_ctx* ctx, const sam_csc* Ak, const sam_csc* A0,
+                         const int32_t* S_colptr, const int32_t* S_rowind, int64_t nnz_S, size_t* bytes,
+                         sam_stream_t stream);
 
 /* Symbolic analysis of the column problems for the structure of A_k (values
  * ignored), the structure of A_0 (values ignored) and the pattern S:
  * row sets I_j = rows(A_k(:,J_j)) (Section 2: the submatrix of A_k selected
  * by S; rows outside I_j are zero), the position of every A_k and A_0 entry
  * inside its column block, and the size classes (buckets) the numeric kernels
- * run in.  The plan keeps pointers to the caller's structure arrays, which
- * must stay valid and unchanged while the plan is used.  Synchronising.
- * Errors: SAM_ERR_SHAPE (n mismatch, S size), SAM_ERR_UNSUPPORTED (a column
- * block larger than the largest kernel class: |I_j| > 128 or |J_j| > 32),
- * SAM_ERR_OVERFLOW, SAM_ERR_NOMEM. */
+ * run in.  The three structures are checked on the device first.  The plan's
+ * arrays are carved from the caller's `mem` (mem_bytes >= sam_plan_size),
+ * which the plan owns until sam_plan_destroy.  The plan also keeps pointers
+ * to the caller's structure arrays, which must stay valid and unchanged while
+ * the plan is used.  Synchronising.
+ * Errors: SAM_ERR_SHAPE (n mismatch, S size), SAM_ERR_UNSORTED (a bad
+ * structure), SAM_ERR_UNSUPPORTED (a column block larger than the largest
+ * kernel class: |I_j| > 128 or |J_j| > 32), SAM_ERR_OVERFLOW, SAM_ERR_ARG
+ * (memory too small or unaligned). */
 sam_status sam_plan_create(sam_ctx* ctx, const sam_csc* Ak, const sam_csc* A0,
                            const int32_t* S_colptr, const int32_t* S_rowind, int64_t nnz_S,
-                           sam_plan** plan, sam_stream_t stream);
+                           void* mem, size_t mem_bytes, sam_plan** plan, sam_stream_t stream);
 
 /* Release a plan (NULL allowed).  Synchronises the device first, so work
- * still enqueued on the plan finishes before its memory is freed. */
+ * still enqueued on the plan finishes; its memory then returns to the
+ * caller. */
 sam_status sam_plan_destroy(sam_plan* plan);
 
 /* Shape statistics of a plan (host outputs, any may be NULL): number of
@@ -227,43 +275,65 @@ sam_status sam_plan_select(sam_plan* plan, sam_precision prec, const int32_t* or
  * NULL).  res2 (optional device scalar) receives sum_j rho_j =
  * ||A_k M - A_0||_F^2, summed in a fixed order (bitwise reproducible).
  * Ak_val and A0_val are the values matching the plan's structures.
- * Allocates nothing; safe to capture in a HIP graph.  Calls on one plan
- * (builds and sam_backward) must not overlap in time: they share the plan's
- * scratch (column residuals when col_res2 is NULL, the residual sum's
- * partials).
+ * Uses only the plan's memory; safe to capture in a HIP graph.  Calls on
+ * one plan (builds and sam_backward) must not overlap in time: they share
+ * the plan's scratch (column residuals when col_res2 is NULL, the residual
+ * sum's partials).
  * Async errors (sam_sync_status): SAM_ERR_RANK, SAM_ERR_NONFINITE. */
 sam_status sam_build_planned(sam_plan* plan, const double* Ak_val, const double* A0_val,
                              sam_precision prec, void* M_val, double* col_res2, double* res2,
                              sam_stream_t stream);
 
-/* One-shot build: sam_plan_create + sam_build_planned + sam_plan_destroy.
- * Synchronising (the plan is symbolic work with host-side sizing). */
+/* Bytes of the workspace sam_build needs (host output): the plan of the
+ * column problems (sam_plan_size; the same for both precisions).
+ * Synchronising. */
+sam_status sam_workspace_size(sam_ctx* ctx, const sam_csc* Ak, const sam_csc* A0,
+                              const int32_t* S_colptr, const int32_t* S_rowind, int64_t nnz_S,
+                              sam_precision prec, size_t* bytes, sam_stream_t stream);
+
+/* One-shot build (Section 2): sam_plan_create in `ws` (ws_bytes >=
+ * sam_workspace_size), then sam_build_planned.  The planning is synchronising
+ * (host-side sizing); the numeric launches are left on the stream and read
+ * ws until it reaches them.  Outputs and errors as sam_plan_create and
+ * sam_build_planned. */
 sam_status sam_build(sam_ctx* ctx, const sam_csc* Ak, const sam_csc* A0,
                      const int32_t* S_colptr, const int32_t* S_rowind, int64_t nnz_S,
                      sam_precision prec, void* M_val, double* col_res2, double* res2,
-                     sam_stream_t stream);
+                     void* ws, size_t ws_bytes, sam_stream_t stream);
 
 /* --------------------------------------------------------------- residual */
+
+/* Bytes of the workspace of sam_residual for order n and nnz(A_0) (host
+ * output; n doubles of column residuals and a reduction temporary). */
+sam_status sam_residual_workspace_size(int32_t n, int32_t nnz_A0, size_t* bytes);
 
 /* Section 2 eq. (res): res2 = ||A_k M - A_0||_F^2 recomputed explicitly from
  * the stored map M (pattern M_colptr/M_rowind, values M_val in double for
  * SAM_PREC_F64 or float for SAM_PREC_F32_REFINE), independently of the
  * build's per-column residuals; a02 (optional) = ||A_0||_F^2, so that the
  * relative residual of Section 5 is sqrt(res2 / a02).  Both are device
- * scalars, summed in a fixed order.  Allocates nothing. */
+ * scalars, summed in a fixed order.  ws: sam_residual_workspace_size bytes.
+ * Asynchronous.  A_k and A_0 are taken as valid (sam_check_csc); a row of M
+ * outside [0, n) is reported through the status word. */
 sam_status sam_residual(sam_ctx* ctx, const sam_csc* Ak, const sam_csc* A0,
                         const int32_t* M_colptr, const int32_t* M_rowind, int64_t nnz_M,
                         const void* M_val, sam_precision prec, double* res2, double* a02,
-                        sam_stream_t stream);
+                        void* ws, size_t ws_bytes, sam_stream_t stream);
 
 /* ------------------------------------------------------------------ apply */
 
+/* Bytes of the workspace of sam_apply_prepare for order n (host output). */
+sam_status sam_apply_workspace_size(int32_t n, size_t* bytes);
+
 /* Row view of a CSC pattern for y = M x: T_rowptr (n+1), T_colind (nnz) and
  * T_perm (nnz) such that row i of M is {(T_colind[e], M_val[T_perm[e]])} for
- * e in [T_rowptr[i], T_rowptr[i+1]), columns ascending.  Synchronising. */
+ * e in [T_rowptr[i], T_rowptr[i+1]), columns ascending.  Checks the pattern
+ * first (synchronising); the view is built asynchronously in the caller's
+ * arrays with ws (sam_apply_workspace_size bytes) as scratch. */
 sam_status sam_apply_prepare(sam_ctx* ctx, int32_t n, const int32_t* M_colptr,
                              const int32_t* M_rowind, int64_t nnz, int32_t* T_rowptr,
-                             int32_t* T_colind, int32_t* T_perm, sam_stream_t stream);
+                             int32_t* T_colind, int32_t* T_perm, void* ws, size_t ws_bytes,
+                             sam_stream_t stream);
 
 /* y = M x (the map applied inside a Krylov iteration), FP64 accumulation in
  * ascending column order per row (bitwise reproducible).  M_val is double or
@@ -274,20 +344,33 @@ sam_status sam_apply(sam_ctx* ctx, int32_t n, const int32_t* T_rowptr, const int
 
 /* --------------------------------------------------------------- sequence */
 
+/* Bytes of sequence memory for sam_sequence_create with the same arguments
+ * (host output).  ws is a pattern workspace for Ak_struct and spec
+ * (sam_pattern_workspace_size).  In it the structural pattern
+ * S((I + S(A_k))^p) is counted, the bound of every source's pattern.  Checks
+ * both structures.  Synchronising.  Errors as sam_sequence_create. */
+sam_status sam_sequence_size(sam_ctx* ctx, const sam_csc* A0, const sam_csc* Ak_struct,
+                             const sam_pattern_spec* spec, int32_t n_src, sam_precision prec,
+                             int32_t replan_each_run, void* ws, size_t ws_bytes, size_t* bytes,
+                             sam_stream_t stream);
+
 /* A sequence A_1..A_N mapped to the target A_0 (Section 2: every source is
  * mapped back to A_0).  All sources share the structure of `Ak_struct`
  * (values ignored); their values are passed per run.  The pattern follows
  * `spec` per source: when the rule does not depend on values
  * (SAM_SPARSIFY_NONE) the pattern and plan are computed once here, unless
  * `replan_each_run` is nonzero; value-dependent rules are recomputed for every
- * source inside each run, sized to the unsparsified bound.  The first run
- * with a given set of pointers is captured into a HIP graph; later runs with
- * the same pointers replay it.  M_vals[k] must hold nnz_bound entries
- * (sam_sequence_info).  Errors: SAM_ERR_ARG also for n = 0 (nothing to
- * map).  Synchronising (create). */
+ * source inside each run, sized to the unsparsified bound.  Everything lives
+ * in the caller's `mem` (mem_bytes >= sam_sequence_size), owned by the
+ * sequence until sam_sequence_destroy.  The first run with a given set of
+ * pointers is captured into a HIP graph; later runs with the same pointers
+ * replay it.  M_vals[k] must hold nnz_bound entries (sam_sequence_info).
+ * Errors: SAM_ERR_ARG also for n = 0 (nothing to map) and for memory too
+ * small; SAM_ERR_UNSORTED (a bad structure).  Synchronising. */
 sam_status sam_sequence_create(sam_ctx* ctx, const sam_csc* A0, const sam_csc* Ak_struct,
                                const sam_pattern_spec* spec, int32_t n_src, sam_precision prec,
-                               int32_t replan_each_run, sam_seq** seq, sam_stream_t stream);
+                               int32_t replan_each_run, void* mem, size_t mem_bytes, sam_seq** seq,
+                               sam_stream_t stream);
 
 sam_status sam_sequence_destroy(sam_seq* seq);
 
@@ -324,6 +407,15 @@ sam_status sam_build_weighted(sam_plan* plan, const double* Ak_val, const double
                               const double* w, double mu, sam_precision prec, void* M_val,
                               double* col_res2, double* res2, sam_stream_t stream);
 
+/* Bytes of the workspace of sam_backward on this plan (host output): a
+ * staging double per gathered entry, an offset per S entry, the row view of
+ * S and its temporaries. */
+sam_status sam_backward_workspace_size(const sam_plan* plan, size_t* bytes);
+
+/* Build the row view of S (which columns j contain row l, ascending j) in
+ * ws for sam_backward on this plan.  Asynchronous. */
+sam_status sam_backward_prepare(sam_plan* plan, void* ws, size_t ws_bytes, sam_stream_t stream);
+
 /* Adjoint of L = dL * ||A_k M - A_0||_F^2 for the soft-weighted map M: the
  * QR of each stacked block is recomputed (nothing is stored by the forward
  * pass), lambda = (A^T A + P)^{-1} 2 A^T r with r = A m - b (FP32 mode: two
@@ -335,13 +427,14 @@ sam_status sam_build_weighted(sam_plan* plan, const double* Ak_val, const double
  *   gw   (nnz_S, optional):       dL mu lambda_l m_l / w_l^2,
  *   loss (optional device scalar): ||A_k M - A_0||_F^2 (not scaled by dL).
  * The A_k gradient is summed per entry over the columns in ascending order
- * from a staging buffer (no atomics: bitwise reproducible).  The staging
- * buffer and the row view of S are allocated on the first call on a plan
- * (that call synchronises); later calls allocate nothing. */
+ * from the staging part of ws (no atomics: bitwise reproducible).  ws must
+ * have been prepared for this plan by sam_backward_prepare and not changed
+ * since (else SAM_ERR_ARG); its staging part is rewritten by every call.
+ * Asynchronous; calls on one plan must not overlap in time. */
 sam_status sam_backward(sam_plan* plan, const double* Ak_val, const double* A0_val,
                         const double* w, double mu, double dL, sam_precision prec,
                         double* gAk, double* gA0, double* gw, double* loss,
-                        sam_stream_t stream);
+                        void* ws, size_t ws_bytes, sam_stream_t stream);
 
 /* ------------------------------------------------------ adaptive patterns */
 
@@ -362,21 +455,31 @@ sam_status sam_candidate_weights(sam_ctx* ctx, int32_t n, const int32_t* S_colpt
                                  int64_t nnz_S, const int32_t* B_colptr, const int32_t* B_rowind, int64_t nnz_B,
                                  double w_base, double w_cand, double* w, sam_stream_t stream);
 
+/* Bytes of the workspace of sam_pattern_topk for order n (host output). */
+sam_status sam_topk_workspace_size(int32_t n, size_t* bytes);
+
 /* Top-k selection: column j of the output keeps, in S's (ascending) order,
  * every entry of S(:, j) with w >= 1 and the k entries with w < 1 that have
  * the smallest grad (NaN counts as +inf; ties go to the smaller row).  grad
  * is typically sam_backward's gw (negative: admitting the entry lowers the
  * loss).  out_colptr (n+1) and out_rowind (at most nnz_S entries) are device
- * arrays of the caller; *nnz_out (host) receives the output size.  Errors as
- * for sam_candidate_weights, and SAM_ERR_ARG for k < 0.  Synchronising. */
+ * arrays of the caller; *nnz_out (host) receives the output size.  ws:
+ * sam_topk_workspace_size bytes.  Errors as for sam_candidate_weights, and
+ * SAM_ERR_ARG for k < 0.  Synchronising. */
 sam_status sam_pattern_topk(sam_ctx* ctx, int32_t n, const int32_t* S_colptr, const int32_t* S_rowind,
                             int64_t nnz_S, const double* w, const double* grad, int32_t k, int32_t* out_colptr,
-                            int32_t* out_rowind, int64_t* nnz_out, sam_stream_t stream);
+                            int32_t* out_rowind, int64_t* nnz_out, void* ws, size_t ws_bytes,
+                            sam_stream_t stream);
+
+/* Bytes of the workspace of sam_penalty_scale for nnz(A_k) (host output). */
+sam_status sam_penalty_workspace_size(int32_t nnz, size_t* bytes);
 
 /* The penalty scale of the soft weights: *mu (host) = ||A_k||_F^2 / n, the
- * mean squared column norm (a fixed scalar, not differentiated).  Errors:
- * SAM_ERR_ARG (NULL, n = 0, no values).  Synchronising. */
-sam_status sam_penalty_scale(sam_ctx* ctx, const sam_csc* Ak, double* mu, sam_stream_t stream);
+ * mean squared column norm (a fixed scalar, not differentiated).  ws:
+ * sam_penalty_workspace_size bytes.  Errors: SAM_ERR_ARG (NULL, n = 0, no
+ * values).  Synchronising. */
+sam_status sam_penalty_scale(sam_ctx* ctx, const sam_csc* Ak, double* mu, void* ws, size_t ws_bytes,
+                             sam_stream_t stream);
 
 #ifdef __cplusplus
 }

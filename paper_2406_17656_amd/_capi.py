@@ -46,6 +46,9 @@ CSCP = ctypes.POINTER(sam_csc)
 SPECP = ctypes.POINTER(sam_pattern_spec)
 
 # name -> (restype, argtypes)
+SZ = ctypes.POINTER(ctypes.c_size_t)
+c_size_t = ctypes.c_size_t
+
 SIGNATURES = {
     "sam_create": (c_int32, [ctypes.POINTER(c_void_p), c_int32]),
     "sam_destroy": (c_int32, [P]),
@@ -54,9 +57,11 @@ SIGNATURES = {
     "sam_version": (c_char_p, []),
     "sam_sync_status": (c_int32, [P, P, ctypes.POINTER(c_int32)]),
     "sam_check_csc": (c_int32, [P, CSCP, P]),
-    "sam_pattern_count": (c_int32, [P, CSCP, SPECP, ctypes.POINTER(c_int64), P]),
-    "sam_pattern_fill": (c_int32, [P, CSCP, SPECP, P, P, P]),
-    "sam_plan_create": (c_int32, [P, CSCP, CSCP, P, P, c_int64, ctypes.POINTER(c_void_p), P]),
+    "sam_pattern_workspace_size": (c_int32, [P, CSCP, SPECP, SZ, P]),
+    "sam_pattern_count": (c_int32, [P, CSCP, SPECP, P, c_size_t, ctypes.POINTER(c_int64), P]),
+    "sam_pattern_fill": (c_int32, [P, CSCP, SPECP, P, c_size_t, P, P, P]),
+    "sam_plan_size": (c_int32, [P, CSCP, CSCP, P, P, c_int64, SZ, P]),
+    "sam_plan_create": (c_int32, [P, CSCP, CSCP, P, P, c_int64, P, c_size_t, ctypes.POINTER(c_void_p), P]),
     "sam_plan_destroy": (c_int32, [P]),
     "sam_plan_info": (c_int32, [P, ctypes.POINTER(c_int32), ctypes.POINTER(c_int32),
                                 ctypes.POINTER(c_int32), ctypes.POINTER(c_int64),
@@ -67,21 +72,30 @@ SIGNATURES = {
     "sam_plan_select": (c_int32, [P, c_int32, P, c_int32, P]),
     "sam_sequence_select": (c_int32, [P, P, c_int32, P]),
     "sam_build_planned": (c_int32, [P, P, P, c_int32, P, P, P, P]),
-    "sam_build": (c_int32, [P, CSCP, CSCP, P, P, c_int64, c_int32, P, P, P, P]),
-    "sam_residual": (c_int32, [P, CSCP, CSCP, P, P, c_int64, P, c_int32, P, P, P]),
-    "sam_apply_prepare": (c_int32, [P, c_int32, P, P, c_int64, P, P, P, P]),
+    "sam_workspace_size": (c_int32, [P, CSCP, CSCP, P, P, c_int64, c_int32, SZ, P]),
+    "sam_build": (c_int32, [P, CSCP, CSCP, P, P, c_int64, c_int32, P, P, P, P, c_size_t, P]),
+    "sam_residual_workspace_size": (c_int32, [c_int32, c_int32, SZ]),
+    "sam_residual": (c_int32, [P, CSCP, CSCP, P, P, c_int64, P, c_int32, P, P, P, c_size_t, P]),
+    "sam_apply_workspace_size": (c_int32, [c_int32, SZ]),
+    "sam_apply_prepare": (c_int32, [P, c_int32, P, P, c_int64, P, P, P, P, c_size_t, P]),
     "sam_apply": (c_int32, [P, c_int32, P, P, P, P, c_int32, P, P, P]),
-    "sam_sequence_create": (c_int32, [P, CSCP, CSCP, SPECP, c_int32, c_int32, c_int32,
+    "sam_sequence_size": (c_int32, [P, CSCP, CSCP, SPECP, c_int32, c_int32, c_int32, P, c_size_t, SZ, P]),
+    "sam_sequence_create": (c_int32, [P, CSCP, CSCP, SPECP, c_int32, c_int32, c_int32, P, c_size_t,
                                       ctypes.POINTER(c_void_p), P]),
     "sam_sequence_destroy": (c_int32, [P]),
     "sam_sequence_info": (c_int32, [P, ctypes.POINTER(c_int64)]),
     "sam_sequence_pattern": (c_int32, [P, c_int32, P, P, ctypes.POINTER(c_int64), P]),
     "sam_sequence_run": (c_int32, [P, P, P, P, P]),
     "sam_build_weighted": (c_int32, [P, P, P, P, c_double, c_int32, P, P, P, P]),
-    "sam_backward": (c_int32, [P, P, P, P, c_double, c_double, c_int32, P, P, P, P, P]),
+    "sam_backward_workspace_size": (c_int32, [P, SZ]),
+    "sam_backward_prepare": (c_int32, [P, P, c_size_t, P]),
+    "sam_backward": (c_int32, [P, P, P, P, c_double, c_double, c_int32, P, P, P, P, P, c_size_t, P]),
     "sam_candidate_weights": (c_int32, [P, c_int32, P, P, c_int64, P, P, c_int64, c_double, c_double, P, P]),
-    "sam_pattern_topk": (c_int32, [P, c_int32, P, P, c_int64, P, P, c_int32, P, P, ctypes.POINTER(c_int64), P]),
-    "sam_penalty_scale": (c_int32, [P, CSCP, ctypes.POINTER(c_double), P]),
+    "sam_topk_workspace_size": (c_int32, [c_int32, SZ]),
+    "sam_pattern_topk": (c_int32, [P, c_int32, P, P, c_int64, P, P, c_int32, P, P, ctypes.POINTER(c_int64),
+                                   P, c_size_t, P]),
+    "sam_penalty_workspace_size": (c_int32, [c_int32, SZ]),
+    "sam_penalty_scale": (c_int32, [P, CSCP, ctypes.POINTER(c_double), P, c_size_t, P]),
 }
 
 

@@ -227,6 +227,17 @@ hipError_t identity_queue(int n, int* queue, int* bstart, hipStream_t s) {
     return hipGetLastError();
 }
 
+__global__ void k_fill_i32(int* p, int64_t count, int v) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) p[i] = v;
+}
+
+hipError_t fill_i32(int* p, int64_t count, int v, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, p, count, v);
+    return hipGetLastError();
+}
+
 hipError_t transpose_count(int n, const int* cp, const int* ri, int64_t nnz, int* rowcount,
                            hipStream_t s) {
     (void)cp;

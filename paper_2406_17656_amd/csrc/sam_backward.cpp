@@ -1,6 +1,7 @@
 // sam_backward.cpp -- host side of the soft-weighted map's adjoint: the
-// staging buffers (allocated on the first call), the backward launches per
-// bucket, and the deterministic A_k-value accumulation.
+// caller's workspace (staging of the per-column contributions and the row
+// view of S), the backward launches per bucket, and the deterministic A_k
+// value accumulation.
 #include "sam_host.hpp"
 
 #include <climits>
@@ -10,60 +11,69 @@ using namespace samh;
 namespace {
 
 struct BwdBufs {
-    double* contrib;
-    int64_t* segoff;
-    int* ST_rowptr;
-    int* ST_colind;
+    double* contrib;      // one per gathered entry, at the plan's eoff[j]
+    int64_t* segoff;      // per S entry: where its column's contributions start
+    int* ST_rowptr;       // row view of S: which columns j contain row l,
+    int* ST_colind;       // ascending j
     int* ST_perm;
+    int* rowcount;        // temporaries of the row view
+    int* cursor;
+    int64_t* off;
+    void* stemp;
 };
 
-BwdBufs bwd_views(sam_plan* pl) {
-    Carve cv(pl->bwd.p);
-    BwdBufs b;
-    b.contrib = cv.take<double>((size_t)std::max<int64_t>(pl->E, 1));
-    b.segoff = cv.take<int64_t>((size_t)std::max<int64_t>(pl->nnzS, 1));
-    b.ST_rowptr = cv.take<int>((size_t)pl->n + 1);
-    b.ST_colind = cv.take<int>((size_t)std::max<int64_t>(pl->nnzS, 1));
-    b.ST_perm = cv.take<int>((size_t)std::max<int64_t>(pl->nnzS, 1));
-    return b;
-}
-
-// Staging for the contributions and the row view of S (which columns j
-// contain row l, ascending j), built once per plan.
-sam_status ensure_backward(sam_plan* pl, hipStream_t s) {
-    sam_ctx* ctx = pl->ctx;
-    if (pl->bwd.p) return SAM_OK;
-    const int n = pl->n;
-    const size_t nS = (size_t)std::max<int64_t>(pl->nnzS, 1);
-    const size_t need = align256((size_t)std::max<int64_t>(pl->E, 1) * 8) + align256(nS * 8) +
-                        align256(((size_t)n + 1) * 4) + 2 * align256(nS * 4) + 1024;
-    HIP_TRY(ctx, grow(pl->bwd, need));
-    BwdBufs b = bwd_views(pl);
-    const size_t tneed = 2 * align256((size_t)std::max(n, 1) * 4) + align256(((size_t)n + 1) * 8) +
-                         align256(samk::scan_temp_bytes(n)) + 512;
-    HIP_TRY(ctx, grow(ctx->ws, tneed));
-    Carve tw(ctx->ws.p);
-    int* rowcount = tw.take<int>(std::max(n, 1));
-    int* cursor = tw.take<int>(std::max(n, 1));
-    int64_t* off = tw.take<int64_t>((size_t)n + 1);
-    void* stemp = tw.take<char>(samk::scan_temp_bytes(n));
-    HIP_TRY(ctx, hipMemsetAsync(rowcount, 0, (size_t)std::max(n, 1) * 4, s));
-    HIP_TRY(ctx, hipMemsetAsync(cursor, 0, (size_t)std::max(n, 1) * 4, s));
-    HIP_TRY(ctx, samk::transpose_count(n, pl->S_cp, pl->S_ri, pl->nnzS, rowcount, s));
-    HIP_TRY(ctx, samk::scan_counts(rowcount, n, off, b.ST_rowptr, nullptr, stemp, s));
-    HIP_TRY(ctx, samk::transpose_fill(n, pl->S_cp, pl->S_ri, b.ST_rowptr, cursor, b.ST_colind, b.ST_perm, s));
-    HIP_TRY(ctx, samk::transpose_sort_rows(n, b.ST_rowptr, b.ST_colind, b.ST_perm, s));
-    HIP_TRY(ctx, hipStreamSynchronize(s));
-    return SAM_OK;
+size_t bwd_layout(Carve& cv, int n, int64_t E, int64_t nnzS, BwdBufs* b) {
+    BwdBufs x;
+    x.contrib = cv.take<double>((size_t)E);
+    x.segoff = cv.take<int64_t>((size_t)nnzS);
+    x.ST_rowptr = cv.take<int>((size_t)n + 1);
+    x.ST_colind = cv.take<int>((size_t)nnzS);
+    x.ST_perm = cv.take<int>((size_t)nnzS);
+    x.rowcount = cv.take<int>((size_t)std::max(n, 1));
+    x.cursor = cv.take<int>((size_t)std::max(n, 1));
+    x.off = cv.take<int64_t>((size_t)n + 1);
+    x.stemp = cv.take<char>(samk::scan_temp_bytes(n));
+    if (b) *b = x;
+    return cv.off;
 }
 
 }  // namespace
 
 extern "C" {
 
+sam_status sam_backward_workspace_size(const sam_plan* plan, size_t* bytes) {
+    if (!plan || !bytes) return SAM_ERR_ARG;
+    Carve cv(nullptr);
+    *bytes = bwd_layout(cv, plan->n, plan->E, plan->nnzS, nullptr);
+    return SAM_OK;
+}
+
+sam_status sam_backward_prepare(sam_plan* plan, void* ws, size_t ws_bytes, sam_stream_t stream) {
+    if (!plan || !plan->ctx) return SAM_ERR_ARG;
+    sam_ctx* ctx = plan->ctx;
+    check_ctx(ctx);
+    Carve cv(ws);
+    BwdBufs b;
+    sam_status st;
+    if ((st = check_ws(ctx, ws, ws_bytes, bwd_layout(cv, plan->n, plan->E, plan->nnzS, &b), "backward workspace")))
+        return st;
+    if ((st = need_device(ctx))) return st;
+    hipStream_t s = S(stream);
+    const int n = plan->n;
+    plan->bwd_ws = nullptr;
+    HIP_TRY(ctx, samk::fill_i32(b.rowcount, std::max(n, 1), 0, s));
+    HIP_TRY(ctx, samk::fill_i32(b.cursor, std::max(n, 1), 0, s));
+    HIP_TRY(ctx, samk::transpose_count(n, plan->S_cp, plan->S_ri, plan->nnzS, b.rowcount, s));
+    HIP_TRY(ctx, samk::scan_counts(b.rowcount, n, b.off, b.ST_rowptr, nullptr, b.stemp, s));
+    HIP_TRY(ctx, samk::transpose_fill(n, plan->S_cp, plan->S_ri, b.ST_rowptr, b.cursor, b.ST_colind, b.ST_perm, s));
+    HIP_TRY(ctx, samk::transpose_sort_rows(n, b.ST_rowptr, b.ST_colind, b.ST_perm, s));
+    plan->bwd_ws = ws;
+    return SAM_OK;
+}
+
 sam_status sam_backward(sam_plan* plan, const double* Ak_val, const double* A0_val, const double* w, double mu,
-                        double dL, sam_precision prec, double* gAk, double* gA0, double* gw, double* loss,
-                        sam_stream_t stream) {
+                        double dL, sam_precision prec, double* gAk, double* gA0, double* gw, double* loss, void* ws,
+                        size_t ws_bytes, sam_stream_t stream) {
     if (!plan || !plan->ctx) return SAM_ERR_ARG;
     sam_ctx* ctx = plan->ctx;
     check_ctx(ctx);
@@ -72,14 +82,18 @@ sam_status sam_backward(sam_plan* plan, const double* Ak_val, const double* A0_v
         return fail(ctx, SAM_ERR_ARG, "value or gradient array is NULL");
     if (plan->nnzS > 0 && !w) return fail(ctx, SAM_ERR_ARG, "w is NULL");
     if (!(mu >= 0.0)) return fail(ctx, SAM_ERR_ARG, "mu must be >= 0 (got %g)", mu);
-    sam_status st = need_device(ctx);
-    if (st) return st;
+    Carve cv(ws);
+    BwdBufs b;
+    sam_status st;
+    if ((st = check_ws(ctx, ws, ws_bytes, bwd_layout(cv, plan->n, plan->E, plan->nnzS, &b), "backward workspace")))
+        return st;
+    if (plan->bwd_ws != ws)
+        return fail(ctx, SAM_ERR_ARG, "the backward workspace was not prepared for this plan (sam_backward_prepare)");
+    if ((st = need_device(ctx))) return st;
     hipStream_t s = S(stream);
     const int pi = prec == SAM_PREC_F32_REFINE ? 1 : 0;
     Combo& cb = plan->combo[pi][1];
     if (!cb.ok) return fail(ctx, SAM_ERR_UNSUPPORTED, "%s", cb.why.c_str());
-    if ((st = ensure_backward(plan, s))) return st;
-    BwdBufs b = bwd_views(plan);
 
     samk::NumericArgs a{};
     a.n = plan->n;

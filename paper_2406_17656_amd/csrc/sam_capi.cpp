@@ -1,6 +1,6 @@
 // sam_capi.cpp -- host implementation of the C ABI declared in include/sam.h:
-// argument validation, context / pattern / plan objects, device memory
-// management and the launch sequence of the gfx950 kernels.
+// argument and structure validation, the context, patterns and plans in
+// caller memory, and the launch sequence of the gfx950 kernels.
 #include "sam_host.hpp"
 
 #include <climits>
@@ -15,7 +15,6 @@ using namespace samh;
 
 namespace samh {
 
-
 sam_status fail(sam_ctx* ctx, sam_status st, const char* fmt, ...) {
     if (ctx) {
         char buf[512];
@@ -27,34 +26,6 @@ sam_status fail(sam_ctx* ctx, sam_status st, const char* fmt, ...) {
     }
     return st;
 }
-
-
-
-
-hipError_t grow(DevBuf& b, size_t bytes) {
-    if (b.bytes >= bytes && b.p) return hipSuccess;
-    if (b.p) {
-        hipError_t e = hipFree(b.p);
-        if (e != hipSuccess) return e;
-        b.p = nullptr;
-        b.bytes = 0;
-    }
-    size_t want = std::max<size_t>(align256(bytes), 256);
-    hipError_t e = hipMalloc(&b.p, want);
-    if (e != hipSuccess) {
-        b.p = nullptr;
-        return e;
-    }
-    b.bytes = want;
-    return hipSuccess;
-}
-
-void release(DevBuf& b) {
-    if (b.p) (void)hipFree(b.p);
-    b.p = nullptr;
-    b.bytes = 0;
-}
-
 
 sam_status check_ctx(sam_ctx* ctx) {
     if (!ctx) return SAM_ERR_ARG;
@@ -93,6 +64,14 @@ sam_status check_spec(sam_ctx* ctx, const sam_pattern_spec* spec) {
     return SAM_OK;
 }
 
+sam_status check_ws(sam_ctx* ctx, const void* ws, size_t ws_bytes, size_t need, const char* what) {
+    if (ws_bytes < need)
+        return fail(ctx, SAM_ERR_ARG, "%s: %zu bytes given, %zu needed", what, ws_bytes, need);
+    if (need > 0 && !ws) return fail(ctx, SAM_ERR_ARG, "%s is NULL", what);
+    if (((uintptr_t)ws & 255u) != 0) return fail(ctx, SAM_ERR_ARG, "%s is not 256-byte aligned", what);
+    return SAM_OK;
+}
+
 samk::SparsifySpec to_sp(const sam_pattern_spec* spec) {
     samk::SparsifySpec sp;
     sp.kind = spec->kind;
@@ -103,61 +82,112 @@ samk::SparsifySpec to_sp(const sam_pattern_spec* spec) {
     return sp;
 }
 
+sam_status host_colptr(sam_ctx* ctx, const int32_t* cp, int n, int64_t nnz, const char* name, int* longest,
+                       hipStream_t s, std::vector<int>* keep) {
+    std::vector<int> local;
+    std::vector<int>& h = keep ? *keep : local;
+    h.assign((size_t)n + 1, 0);
+    HIP_TRY(ctx, hipMemcpyAsync(h.data(), cp, h.size() * 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, hipStreamSynchronize(s));
+    if (h[0] != 0 || h[(size_t)n] != nnz)
+        return fail(ctx, SAM_ERR_UNSORTED, "%s: colptr[0] = %d and colptr[n] = %d, expected 0 and %lld", name, h[0],
+                    h[(size_t)n], (long long)nnz);
+    int most = 0;
+    for (int j = 0; j < n; ++j) {
+        const int len = h[(size_t)j + 1] - h[(size_t)j];
+        if (len < 0) return fail(ctx, SAM_ERR_UNSORTED, "%s: colptr decreases at column %d", name, j);
+        most = std::max(most, len);
+    }
+    if (longest) *longest = most;
+    return SAM_OK;
+}
 
+sam_status validate_csc(sam_ctx* ctx, int n, int64_t nnz, const int32_t* cp, const int32_t* ri, const char* name,
+                        hipStream_t s) {
+    if (n == 0) return SAM_OK;
+    int h = n;
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->d_bad, &h, sizeof h, hipMemcpyHostToDevice, s));
+    HIP_TRY(ctx, samk::check_csc(n, (int)nnz, cp, ri, ctx->d_bad, s));
+    HIP_TRY(ctx, hipMemcpyAsync(&h, ctx->d_bad, sizeof h, hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, hipStreamSynchronize(s));
+    if (h != n)
+        return fail(ctx, SAM_ERR_UNSORTED,
+                    "%s: invalid CSC structure at column %d (colptr not monotone or not ending at nnz, or rows "
+                    "outside [0, n), unsorted or repeated)", name, h);
+    return SAM_OK;
+}
 
-// Pattern pipeline: B = sparsify(A_k) (diagonal added), then S = B, and
-// p-1 times S <- expand(S, B).  Produces device arrays into out_cp/out_ri
-// (grown as needed) and the host nnz.
-sam_status compute_pattern(sam_ctx* ctx, const sam_csc* Ak, const sam_pattern_spec* spec, DevBuf& out_cp,
-                           DevBuf& out_ri, int64_t* nnz_out, hipStream_t s, PatternLevels* levels) {
+// ------------------------------------------------------------- patterns
+
+int64_t level_bound(int n, int longest, int power) {
+    const int64_t width = (int64_t)longest + 1;   // B adds the diagonal
+    int64_t per = 1;
+    for (int q = 0; q < power && per < n; ++q) per = std::min<int64_t>((int64_t)n, per * width);
+    per = std::min<int64_t>(per, (int64_t)n);
+    const int64_t b = per * (int64_t)n;
+    return std::min<int64_t>(b, (int64_t)INT_MAX);
+}
+
+void pattern_ws_layout(Carve& cv, int n, int nnzA, int longest, int power, PatternWs* w) {
+    PatternWs t;
+    t.counts = cv.take<int>((size_t)n);
+    t.off = cv.take<int64_t>((size_t)n + 1);
+    t.stemp = cv.take<char>(samk::scan_temp_bytes(n));
+    t.D = cv.take<double>((size_t)n);
+    t.B_cp = cv.take<int>((size_t)n + 1);
+    t.B_ri = cv.take<int>((size_t)nnzA + (size_t)n);
+    t.flags = cv.take<int>(4);
+    const int mids = power >= 3 ? std::min(power - 2, 2) : 0;
+    t.Lcap = power >= 3 ? level_bound(n, longest, power - 1) : 0;
+    for (int i = 0; i < mids; ++i) {
+        t.L_cp[i] = cv.take<int>((size_t)n + 1);
+        t.L_ri[i] = cv.take<int>((size_t)t.Lcap);
+    }
+    t.S_cp = cv.take<int>((size_t)n + 1);
+    if (w) *w = t;
+}
+
+// Pattern pipeline: B = sparsify(A_k) (diagonal added), then p-1 times
+// level <- expand(level, B).  Intermediate levels are stored in the
+// workspace; the last is counted only.
+sam_status compute_pattern(sam_ctx* ctx, const sam_csc* Ak, const sam_pattern_spec* spec, const PatternWs& w,
+                           PatternResult* res, hipStream_t s, PatternLevels* levels) {
     const int n = Ak->n;
+    const int p = spec->power;
     const size_t cp_bytes = (size_t)(n + 1) * 4;
-    DevBuf* levels_cp = levels ? levels->cp : nullptr;
     if (levels) {
         levels->nnz.clear();
         levels->maxcol.clear();
     }
-    if (levels_cp) HIP_TRY(ctx, grow(*levels_cp, cp_bytes * (size_t)std::max(spec->power, 1)));
     auto keep_level = [&](int lev, const int* cp) {
-        return levels_cp ? hipMemcpyAsync((char*)levels_cp->p + cp_bytes * lev, cp, cp_bytes,
-                                          hipMemcpyDeviceToDevice, s)
-                         : hipSuccess;
+        return (levels && levels->cp)
+                   ? hipMemcpyAsync(levels->cp + (size_t)lev * (n + 1), cp, cp_bytes, hipMemcpyDeviceToDevice, s)
+                   : hipSuccess;
     };
+    *res = PatternResult{};
     samk::SparsifySpec sp = to_sp(spec);
-    // workspace: counts (n int), scan out (n+1 int64), scan temp, D (n double),
-    // B_cp (n+1), B_ri (nnz+n), flags (overflow, bad column, longest column)
-    const size_t nnzB_bound = (size_t)Ak->nnz + (size_t)n;
-    size_t need = align256((size_t)n * 4) + align256((size_t)(n + 1) * 8) + align256(samk::scan_temp_bytes(n)) +
-                  align256((size_t)n * 8) + align256((size_t)(n + 1) * 4) + align256(nnzB_bound * 4) + 512;
-    HIP_TRY(ctx, grow(ctx->ws, need));
-    Carve cv(ctx->ws.p);
-    int* counts = cv.take<int>(n);
-    int64_t* off = cv.take<int64_t>(n + 1);
-    void* stemp = cv.take<char>(samk::scan_temp_bytes(n));
-    double* D = cv.take<double>(n);
-    int* B_cp = cv.take<int>(n + 1);
-    int* B_ri = cv.take<int>(nnzB_bound);
-    int* flags = cv.take<int>(3);  // [0] overflow, [1] bad column, [2] longest column of the last level
     const int init[3] = {0, n, 0};
-    HIP_TRY(ctx, hipMemcpyAsync(flags, init, sizeof init, hipMemcpyHostToDevice, s));
+    HIP_TRY(ctx, hipMemcpyAsync(w.flags, init, sizeof init, hipMemcpyHostToDevice, s));
     if (n == 0) {
-        HIP_TRY(ctx, grow(out_cp, sizeof(int)));
-        HIP_TRY(ctx, hipMemsetAsync(out_cp.p, 0, sizeof(int), s));
-        *nnz_out = 0;
+        HIP_TRY(ctx, samk::fill_i32(w.B_cp, 1, 0, s));
+        HIP_TRY(ctx, samk::fill_i32(w.S_cp, 1, 0, s));
+        res->B_cp = w.B_cp;
+        res->B_ri = w.B_ri;
+        res->S_cp = p == 1 ? w.B_cp : w.S_cp;
         HIP_TRY(ctx, hipStreamSynchronize(s));
         return SAM_OK;
     }
-    // total and longest column of the level just counted
+    // total and longest column of the level just scanned
     auto level_facts = [&](int64_t* tot, int* maxc) {
-        hipError_t e = hipMemcpyAsync(tot, off + n, sizeof(int64_t), hipMemcpyDeviceToHost, s);
-        if (e == hipSuccess) e = hipMemcpyAsync(maxc, flags + 2, sizeof(int), hipMemcpyDeviceToHost, s);
+        hipError_t e = hipMemcpyAsync(tot, w.off + n, sizeof(int64_t), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(maxc, w.flags + 2, sizeof(int), hipMemcpyDeviceToHost, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         return e;
     };
-    HIP_TRY(ctx, samk::sparsify_count(n, Ak->colptr, Ak->rowind, Ak->val, sp, D, counts, s));
-    HIP_TRY(ctx, samk::scan_counts(counts, n, off, B_cp, flags, stemp, s, flags + 2));
-    HIP_TRY(ctx, samk::sparsify_fill(n, Ak->colptr, Ak->rowind, Ak->val, sp, D, B_cp, B_ri, s));
-    HIP_TRY(ctx, keep_level(0, B_cp));
+    HIP_TRY(ctx, samk::sparsify_count(n, Ak->colptr, Ak->rowind, Ak->val, sp, w.D, w.counts, s));
+    HIP_TRY(ctx, samk::scan_counts(w.counts, n, w.off, w.B_cp, w.flags, w.stemp, s, w.flags + 2));
+    HIP_TRY(ctx, samk::sparsify_fill(n, Ak->colptr, Ak->rowind, Ak->val, sp, w.D, w.B_cp, w.B_ri, s));
+    HIP_TRY(ctx, keep_level(0, w.B_cp));
     int64_t nnzB = 0;
     int maxB = 0;
     HIP_TRY(ctx, level_facts(&nnzB, &maxB));
@@ -165,58 +195,67 @@ sam_status compute_pattern(sam_ctx* ctx, const sam_csc* Ak, const sam_pattern_sp
         levels->nnz.push_back(nnzB);
         levels->maxcol.push_back(maxB);
     }
-    const int* cur_cp = B_cp;
-    const int* cur_ri = B_ri;
-    int64_t cur_nnz = nnzB;
+    const int* cur_cp = w.B_cp;
+    const int* cur_ri = w.B_ri;
     int cur_max = maxB;
-    DevBuf level_cp, level_ri;  // alternating level buffers
-    DevBuf level_cp2, level_ri2;
-    for (int lev = 1; lev < spec->power; ++lev) {
-        HIP_TRY(ctx, samk::expand_count(n, cur_cp, cur_ri, B_cp, B_ri, counts, flags + 1, cur_max, s));
-        HIP_TRY(ctx, hipMemsetAsync(flags + 2, 0, sizeof(int), s));
-        HIP_TRY(ctx, samk::scan_counts(counts, n, off, nullptr, flags, stemp, s, flags + 2));
+    int64_t last_nnz = nnzB;
+    for (int lev = 1; lev < p; ++lev) {
+        HIP_TRY(ctx, samk::expand_count(n, cur_cp, cur_ri, w.B_cp, w.B_ri, w.counts, w.flags + 1, cur_max, s));
+        HIP_TRY(ctx, samk::fill_i32(w.flags + 2, 1, 0, s));
+        const bool last = lev == p - 1;
+        int* dst_cp = last ? w.S_cp : w.L_cp[(lev - 1) & 1];
+        HIP_TRY(ctx, samk::scan_counts(w.counts, n, w.off, dst_cp, w.flags, w.stemp, s, w.flags + 2));
         int64_t tot = 0;
         int tmax = 0;
         HIP_TRY(ctx, level_facts(&tot, &tmax));
-        if (tot > INT_MAX) {
-            release(level_cp); release(level_ri); release(level_cp2); release(level_ri2);
+        if (tot > INT_MAX)
             return fail(ctx, SAM_ERR_OVERFLOW, "pattern level %d has %lld entries (>= 2^31)", lev + 1, (long long)tot);
-        }
-        DevBuf& ncp = (lev & 1) ? level_cp : level_cp2;
-        DevBuf& nri = (lev & 1) ? level_ri : level_ri2;
-        HIP_TRY(ctx, grow(ncp, (size_t)(n + 1) * 4));
-        HIP_TRY(ctx, grow(nri, (size_t)std::max<int64_t>(tot, 1) * 4));
-        HIP_TRY(ctx, samk::scan_counts(counts, n, off, (int*)ncp.p, flags, stemp, s));
-        HIP_TRY(ctx, samk::expand_fill(n, cur_cp, cur_ri, B_cp, B_ri, (int*)ncp.p, (int*)nri.p, cur_max, maxB, s));
-        HIP_TRY(ctx, keep_level(lev, (const int*)ncp.p));
-        cur_cp = (int*)ncp.p;
-        cur_ri = (int*)nri.p;
-        cur_nnz = tot;
-        cur_max = tmax;
+        HIP_TRY(ctx, keep_level(lev, dst_cp));
         if (levels) {
             levels->nnz.push_back(tot);
             levels->maxcol.push_back(tmax);
         }
+        if (last) {
+            res->last_cp = cur_cp;
+            res->last_ri = cur_ri;
+            res->last_max = cur_max;
+            last_nnz = tot;
+        } else {
+            if (tot > w.Lcap)   // cannot happen: the bound holds for every pattern of this structure
+                return fail(ctx, SAM_ERR_OVERFLOW, "pattern level %d exceeds its workspace bound", lev + 1);
+            int* dst_ri = w.L_ri[(lev - 1) & 1];
+            HIP_TRY(ctx, samk::expand_fill(n, cur_cp, cur_ri, w.B_cp, w.B_ri, dst_cp, dst_ri, cur_max, maxB, s));
+            cur_cp = dst_cp;
+            cur_ri = dst_ri;
+            cur_max = tmax;
+        }
     }
     int hflags[2] = {0, n};
-    HIP_TRY(ctx, hipMemcpyAsync(hflags, flags, sizeof hflags, hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, hipMemcpyAsync(hflags, w.flags, sizeof hflags, hipMemcpyDeviceToHost, s));
     HIP_TRY(ctx, hipStreamSynchronize(s));
-    sam_status st = SAM_OK;
-    if (hflags[1] != n) st = fail(ctx, SAM_ERR_UNSORTED, "column %d references a column index outside [0, n)", hflags[1]);
-    else if (hflags[0]) st = fail(ctx, SAM_ERR_OVERFLOW, "pattern size does not fit in int32");
-    if (st == SAM_OK) {
-        HIP_TRY(ctx, grow(out_cp, (size_t)(n + 1) * 4));
-        HIP_TRY(ctx, grow(out_ri, (size_t)std::max<int64_t>(cur_nnz, 1) * 4));
-        HIP_TRY(ctx, hipMemcpyAsync(out_cp.p, cur_cp, (size_t)(n + 1) * 4, hipMemcpyDeviceToDevice, s));
-        if (cur_nnz > 0)
-            HIP_TRY(ctx, hipMemcpyAsync(out_ri.p, cur_ri, (size_t)cur_nnz * 4, hipMemcpyDeviceToDevice, s));
-        HIP_TRY(ctx, hipStreamSynchronize(s));
-        *nnz_out = cur_nnz;
-    }
-    release(level_cp); release(level_ri); release(level_cp2); release(level_ri2);
-    return st;
+    if (hflags[1] != n) return fail(ctx, SAM_ERR_UNSORTED, "column %d references a column index outside [0, n)", hflags[1]);
+    if (hflags[0]) return fail(ctx, SAM_ERR_OVERFLOW, "pattern size does not fit in int32");
+    res->nnz = last_nnz;
+    res->B_cp = w.B_cp;
+    res->B_ri = w.B_ri;
+    res->maxB = maxB;
+    res->S_cp = p == 1 ? w.B_cp : w.S_cp;
+    return SAM_OK;
 }
 
+sam_status pattern_fill(sam_ctx* ctx, int n, const PatternResult& res, int* S_cp, int* S_ri, hipStream_t s) {
+    HIP_TRY(ctx, hipMemcpyAsync(S_cp, res.S_cp, (size_t)(n + 1) * 4, hipMemcpyDeviceToDevice, s));
+    if (res.nnz == 0) return SAM_OK;
+    if (!res.last_cp) {   // power 1: S = B
+        HIP_TRY(ctx, hipMemcpyAsync(S_ri, res.B_ri, (size_t)res.nnz * 4, hipMemcpyDeviceToDevice, s));
+        return SAM_OK;
+    }
+    HIP_TRY(ctx, samk::expand_fill(n, res.last_cp, res.last_ri, res.B_cp, res.B_ri, S_cp, S_ri, res.last_max,
+                                   res.maxB, s));
+    return SAM_OK;
+}
+
+// ---------------------------------------------------------------- plans
 
 BucketTable menu_table(int prec, int weighted, std::vector<const NumericVariant*>* variants) {
     int cnt = 0;
@@ -245,22 +284,23 @@ BucketTable table_of(const std::vector<const NumericVariant*>& vars, int weighte
     return tab;
 }
 
-sam_status plan_combo(sam_plan* pl, int prec, int weighted, void* temp, int* unfit_d, hipStream_t s) {
+sam_status plan_combo(sam_plan* pl, int prec, int weighted, hipStream_t s) {
     std::vector<const NumericVariant*> vars;
     menu_table(prec, weighted, &vars);
-    return plan_combo_with(pl, prec, weighted, vars, temp, unfit_d, s);
+    return plan_combo_with(pl, prec, weighted, vars, s);
 }
 
 sam_status plan_combo_with(sam_plan* pl, int prec, int weighted, const std::vector<const NumericVariant*>& vars,
-                           void* temp, int* unfit_d, hipStream_t s) {
+                           hipStream_t s) {
     sam_ctx* ctx = pl->ctx;
     Combo& cb = pl->combo[prec][weighted];
     cb.variants = vars;
     if (cb.variants.size() > (size_t)samk::kMaxBuckets) cb.variants.resize(samk::kMaxBuckets);
     BucketTable tab = table_of(cb.variants, weighted);
     cb.tab = tab;
-    HIP_TRY(ctx, hipMemsetAsync(unfit_d, 0, sizeof(int), s));
-    HIP_TRY(ctx, samk::bucket_sort(pl->n, pl->S_cp, pl->nI, tab, cb.queue, cb.bstart, unfit_d, nullptr, temp, s));
+    int* unfit_d = pl->flags;
+    HIP_TRY(ctx, samk::fill_i32(unfit_d, 1, 0, s));
+    HIP_TRY(ctx, samk::bucket_sort(pl->n, pl->S_cp, pl->nI, tab, cb.queue, cb.bstart, unfit_d, nullptr, pl->btemp, s));
     std::vector<int> hb(tab.nb + 1, 0);
     int unfit = 0;
     HIP_TRY(ctx, hipMemcpyAsync(hb.data(), cb.bstart, sizeof(int) * (tab.nb + 1), hipMemcpyDeviceToHost, s));
@@ -279,7 +319,6 @@ sam_status plan_combo_with(sam_plan* pl, int prec, int weighted, const std::vect
     return SAM_OK;
 }
 
-
 // Blocks of a numeric variant the GPU holds at once per CU (16 when the
 // occupancy query failed).
 int resident_blocks(const sam_ctx* ctx, const NumericVariant* v) {
@@ -294,6 +333,138 @@ int partial_capacity(const sam_ctx* ctx) {
     int most = 16;
     for (int r : ctx->resident) most = std::max(most, r);
     return samk::kMaxBuckets * ctx->CUs * most;
+}
+
+namespace {
+
+struct PlanTemps {
+    int* counts;
+    int64_t* off;
+    void* stemp;
+};
+
+void plan_temp_layout(Carve& cv, int n, PlanTemps* t) {
+    PlanTemps x;
+    x.counts = cv.take<int>((size_t)n);
+    x.off = cv.take<int64_t>((size_t)n + 1);
+    x.stemp = cv.take<char>(samk::scan_temp_bytes(n));
+    if (t) *t = x;
+}
+
+// The plan's arrays (pl == null: measure only).
+void plan_array_layout(Carve& cv, int n, int64_t E, int nnzA0, int partcap, sam_plan* pl) {
+    sam_plan dummy;
+    sam_plan* p = pl ? pl : &dummy;
+    p->nI = cv.take<int>((size_t)n);
+    p->eoff = cv.take<int64_t>((size_t)n + 1);
+    p->posA = cv.take<unsigned char>((size_t)E);
+    p->posB = cv.take<unsigned char>((size_t)nnzA0);
+    for (int a = 0; a < 2; ++a)
+        for (int w = 0; w < 2; ++w) {
+            p->combo[a][w].queue = cv.take<int>((size_t)n);
+            p->combo[a][w].bstart = cv.take<int>(64);
+        }
+    p->colbuf = cv.take<double>((size_t)n);
+    p->partcap = partcap;
+    p->partbuf = cv.take<double>((size_t)partcap);
+    p->rtemp = cv.take<char>(samk::reduce_temp_bytes(std::max(n, partcap)));
+    p->btemp = cv.take<char>(samk::bucket_temp_bytes(n));
+    p->flags = cv.take<int>(4);
+}
+
+}  // namespace
+
+size_t plan_bytes(int n, int64_t E, int nnzA0, int partcap) {
+    Carve cv(nullptr);
+    plan_temp_layout(cv, n, nullptr);
+    plan_array_layout(cv, n, E, nnzA0, partcap, nullptr);
+    return cv.off;
+}
+
+sam_status gathered_total(sam_ctx* ctx, int n, const int32_t* S_cp, const int32_t* S_ri, const int32_t* Ak_cp,
+                          int64_t* E, hipStream_t s) {
+    *E = 0;
+    if (n == 0) return SAM_OK;
+    unsigned long long h = 0;
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->d_total, &h, sizeof h, hipMemcpyHostToDevice, s));
+    HIP_TRY(ctx, samk::plan_gather_total(n, S_cp, S_ri, Ak_cp, ctx->d_total, s));
+    HIP_TRY(ctx, read_back(ctx->d_total, &h, s));
+    *E = (int64_t)h;
+    return SAM_OK;
+}
+
+sam_status plan_init(sam_ctx* ctx, sam_plan* pl, const sam_csc* Ak, const sam_csc* A0, const int32_t* S_colptr,
+                     const int32_t* S_rowind, int64_t nnz_S, void* mem, size_t mem_bytes, hipStream_t s) {
+    const int n = Ak->n;
+    pl->ctx = ctx;
+    pl->n = n;
+    pl->nnzA = Ak->nnz;
+    pl->nnzA0 = A0->nnz;
+    pl->nnzS = nnz_S;
+    pl->Ak_cp = Ak->colptr;
+    pl->Ak_ri = Ak->rowind;
+    pl->A0_cp = A0->colptr;
+    pl->A0_ri = A0->rowind;
+    pl->S_cp = S_colptr;
+    pl->S_ri = S_rowind;
+    pl->mem = mem;
+    pl->mem_bytes = mem_bytes;
+    Carve cv(mem);
+    PlanTemps t;
+    plan_temp_layout(cv, n, &t);
+    const size_t temps = cv.off;
+    if (mem_bytes < temps) return fail(ctx, SAM_ERR_ARG, "plan memory: %zu bytes given, more needed", mem_bytes);
+
+    std::vector<int> hcp;
+    int longest = 0;
+    sam_status st;
+    if ((st = host_colptr(ctx, Ak->colptr, n, Ak->nnz, "Ak", &pl->max_len_A, s))) return st;
+    if ((st = host_colptr(ctx, S_colptr, n, nnz_S, "S", &longest, s, &hcp))) return st;
+    // pass 1: gathered entries per column -> eoff
+    int64_t E = 0;
+    if (n > 0) {
+        HIP_TRY(ctx, samk::plan_gather_count(n, S_colptr, S_rowind, Ak->colptr, t.counts, s));
+        HIP_TRY(ctx, samk::scan_counts(t.counts, n, t.off, nullptr, nullptr, t.stemp, s));
+        HIP_TRY(ctx, read_back(t.off + n, &E, s));
+    }
+    pl->E = E;
+    // the numeric kernels address A_k, A_0 and the gathered positions with
+    // 32-bit byte offsets
+    if ((int64_t)Ak->nnz * 8 > (int64_t)UINT32_MAX || (int64_t)A0->nnz * 8 > (int64_t)UINT32_MAX ||
+        E > (int64_t)UINT32_MAX)
+        return fail(ctx, SAM_ERR_UNSUPPORTED,
+                    "nnz(A_k) = %d, nnz(A_0) = %d, gathered entries = %lld: the numeric kernels need "
+                    "nnz < 2^29 and fewer than 2^32 gathered entries (split the columns)",
+                    Ak->nnz, A0->nnz, (long long)E);
+    plan_array_layout(cv, n, E, A0->nnz, partial_capacity(ctx), pl);
+    if (cv.off > mem_bytes)
+        return fail(ctx, SAM_ERR_ARG, "plan memory: %zu bytes given, %zu needed", mem_bytes, cv.off);
+
+    if (n > 0) {
+        std::vector<int> hnI(n);
+        HIP_TRY(ctx, hipMemcpyAsync(pl->eoff, t.off, (size_t)(n + 1) * 8, hipMemcpyDeviceToDevice, s));
+        HIP_TRY(ctx, samk::plan_positions(n, S_colptr, S_rowind, Ak->colptr, Ak->rowind, A0->colptr, A0->rowind,
+                                          pl->eoff, pl->nI, pl->posA, pl->posB, longest, pl->max_len_A, s));
+        HIP_TRY(ctx, hipMemcpyAsync(hnI.data(), pl->nI, (size_t)n * 4, hipMemcpyDeviceToHost, s));
+        HIP_TRY(ctx, hipStreamSynchronize(s));
+        for (int j = 0; j < n; ++j) {
+            pl->max_rows = std::max(pl->max_rows, hnI[j]);
+            const int cj = hcp[(size_t)j + 1] - hcp[(size_t)j];
+            pl->max_cols = std::max(pl->max_cols, cj);
+            const double r = hnI[j], c = cj;
+            // Householder QR of the r x c block (2 r c^2 - 2/3 c^3), Q^T b
+            // (4 r c) and three triangular solves (3 c^2: the solution and
+            // the refinement's two)
+            pl->fl_qr32 += 2.0 * r * c * c - 2.0 / 3.0 * c * c * c + 4.0 * r * c + 3.0 * c * c;
+            pl->fl_ref64 += 6.0 * r * c + 2.0 * r;   // r = b - Am, A^T r, final residual
+            // FP64 mode: QR, Q^T b, one triangular solve, explicit residual
+            pl->fl_f64 += 2.0 * r * c * c - 2.0 / 3.0 * c * c * c + 4.0 * r * c + c * c + 2.0 * r * c + 2.0 * r;
+        }
+        for (int p = 0; p < 2; ++p)
+            for (int w = 0; w < 2; ++w)
+                if ((st = plan_combo(pl, p, w, s))) return st;
+    }
+    return SAM_OK;
 }
 
 // Launch every non-empty bucket of a combination, then the column-residual sum.
@@ -345,15 +516,46 @@ sam_status run_numeric(sam_plan* pl, const double* Ak_val, const double* A0_val,
         parts += grid;
     }
     if (res2 && parts > 0) HIP_TRY(ctx, samk::reduce_sum(pl->partbuf, parts, res2, pl->rtemp, s));
-    if (res2 && parts == 0) HIP_TRY(ctx, hipMemsetAsync(res2, 0, sizeof(double), s));
+    if (res2 && parts == 0) HIP_TRY(ctx, samk::fill_i32((int*)res2, 2, 0, s));
     return SAM_OK;
 }
 
 }  // namespace samh
 
+namespace {
+
+// Residual scratch: the column residuals (n doubles) and the reduction
+// temporary.
+size_t residual_layout(Carve& cv, int n, int nnzA0, double** cols, void** rt) {
+    double* c = cv.take<double>((size_t)std::max(n, 1));
+    void* r = cv.take<char>(samk::reduce_temp_bytes(std::max<int64_t>(n, nnzA0)));
+    if (cols) *cols = c;
+    if (rt) *rt = r;
+    return cv.off;
+}
+
+// Row-view scratch of sam_apply_prepare.
+struct TransposeTemps {
+    int* rowcount;
+    int* cursor;
+    int64_t* off;
+    void* stemp;
+};
+size_t transpose_layout(Carve& cv, int n, TransposeTemps* t) {
+    TransposeTemps x;
+    x.rowcount = cv.take<int>((size_t)std::max(n, 1));
+    x.cursor = cv.take<int>((size_t)std::max(n, 1));
+    x.off = cv.take<int64_t>((size_t)n + 1);
+    x.stemp = cv.take<char>(samk::scan_temp_bytes(n));
+    if (t) *t = x;
+    return cv.off;
+}
+
+}  // namespace
+
 extern "C" {
 
-const char* sam_version(void) { return "0.1.0"; }
+const char* sam_version(void) { return "0.2.0"; }
 
 const char* sam_status_string(sam_status s) {
     switch (s) {
@@ -396,13 +598,18 @@ sam_status sam_create(sam_ctx** out, int device) {
             ctx->resident.assign(cnt, 0);
             for (int i = 0; i < cnt; ++i) ctx->resident[i] = menu[i].blocks_per_cu();
         }
-        if (hipMalloc(&ctx->d_status, sizeof(unsigned long long)) != hipSuccess) {
+        // the context's status block: the only device memory the library
+        // allocates itself
+        if (hipMalloc(&ctx->block, kCtxBlockBytes) != hipSuccess) {
             delete ctx;
             return SAM_ERR_NOMEM;
         }
+        ctx->d_status = (unsigned long long*)ctx->block;
+        ctx->d_bad = (int*)((char*)ctx->block + 64);
+        ctx->d_total = (unsigned long long*)((char*)ctx->block + 128);
         unsigned long long clear = kStatusClear;
         if (hipMemcpy(ctx->d_status, &clear, sizeof clear, hipMemcpyHostToDevice) != hipSuccess) {
-            (void)hipFree(ctx->d_status);
+            (void)hipFree(ctx->block);
             delete ctx;
             return SAM_ERR_HIP;
         }
@@ -416,10 +623,7 @@ sam_status sam_destroy(sam_ctx* ctx) {
     if (ctx->device != SAM_NO_DEVICE) {
         (void)hipSetDevice(ctx->device);
         (void)hipDeviceSynchronize();
-        if (ctx->d_status) (void)hipFree(ctx->d_status);
-        release(ctx->ws);
-        release(ctx->S_cp);
-        release(ctx->S_ri);
+        if (ctx->block) (void)hipFree(ctx->block);
     }
     delete ctx;
     return SAM_OK;
@@ -453,60 +657,107 @@ sam_status sam_check_csc(sam_ctx* ctx, const sam_csc* A, sam_stream_t stream) {
     sam_status st = check_csc_args(ctx, A, "A", false);
     if (st) return st;
     if ((st = need_device(ctx))) return st;
-    hipStream_t s = S(stream);
-    HIP_TRY(ctx, grow(ctx->ws, 256));
-    int* bad = (int*)ctx->ws.p;
-    int h = A->n;
-    HIP_TRY(ctx, hipMemcpyAsync(bad, &h, sizeof h, hipMemcpyHostToDevice, s));
-    HIP_TRY(ctx, samk::check_csc(A->n, A->nnz, A->colptr, A->rowind, bad, s));
-    HIP_TRY(ctx, hipMemcpyAsync(&h, bad, sizeof h, hipMemcpyDeviceToHost, s));
-    HIP_TRY(ctx, hipStreamSynchronize(s));
-    if (h != A->n) return fail(ctx, SAM_ERR_UNSORTED, "invalid CSC structure at column %d", h);
+    return validate_csc(ctx, A->n, A->nnz, A->colptr, A->rowind, "A", S(stream));
+}
+
+// ---------------------------------------------------------------- pattern
+
+sam_status sam_pattern_workspace_size(sam_ctx* ctx, const sam_csc* Ak, const sam_pattern_spec* spec, size_t* bytes,
+                                      sam_stream_t stream) {
+    if (check_ctx(ctx)) return SAM_ERR_ARG;
+    sam_status st;
+    if ((st = check_csc_args(ctx, Ak, "Ak", false))) return st;
+    if ((st = check_spec(ctx, spec))) return st;
+    if (!bytes) return fail(ctx, SAM_ERR_ARG, "bytes is NULL");
+    if ((st = need_device(ctx))) return st;
+    int longest = 0;
+    if ((st = host_colptr(ctx, Ak->colptr, Ak->n, Ak->nnz, "Ak", &longest, S(stream)))) return st;
+    Carve cv(nullptr);
+    pattern_ws_layout(cv, Ak->n, Ak->nnz, longest, spec->power, nullptr);
+    *bytes = cv.off;
     return SAM_OK;
 }
 
-sam_status sam_pattern_count(sam_ctx* ctx, const sam_csc* Ak, const sam_pattern_spec* spec, int64_t* nnz_S,
-                             sam_stream_t stream) {
+sam_status sam_pattern_count(sam_ctx* ctx, const sam_csc* Ak, const sam_pattern_spec* spec, void* ws, size_t ws_bytes,
+                             int64_t* nnz_S, sam_stream_t stream) {
     if (check_ctx(ctx)) return SAM_ERR_ARG;
     sam_status st;
     if ((st = check_csc_args(ctx, Ak, "Ak", spec && spec->kind != SAM_SPARSIFY_NONE))) return st;
     if ((st = check_spec(ctx, spec))) return st;
     if (!nnz_S) return fail(ctx, SAM_ERR_ARG, "nnz_S is NULL");
     if ((st = need_device(ctx))) return st;
-    ctx->S_nnz = -1;
-    int64_t nnz = 0;
-    st = compute_pattern(ctx, Ak, spec, ctx->S_cp, ctx->S_ri, &nnz, S(stream));
-    if (st) return st;
-    ctx->S_nnz = nnz;
-    ctx->S_n = Ak->n;
-    ctx->key_cp = Ak->colptr;
-    ctx->key_ri = Ak->rowind;
-    ctx->key_val = Ak->val;
-    ctx->key_spec = *spec;
-    *nnz_S = nnz;
+    hipStream_t s = S(stream);
+    ctx->pat.valid = false;
+    int longest = 0;
+    if ((st = host_colptr(ctx, Ak->colptr, Ak->n, Ak->nnz, "Ak", &longest, s))) return st;
+    Carve cv(ws);
+    PatternWs w;
+    pattern_ws_layout(cv, Ak->n, Ak->nnz, longest, spec->power, &w);
+    if ((st = check_ws(ctx, ws, ws_bytes, cv.off, "pattern workspace"))) return st;
+    if ((st = validate_csc(ctx, Ak->n, Ak->nnz, Ak->colptr, Ak->rowind, "Ak", s))) return st;
+    PatternResult res;
+    if ((st = compute_pattern(ctx, Ak, spec, w, &res, s))) return st;
+    PatternState& ps = ctx->pat;
+    ps.valid = true;
+    ps.ws = ws;
+    ps.n = Ak->n;
+    ps.nnz_A = Ak->nnz;
+    ps.cp = Ak->colptr;
+    ps.ri = Ak->rowind;
+    ps.val = Ak->val;
+    ps.spec = *spec;
+    ps.power = spec->power;
+    ps.res = res;
+    *nnz_S = res.nnz;
     return SAM_OK;
 }
 
-sam_status sam_pattern_fill(sam_ctx* ctx, const sam_csc* Ak, const sam_pattern_spec* spec, int32_t* S_colptr,
-                            int32_t* S_rowind, sam_stream_t stream) {
+sam_status sam_pattern_fill(sam_ctx* ctx, const sam_csc* Ak, const sam_pattern_spec* spec, void* ws, size_t ws_bytes,
+                            int32_t* S_colptr, int32_t* S_rowind, sam_stream_t stream) {
     if (check_ctx(ctx)) return SAM_ERR_ARG;
     sam_status st;
     if ((st = check_csc_args(ctx, Ak, "Ak", false))) return st;
     if ((st = check_spec(ctx, spec))) return st;
-    if (!S_colptr || (!S_rowind && ctx->S_nnz != 0)) return fail(ctx, SAM_ERR_ARG, "output array is NULL");
+    const PatternState& ps = ctx->pat;
+    if (!S_colptr || (!S_rowind && ps.valid && ps.res.nnz != 0)) return fail(ctx, SAM_ERR_ARG, "output array is NULL");
     if ((st = need_device(ctx))) return st;
-    if (ctx->S_nnz < 0 || ctx->S_n != Ak->n || ctx->key_cp != Ak->colptr || ctx->key_ri != Ak->rowind ||
-        ctx->key_val != Ak->val || memcmp(&ctx->key_spec, spec, sizeof *spec) != 0)
-        return fail(ctx, SAM_ERR_ARG, "sam_pattern_fill must follow sam_pattern_count with the same Ak and spec");
+    (void)ws_bytes;
+    if (!ps.valid || ps.ws != ws || ps.n != Ak->n || ps.nnz_A != Ak->nnz || ps.cp != Ak->colptr ||
+        ps.ri != Ak->rowind || ps.val != Ak->val || memcmp(&ps.spec, spec, sizeof *spec) != 0)
+        return fail(ctx, SAM_ERR_ARG,
+                    "sam_pattern_fill must follow sam_pattern_count with the same Ak, spec and workspace");
+    return pattern_fill(ctx, Ak->n, ps.res, S_colptr, S_rowind, S(stream));
+}
+
+// ------------------------------------------------------------------ plan
+
+sam_status sam_plan_size(sam_ctx* ctx, const sam_csc* Ak, const sam_csc* A0, const int32_t* S_colptr,
+                         const int32_t* S_rowind, int64_t nnz_S, size_t* bytes, sam_stream_t stream) {
+    if (check_ctx(ctx)) return SAM_ERR_ARG;
+    sam_status st;
+    if ((st = check_csc_args(ctx, Ak, "Ak", false))) return st;
+    if ((st = check_csc_args(ctx, A0, "A0", false))) return st;
+    if (Ak->n != A0->n) return fail(ctx, SAM_ERR_SHAPE, "Ak is %d x %d but A0 is %d x %d", Ak->n, Ak->n, A0->n, A0->n);
+    if (Ak->n > 0 && (Ak->nnz == 0 || A0->nnz == 0))
+        return fail(ctx, SAM_ERR_ARG, "Ak and A0 must have stored entries (a nonsingular source has at least n)");
+    if (nnz_S < 0) return fail(ctx, SAM_ERR_ARG, "nnz_S < 0");
+    if (nnz_S > INT_MAX) return fail(ctx, SAM_ERR_OVERFLOW, "nnz_S = %lld does not fit in int32", (long long)nnz_S);
+    if (!S_colptr || (nnz_S > 0 && !S_rowind)) return fail(ctx, SAM_ERR_ARG, "pattern array is NULL");
+    if (!bytes) return fail(ctx, SAM_ERR_ARG, "bytes is NULL");
+    if ((st = need_device(ctx))) return st;
     hipStream_t s = S(stream);
-    HIP_TRY(ctx, hipMemcpyAsync(S_colptr, ctx->S_cp.p, (size_t)(Ak->n + 1) * 4, hipMemcpyDeviceToDevice, s));
-    if (ctx->S_nnz > 0)
-        HIP_TRY(ctx, hipMemcpyAsync(S_rowind, ctx->S_ri.p, (size_t)ctx->S_nnz * 4, hipMemcpyDeviceToDevice, s));
+    const int n = Ak->n;
+    if ((st = validate_csc(ctx, n, Ak->nnz, Ak->colptr, Ak->rowind, "Ak", s))) return st;
+    if ((st = validate_csc(ctx, n, nnz_S, S_colptr, S_rowind, "S", s))) return st;
+    int64_t E = 0;
+    if ((st = gathered_total(ctx, n, S_colptr, S_rowind, Ak->colptr, &E, s))) return st;
+    *bytes = plan_bytes(n, E, A0->nnz, partial_capacity(ctx));
     return SAM_OK;
 }
 
 sam_status sam_plan_create(sam_ctx* ctx, const sam_csc* Ak, const sam_csc* A0, const int32_t* S_colptr,
-                           const int32_t* S_rowind, int64_t nnz_S, sam_plan** plan, sam_stream_t stream) {
+                           const int32_t* S_rowind, int64_t nnz_S, void* mem, size_t mem_bytes, sam_plan** plan,
+                           sam_stream_t stream) {
     if (check_ctx(ctx)) return SAM_ERR_ARG;
     sam_status st;
     if (!plan) return fail(ctx, SAM_ERR_ARG, "plan is NULL");
@@ -519,123 +770,18 @@ sam_status sam_plan_create(sam_ctx* ctx, const sam_csc* Ak, const sam_csc* A0, c
     if (nnz_S < 0) return fail(ctx, SAM_ERR_ARG, "nnz_S < 0");
     if (nnz_S > INT_MAX) return fail(ctx, SAM_ERR_OVERFLOW, "nnz_S = %lld does not fit in int32", (long long)nnz_S);
     if (!S_colptr || (nnz_S > 0 && !S_rowind)) return fail(ctx, SAM_ERR_ARG, "pattern array is NULL");
+    if ((st = check_ws(ctx, mem, mem_bytes, 1, "plan memory"))) return st;
     if ((st = need_device(ctx))) return st;
     hipStream_t s = S(stream);
     const int n = Ak->n;
-
+    if ((st = validate_csc(ctx, n, Ak->nnz, Ak->colptr, Ak->rowind, "Ak", s))) return st;
+    if ((st = validate_csc(ctx, n, A0->nnz, A0->colptr, A0->rowind, "A0", s))) return st;
+    if ((st = validate_csc(ctx, n, nnz_S, S_colptr, S_rowind, "S", s))) return st;
     sam_plan* pl = new (std::nothrow) sam_plan();
     if (!pl) return fail(ctx, SAM_ERR_NOMEM, "host allocation failed");
-    pl->ctx = ctx;
-    pl->n = n;
-    pl->nnzA = Ak->nnz;
-    pl->nnzA0 = A0->nnz;
-    pl->nnzS = nnz_S;
-    pl->Ak_cp = Ak->colptr;
-    pl->Ak_ri = Ak->rowind;
-    pl->A0_cp = A0->colptr;
-    pl->A0_ri = A0->rowind;
-    pl->S_cp = S_colptr;
-    pl->S_ri = S_rowind;
-    auto bail = [&](sam_status code) {
-        release(pl->mem);
+    if ((st = plan_init(ctx, pl, Ak, A0, S_colptr, S_rowind, nnz_S, mem, mem_bytes, s))) {
         delete pl;
-        return code;
-    };
-
-    // pass 1: gathered entries per column -> eoff (host needs E)
-    size_t tmp_need = align256((size_t)n * 4) + align256((size_t)(n + 1) * 8) + align256(samk::scan_temp_bytes(n)) +
-                      align256(samk::bucket_temp_bytes(n)) + 1024;
-    hipError_t he = grow(ctx->ws, tmp_need);
-    if (he != hipSuccess) return bail(fail(ctx, SAM_ERR_NOMEM, "workspace: %s", hipGetErrorString(he)));
-    Carve tw(ctx->ws.p);
-    int* counts = tw.take<int>(n);
-    int64_t* off = tw.take<int64_t>(n + 1);
-    void* stemp = tw.take<char>(samk::scan_temp_bytes(n));
-    void* btemp = tw.take<char>(samk::bucket_temp_bytes(n));
-    int* flags = tw.take<int>(4);
-
-    // S's column pointers are checked on the host before any kernel reads S;
-    // the longest column of A_k sizes the positions launch
-    std::vector<int> hcp((size_t)n + 1, 0);
-    int longest = 0;
-    if (n > 0) {
-        std::vector<int> hak((size_t)n + 1);
-        if ((he = hipMemcpyAsync(hak.data(), Ak->colptr, hak.size() * 4, hipMemcpyDeviceToHost, s)) != hipSuccess ||
-            (he = hipStreamSynchronize(s)) != hipSuccess)
-            return bail(fail(ctx, SAM_ERR_HIP, "reading Ak colptr: %s", hipGetErrorString(he)));
-        for (int j = 0; j < n; ++j) pl->max_len_A = std::max(pl->max_len_A, hak[(size_t)j + 1] - hak[(size_t)j]);
-        if ((he = hipMemcpyAsync(hcp.data(), S_colptr, (size_t)(n + 1) * 4, hipMemcpyDeviceToHost, s)) != hipSuccess ||
-            (he = hipStreamSynchronize(s)) != hipSuccess)
-            return bail(fail(ctx, SAM_ERR_HIP, "reading S_colptr: %s", hipGetErrorString(he)));
-        if (hcp[0] != 0 || hcp[n] != nnz_S)
-            return bail(fail(ctx, SAM_ERR_SHAPE, "S_colptr[0] = %d, S_colptr[n] = %d but nnz_S = %lld", hcp[0], hcp[n],
-                             (long long)nnz_S));
-        for (int j = 0; j < n; ++j) {
-            if (hcp[j + 1] < hcp[j])
-                return bail(fail(ctx, SAM_ERR_UNSORTED, "S_colptr decreases at column %d", j));
-            longest = std::max(longest, hcp[j + 1] - hcp[j]);
-        }
-    }
-    int64_t E = 0;
-    if (n > 0) {
-        if ((he = samk::plan_gather_count(n, S_colptr, S_rowind, Ak->colptr, counts, s)) != hipSuccess ||
-            (he = samk::scan_counts(counts, n, off, nullptr, nullptr, stemp, s)) != hipSuccess ||
-            (he = read_back(off + n, &E, s)) != hipSuccess)
-            return bail(fail(ctx, SAM_ERR_HIP, "plan count: %s", hipGetErrorString(he)));
-    }
-    pl->E = E;
-    // the numeric kernels address A_k, A_0 and the gathered positions with
-    // 32-bit byte offsets
-    if ((int64_t)Ak->nnz * 8 > (int64_t)UINT32_MAX || (int64_t)A0->nnz * 8 > (int64_t)UINT32_MAX ||
-        E > (int64_t)UINT32_MAX)
-        return bail(fail(ctx, SAM_ERR_UNSUPPORTED,
-                         "nnz(A_k) = %d, nnz(A_0) = %d, gathered entries = %lld: the numeric kernels need "
-                         "nnz < 2^29 and fewer than 2^32 gathered entries (split the columns)",
-                         Ak->nnz, A0->nnz, (long long)E));
-    size_t mem = align256((size_t)n * 4) + align256((size_t)(n + 1) * 8) + align256((size_t)std::max<int64_t>(E, 1)) +
-                 align256((size_t)std::max(A0->nnz, 1)) + 4 * (align256((size_t)n * 4) + align256(64 * 4)) +
-                 align256((size_t)n * 8) + align256((size_t)partial_capacity(ctx) * 8) +
-                 align256(samk::reduce_temp_bytes(std::max(n, partial_capacity(ctx)))) + 1024;
-    if ((he = grow(pl->mem, mem)) != hipSuccess)
-        return bail(fail(ctx, SAM_ERR_NOMEM, "plan memory (%zu bytes): %s", mem, hipGetErrorString(he)));
-    Carve cv(pl->mem.p);
-    pl->nI = cv.take<int>(n);
-    pl->eoff = cv.take<int64_t>(n + 1);
-    pl->posA = cv.take<unsigned char>((size_t)std::max<int64_t>(E, 1));
-    pl->posB = cv.take<unsigned char>((size_t)std::max(A0->nnz, 1));
-    for (int p = 0; p < 2; ++p)
-        for (int w = 0; w < 2; ++w) {
-            pl->combo[p][w].queue = cv.take<int>(n);
-            pl->combo[p][w].bstart = cv.take<int>(64);
-        }
-    pl->colbuf = cv.take<double>(n);
-    pl->partcap = partial_capacity(ctx);
-    pl->partbuf = cv.take<double>((size_t)pl->partcap);
-    pl->rtemp = cv.take<char>(samk::reduce_temp_bytes(std::max(n, pl->partcap)));
-
-    if (n > 0) {
-        std::vector<int> hnI(n);
-        if ((he = hipMemcpyAsync(pl->eoff, off, (size_t)(n + 1) * 8, hipMemcpyDeviceToDevice, s)) != hipSuccess ||
-            (he = samk::plan_positions(n, S_colptr, S_rowind, Ak->colptr, Ak->rowind, A0->colptr, A0->rowind,
-                                       pl->eoff, pl->nI, pl->posA, pl->posB, longest, pl->max_len_A, s)) !=
-                hipSuccess)
-            return bail(fail(ctx, SAM_ERR_HIP, "plan positions: %s", hipGetErrorString(he)));
-        if ((he = hipMemcpyAsync(hnI.data(), pl->nI, (size_t)n * 4, hipMemcpyDeviceToHost, s)) != hipSuccess ||
-            (he = hipStreamSynchronize(s)) != hipSuccess)
-            return bail(fail(ctx, SAM_ERR_HIP, "plan stats: %s", hipGetErrorString(he)));
-        for (int j = 0; j < n; ++j) {
-            pl->max_rows = std::max(pl->max_rows, hnI[j]);
-            pl->max_cols = std::max(pl->max_cols, hcp[j + 1] - hcp[j]);
-            const double r = hnI[j], c = hcp[j + 1] - hcp[j];
-            // Householder QR of the r x c block, Q^T b and back substitution
-            const double qr = 2.0 * r * c * c - 2.0 / 3.0 * c * c * c + 4.0 * r * c - 2.0 * c * c + c * c;
-            pl->fl_qr32 += qr + 2.0 * c * c;              // + two triangular solves of the refinement
-            pl->fl_ref64 += 6.0 * r * c + 2.0 * r;         // r = b - Am, A^T r, final residual
-            pl->fl_f64 += qr + 2.0 * r * c + 2.0 * r;      // FP64 mode: explicit residual
-        }
-        for (int p = 0; p < 2; ++p)
-            for (int w = 0; w < 2; ++w)
-                if ((st = plan_combo(pl, p, w, btemp, flags, s))) return bail(st);
+        return st;
     }
     *plan = pl;
     return SAM_OK;
@@ -647,8 +793,6 @@ sam_status sam_plan_destroy(sam_plan* plan) {
         (void)hipSetDevice(plan->ctx->device);
         (void)hipDeviceSynchronize();   // no launch on the plan's memory is still running
     }
-    release(plan->mem);
-    release(plan->bwd);
     delete plan;
     return SAM_OK;
 }
@@ -681,10 +825,7 @@ sam_status sam_plan_info(const sam_plan* plan, int32_t* n, int32_t* max_rows, in
     return SAM_OK;
 }
 
-}  // extern "C"
-
-
-extern "C" {
+// ------------------------------------------------------------------ build
 
 sam_status sam_build_planned(sam_plan* plan, const double* Ak_val, const double* A0_val, sam_precision prec,
                              void* M_val, double* col_res2, double* res2, sam_stream_t stream) {
@@ -700,9 +841,17 @@ sam_status sam_build_planned(sam_plan* plan, const double* Ak_val, const double*
                        res2, S(stream));
 }
 
+sam_status sam_workspace_size(sam_ctx* ctx, const sam_csc* Ak, const sam_csc* A0, const int32_t* S_colptr,
+                              const int32_t* S_rowind, int64_t nnz_S, sam_precision prec, size_t* bytes,
+                              sam_stream_t stream) {
+    if (check_ctx(ctx)) return SAM_ERR_ARG;
+    if (!prec_ok(prec)) return fail(ctx, SAM_ERR_ARG, "unknown precision %d", (int)prec);
+    return sam_plan_size(ctx, Ak, A0, S_colptr, S_rowind, nnz_S, bytes, stream);
+}
+
 sam_status sam_build(sam_ctx* ctx, const sam_csc* Ak, const sam_csc* A0, const int32_t* S_colptr,
                      const int32_t* S_rowind, int64_t nnz_S, sam_precision prec, void* M_val, double* col_res2,
-                     double* res2, sam_stream_t stream) {
+                     double* res2, void* ws, size_t ws_bytes, sam_stream_t stream) {
     if (check_ctx(ctx)) return SAM_ERR_ARG;
     sam_status st;
     if ((st = check_csc_args(ctx, Ak, "Ak", true))) return st;
@@ -710,18 +859,24 @@ sam_status sam_build(sam_ctx* ctx, const sam_csc* Ak, const sam_csc* A0, const i
     if (!prec_ok(prec)) return fail(ctx, SAM_ERR_ARG, "unknown precision %d", (int)prec);
     if (nnz_S > 0 && !M_val) return fail(ctx, SAM_ERR_ARG, "M_val is NULL");
     sam_plan* pl = nullptr;
-    if ((st = sam_plan_create(ctx, Ak, A0, S_colptr, S_rowind, nnz_S, &pl, stream))) return st;
+    if ((st = sam_plan_create(ctx, Ak, A0, S_colptr, S_rowind, nnz_S, ws, ws_bytes, &pl, stream))) return st;
     st = sam_build_planned(pl, Ak->val, A0->val, prec, M_val, col_res2, res2, stream);
-    hipError_t e = hipStreamSynchronize(S(stream));
-    sam_plan_destroy(pl);
-    if (st) return st;
-    if (e != hipSuccess) return fail(ctx, SAM_ERR_HIP, "sam_build: %s", hipGetErrorString(e));
+    delete pl;   // host record only: the launches hold their arguments by value
+    return st;
+}
+
+// --------------------------------------------------------------- residual
+
+sam_status sam_residual_workspace_size(int32_t n, int32_t nnz_A0, size_t* bytes) {
+    if (n < 0 || nnz_A0 < 0 || !bytes) return SAM_ERR_ARG;
+    Carve cv(nullptr);
+    *bytes = residual_layout(cv, n, nnz_A0, nullptr, nullptr);
     return SAM_OK;
 }
 
 sam_status sam_residual(sam_ctx* ctx, const sam_csc* Ak, const sam_csc* A0, const int32_t* M_colptr,
                         const int32_t* M_rowind, int64_t nnz_M, const void* M_val, sam_precision prec, double* res2,
-                        double* a02, sam_stream_t stream) {
+                        double* a02, void* ws, size_t ws_bytes, sam_stream_t stream) {
     if (check_ctx(ctx)) return SAM_ERR_ARG;
     sam_status st;
     if ((st = check_csc_args(ctx, Ak, "Ak", true))) return st;
@@ -730,17 +885,17 @@ sam_status sam_residual(sam_ctx* ctx, const sam_csc* Ak, const sam_csc* A0, cons
     if (!prec_ok(prec)) return fail(ctx, SAM_ERR_ARG, "unknown precision %d", (int)prec);
     if (!M_colptr || (nnz_M > 0 && (!M_rowind || !M_val)) || !res2) return fail(ctx, SAM_ERR_ARG, "NULL argument");
     if (nnz_M < 0 || nnz_M > INT_MAX) return fail(ctx, SAM_ERR_OVERFLOW, "nnz_M out of range");
+    const int n = Ak->n;
+    Carve cv(ws);
+    double* cols = nullptr;
+    void* rt = nullptr;
+    if ((st = check_ws(ctx, ws, ws_bytes, residual_layout(cv, n, A0->nnz, &cols, &rt), "residual workspace")))
+        return st;
     if ((st = need_device(ctx))) return st;
     hipStream_t s = S(stream);
-    const int n = Ak->n;
-    const size_t need = align256((size_t)std::max(n, 1) * 8) + align256(samk::reduce_temp_bytes(std::max<int64_t>(n, A0->nnz))) + 512;
-    HIP_TRY(ctx, grow(ctx->ws, need));
-    Carve cv(ctx->ws.p);
-    double* cols = cv.take<double>(std::max(n, 1));
-    void* rt = cv.take<char>(samk::reduce_temp_bytes(std::max<int64_t>(n, A0->nnz)));
     if (n == 0) {
-        HIP_TRY(ctx, hipMemsetAsync(res2, 0, sizeof(double), s));
-        if (a02) HIP_TRY(ctx, hipMemsetAsync(a02, 0, sizeof(double), s));
+        HIP_TRY(ctx, samk::fill_i32((int*)res2, 2, 0, s));
+        if (a02) HIP_TRY(ctx, samk::fill_i32((int*)a02, 2, 0, s));
         return SAM_OK;
     }
     HIP_TRY(ctx, samk::residual_columns(n, Ak->colptr, Ak->rowind, Ak->val, A0->colptr, A0->rowind, A0->val, M_colptr,
@@ -750,31 +905,36 @@ sam_status sam_residual(sam_ctx* ctx, const sam_csc* Ak, const sam_csc* A0, cons
     return SAM_OK;
 }
 
+// ------------------------------------------------------------------ apply
+
+sam_status sam_apply_workspace_size(int32_t n, size_t* bytes) {
+    if (n < 0 || !bytes) return SAM_ERR_ARG;
+    Carve cv(nullptr);
+    *bytes = transpose_layout(cv, n, nullptr);
+    return SAM_OK;
+}
+
 sam_status sam_apply_prepare(sam_ctx* ctx, int32_t n, const int32_t* M_colptr, const int32_t* M_rowind, int64_t nnz,
-                             int32_t* T_rowptr, int32_t* T_colind, int32_t* T_perm, sam_stream_t stream) {
+                             int32_t* T_rowptr, int32_t* T_colind, int32_t* T_perm, void* ws, size_t ws_bytes,
+                             sam_stream_t stream) {
     if (check_ctx(ctx)) return SAM_ERR_ARG;
     if (n < 0 || nnz < 0) return fail(ctx, SAM_ERR_ARG, "negative size");
     if (nnz > INT_MAX) return fail(ctx, SAM_ERR_OVERFLOW, "nnz does not fit in int32");
     if (!M_colptr || !T_rowptr || (nnz > 0 && (!M_rowind || !T_colind || !T_perm)))
         return fail(ctx, SAM_ERR_ARG, "NULL argument");
-    sam_status st = need_device(ctx);
-    if (st) return st;
+    Carve cv(ws);
+    TransposeTemps t;
+    sam_status st;
+    if ((st = check_ws(ctx, ws, ws_bytes, transpose_layout(cv, n, &t), "apply workspace"))) return st;
+    if ((st = need_device(ctx))) return st;
     hipStream_t s = S(stream);
-    const size_t need = 2 * align256((size_t)std::max(n, 1) * 4) + align256((size_t)(n + 1) * 8) +
-                        align256(samk::scan_temp_bytes(n)) + 512;
-    HIP_TRY(ctx, grow(ctx->ws, need));
-    Carve cv(ctx->ws.p);
-    int* rowcount = cv.take<int>(std::max(n, 1));
-    int* cursor = cv.take<int>(std::max(n, 1));
-    int64_t* off = cv.take<int64_t>(n + 1);
-    void* stemp = cv.take<char>(samk::scan_temp_bytes(n));
-    HIP_TRY(ctx, hipMemsetAsync(rowcount, 0, (size_t)std::max(n, 1) * 4, s));
-    HIP_TRY(ctx, hipMemsetAsync(cursor, 0, (size_t)std::max(n, 1) * 4, s));
-    HIP_TRY(ctx, samk::transpose_count(n, M_colptr, M_rowind, nnz, rowcount, s));
-    HIP_TRY(ctx, samk::scan_counts(rowcount, n, off, T_rowptr, nullptr, stemp, s));
-    HIP_TRY(ctx, samk::transpose_fill(n, M_colptr, M_rowind, T_rowptr, cursor, T_colind, T_perm, s));
+    if ((st = validate_csc(ctx, n, nnz, M_colptr, M_rowind, "M", s))) return st;
+    HIP_TRY(ctx, samk::fill_i32(t.rowcount, std::max(n, 1), 0, s));
+    HIP_TRY(ctx, samk::fill_i32(t.cursor, std::max(n, 1), 0, s));
+    HIP_TRY(ctx, samk::transpose_count(n, M_colptr, M_rowind, nnz, t.rowcount, s));
+    HIP_TRY(ctx, samk::scan_counts(t.rowcount, n, t.off, T_rowptr, nullptr, t.stemp, s));
+    HIP_TRY(ctx, samk::transpose_fill(n, M_colptr, M_rowind, T_rowptr, t.cursor, T_colind, T_perm, s));
     HIP_TRY(ctx, samk::transpose_sort_rows(n, T_rowptr, T_colind, T_perm, s));
-    HIP_TRY(ctx, hipStreamSynchronize(s));
     return SAM_OK;
 }
 
@@ -789,10 +949,6 @@ sam_status sam_apply(sam_ctx* ctx, int32_t n, const int32_t* T_rowptr, const int
     HIP_TRY(ctx, samk::spmv_rows(n, T_rowptr, T_colind, T_perm, M_val, prec == SAM_PREC_F32_REFINE, x, y, S(stream)));
     return SAM_OK;
 }
-
-}  // extern "C"
-
-extern "C" {
 
 sam_status sam_build_weighted(sam_plan* plan, const double* Ak_val, const double* A0_val, const double* w, double mu,
                               sam_precision prec, void* M_val, double* col_res2, double* res2, sam_stream_t stream) {
@@ -829,19 +985,13 @@ std::vector<const NumericVariant*> menu_subset(int prec, int weighted, const int
 
 sam_status plan_select(sam_plan* pl, int prec, const std::vector<const NumericVariant*>& vars, hipStream_t s) {
     sam_ctx* ctx = pl->ctx;
-    const int n = pl->n;
-    const size_t need = align256(samk::bucket_temp_bytes(n)) + 512;
-    HIP_TRY(ctx, grow(ctx->ws, need));
-    Carve cv(ctx->ws.p);
-    void* btemp = cv.take<char>(samk::bucket_temp_bytes(n));
-    int* flag = cv.take<int>(4);
     Combo& cb = pl->combo[prec][0];
     const std::vector<const NumericVariant*> previous = cb.variants;
-    sam_status st = plan_combo_with(pl, prec, 0, vars, btemp, flag, s);
+    sam_status st = plan_combo_with(pl, prec, 0, vars, s);
     if (st) return st;
     if (!cb.ok) {
         const std::string why = cb.why;
-        st = plan_combo_with(pl, prec, 0, previous, btemp, flag, s);
+        st = plan_combo_with(pl, prec, 0, previous, s);
         if (st) return st;
         return fail(ctx, SAM_ERR_UNSUPPORTED, "selection rejected: %s", why.c_str());
     }

@@ -62,6 +62,9 @@ hipError_t expand_slots(int n, const int* P_cp, const int* P_cnt, const int* P_r
 // Per column j: E_j = sum_{l in J_j} nnz(A_k(:,l)).
 hipError_t plan_gather_count(int n, const int* S_cp, const int* S_ri, const int* Ak_cp,
                              int* counts, hipStream_t s);
+// *total (device, preset by the caller) += sum_j E_j.
+hipError_t plan_gather_total(int n, const int* S_cp, const int* S_ri, const int* Ak_cp,
+                             unsigned long long* total, hipStream_t s);
 // Per column j: nI[j] = |I_j|, positions of the gathered A_k entries (posA,
 // at eoff[j]) and of the A_0(:,j) entries (posB aligned with A_0's entries,
 // 0xFF outside I_j).  Columns with |I_j| > 255 get nI = |I_j| and no
@@ -111,6 +114,8 @@ hipError_t residual_columns(int n, const int* Ak_cp, const int* Ak_ri, const dou
                             double* col_out, unsigned long long* status, hipStream_t s);
 
 // ----------------------------------------------------------------- apply
+// p[0 .. count) = v (a kernel, so that graph captures record no memset node)
+hipError_t fill_i32(int* p, int64_t count, int v, hipStream_t s);
 // queue = 0..n-1 and bstart = {0, n}: every column in bucket 0
 hipError_t identity_queue(int n, int* queue, int* bstart, hipStream_t s);
 hipError_t transpose_count(int n, const int* cp, const int* ri, int64_t nnz, int* rowcount,

@@ -31,28 +31,29 @@ struct sam_seq {
     const int *A0_cp = nullptr, *A0_ri = nullptr, *Ak_cp = nullptr, *Ak_ri = nullptr;
     const double* A0_val = nullptr;
     int nnzA = 0, nnzA0 = 0;
+    // caller memory holding everything below
+    void* mem = nullptr;
+    size_t mem_bytes = 0;
     // structural pattern (the pattern of every map in static mode, the bound
     // otherwise) and its plan
-    DevBuf S_cp, S_ri;
+    int *S_cp = nullptr, *S_ri = nullptr;
     int64_t nnzS = 0;
     PatternLevels levels;          // structural level sizes, longest columns, column pointers
     sam_plan* plan = nullptr;
     // replanning mode: every level of the pattern is written into slots laid
-    // out like the structural level (lev_cp, p arrays of n+1), with its
-    // column lengths beside it; only the final S_k is compacted (Sk_cp/Sk_ri)
+    // out like the structural level (levels.cp, p arrays of n+1), with its
+    // column lengths beside it; only the final S_k is compacted (Sk_cp/Sk_ri).
     // kBranches sets of scratch and plan arrays: the symbolic work of the
     // next sources (set (k+1) % kBranches, ...) runs while the numeric build
     // of source k (set k % kBranches) still reads its plan.
     struct Scratch {
-        sam_plan dplan;            // views into dyn
+        sam_plan dplan;            // views into the sequence memory
         int *B_ri = nullptr, *B_cnt = nullptr, *L_ri[2] = {nullptr, nullptr}, *L_cnt[2] = {nullptr, nullptr},
             *F_ri = nullptr, *F_cnt = nullptr;
         int64_t* off = nullptr;
         void *stemp = nullptr, *btemp = nullptr;
         double* D = nullptr;
     };
-    DevBuf dyn;
-    DevBuf lev_cp;
     Scratch part[kBranches];
     std::vector<int*> Sk_cp, Sk_ri;
     // graph: source k runs on branch k mod kBranches, branch 0 being the
@@ -134,7 +135,7 @@ sam_status enqueue_symbolic(sam_seq* q, int k, sam_seq::Scratch& R, const double
     const int n = q->n;
     const samk::SparsifySpec sp = to_sp(&q->spec);
     const int p = q->spec.power;
-    const int* lcp = (const int*)q->lev_cp.p;
+    const int* lcp = q->levels.cp;
     auto level_cp = [&](int lev) { return lcp + (size_t)lev * (n + 1); };
     int* Scp = q->Sk_cp[k];
     int* Sri = q->Sk_ri[k];
@@ -210,16 +211,79 @@ sam_status enqueue_run(sam_seq* q, const double* const* vals, void* const* M, do
     return SAM_OK;
 }
 
-}  // namespace
+// Sizes that fix a sequence's memory layout: the structural pattern's level
+// sizes (from its count), and the bound nnz(S) x longest column of A_k for
+// the gathered entries of a plan on it.
+struct SeqDims {
+    int n = 0, p = 1, nnzA = 0, nnzA0 = 0, longest = 0, n_src = 0, partcap = 0;
+    bool replan = false;
+    int64_t nnzS = 0, Ebound = 0;
+    std::vector<int64_t> lev_nnz;
+};
 
-extern "C" {
+// Layout of a sequence's memory (q == null: measure only): the structural
+// pattern's workspace (creation only), the structural S and its level column
+// pointers, the plan, then (replanning) the per-source patterns and the
+// scratch sets.  Returns the plan region through plan_mem / plan_bytes_out.
+size_t seq_layout(Carve& cv, const SeqDims& d, sam_seq* q, PatternWs* pw, void** plan_mem, size_t* plan_sz) {
+    const int n = d.n;
+    pattern_ws_layout(cv, n, d.nnzA, d.longest, d.p, pw);
+    int* S_cp = cv.take<int>((size_t)n + 1);
+    int* S_ri = cv.take<int>((size_t)d.nnzS);
+    int* lev = cv.take<int>((size_t)d.p * ((size_t)n + 1));
+    const size_t pb = plan_bytes(n, d.Ebound, d.nnzA0, d.partcap);
+    void* pm = cv.take<char>(pb);
+    if (plan_mem) *plan_mem = pm;
+    if (plan_sz) *plan_sz = pb;
+    if (q) {
+        q->S_cp = S_cp;
+        q->S_ri = S_ri;
+        q->levels.cp = lev;
+    }
+    if (!d.replan) return cv.off;
+    auto lev_nnz = [&](int l) { return std::max<int64_t>(d.lev_nnz[(size_t)l], 1); };
+    int64_t mid_max = 1;
+    for (int l = 1; l + 1 < d.p; ++l) mid_max = std::max(mid_max, lev_nnz(l));
+    for (int k = 0; k < d.n_src; ++k) {
+        int* cp = cv.take<int>((size_t)n + 1);
+        int* ri = cv.take<int>((size_t)d.nnzS);
+        if (q) {
+            q->Sk_cp.push_back(cp);
+            q->Sk_ri.push_back(ri);
+        }
+    }
+    for (int b = 0; b < kBranches; ++b) {
+        sam_seq::Scratch dummy;
+        sam_seq::Scratch& R = q ? q->part[b] : dummy;
+        R.off = cv.take<int64_t>((size_t)n + 1);
+        R.stemp = cv.take<char>(samk::scan_temp_bytes(n));
+        R.btemp = cv.take<char>(samk::bucket_temp_bytes(n));
+        R.D = cv.take<double>((size_t)n);
+        R.B_ri = cv.take<int>((size_t)lev_nnz(0));
+        R.B_cnt = cv.take<int>((size_t)n);
+        for (int i = 0; i < 2; ++i) {
+            R.L_ri[i] = cv.take<int>((size_t)mid_max);
+            R.L_cnt[i] = cv.take<int>((size_t)n);
+        }
+        R.F_ri = cv.take<int>((size_t)lev_nnz(d.p - 1));
+        R.F_cnt = cv.take<int>((size_t)n);
+        sam_plan& pl = R.dplan;
+        pl.nI = cv.take<int>((size_t)n);
+        pl.posA = cv.take<unsigned char>((size_t)d.Ebound);
+        pl.posB = cv.take<unsigned char>((size_t)d.nnzA0);
+        Combo& cb = pl.combo[q ? q->prec : 0][0];
+        cb.queue = cv.take<int>((size_t)n);
+        cb.bstart = cv.take<int>(64);
+        pl.colbuf = cv.take<double>((size_t)n);
+        pl.partcap = d.partcap;
+        pl.partbuf = cv.take<double>((size_t)d.partcap);
+        pl.rtemp = cv.take<char>(samk::reduce_temp_bytes(std::max(n, d.partcap)));
+    }
+    return cv.off;
+}
 
-sam_status sam_sequence_create(sam_ctx* ctx, const sam_csc* A0, const sam_csc* Ak_struct, const sam_pattern_spec* spec,
-                               int32_t n_src, sam_precision prec, int32_t replan_each_run, sam_seq** out,
-                               sam_stream_t stream) {
-    if (check_ctx(ctx)) return SAM_ERR_ARG;
-    if (!out) return fail(ctx, SAM_ERR_ARG, "seq is NULL");
-    *out = nullptr;
+sam_status seq_args(sam_ctx* ctx, const sam_csc* A0, const sam_csc* Ak_struct, const sam_pattern_spec* spec,
+                    int32_t n_src, sam_precision prec) {
     sam_status st;
     if ((st = check_csc_args(ctx, A0, "A0", true))) return st;
     if ((st = check_csc_args(ctx, Ak_struct, "Ak_struct", false))) return st;
@@ -228,9 +292,85 @@ sam_status sam_sequence_create(sam_ctx* ctx, const sam_csc* A0, const sam_csc* A
     if (n_src < 1) return fail(ctx, SAM_ERR_ARG, "n_src must be >= 1 (got %d)", n_src);
     if (A0->n == 0) return fail(ctx, SAM_ERR_ARG, "empty matrices (n = 0): nothing to map");
     if (!prec_ok(prec)) return fail(ctx, SAM_ERR_ARG, "unknown precision %d", (int)prec);
+    if (Ak_struct->nnz == 0 || A0->nnz == 0)
+        return fail(ctx, SAM_ERR_ARG, "Ak and A0 must have stored entries (a nonsingular source has at least n)");
+    return SAM_OK;
+}
+
+// Validates both structures and counts the structural pattern
+// S((I + S(A_k))^p) in the pattern workspace w: fills d (all but the
+// layout's own choices) and res.
+sam_status seq_count(sam_ctx* ctx, const sam_csc* A0, const sam_csc* Ak_struct, const sam_pattern_spec* spec,
+                     int32_t n_src, int32_t replan, const PatternWs& w, PatternLevels* levels, SeqDims* d,
+                     PatternResult* res, hipStream_t s) {
+    sam_status st;
+    const int n = A0->n;
+    if ((st = validate_csc(ctx, n, A0->nnz, A0->colptr, A0->rowind, "A0", s))) return st;
+    if ((st = validate_csc(ctx, n, Ak_struct->nnz, Ak_struct->colptr, Ak_struct->rowind, "Ak_struct", s))) return st;
+    sam_pattern_spec structural = *spec;
+    structural.kind = SAM_SPARSIFY_NONE;
+    sam_csc skel = *Ak_struct;
+    skel.val = nullptr;
+    if ((st = compute_pattern(ctx, &skel, &structural, w, res, s, levels))) return st;
+    d->nnzS = res->nnz;
+    d->lev_nnz = levels->nnz;
+    d->Ebound = std::max<int64_t>(d->nnzS * (int64_t)d->longest, 1);
+    d->n_src = n_src;
+    d->replan = replan != 0 || spec->kind != SAM_SPARSIFY_NONE;
+    return SAM_OK;
+}
+
+sam_status seq_dims_base(sam_ctx* ctx, const sam_csc* A0, const sam_csc* Ak_struct, const sam_pattern_spec* spec,
+                         SeqDims* d, hipStream_t s) {
+    d->n = A0->n;
+    d->p = spec->power;
+    d->nnzA = Ak_struct->nnz;
+    d->nnzA0 = A0->nnz;
+    d->partcap = partial_capacity(ctx);
+    return host_colptr(ctx, Ak_struct->colptr, d->n, Ak_struct->nnz, "Ak_struct", &d->longest, s);
+}
+
+}  // namespace
+
+extern "C" {
+
+sam_status sam_sequence_size(sam_ctx* ctx, const sam_csc* A0, const sam_csc* Ak_struct, const sam_pattern_spec* spec,
+                             int32_t n_src, sam_precision prec, int32_t replan_each_run, void* ws, size_t ws_bytes,
+                             size_t* bytes, sam_stream_t stream) {
+    if (check_ctx(ctx)) return SAM_ERR_ARG;
+    sam_status st;
+    if ((st = seq_args(ctx, A0, Ak_struct, spec, n_src, prec))) return st;
+    if (!bytes) return fail(ctx, SAM_ERR_ARG, "bytes is NULL");
+    if ((st = need_device(ctx))) return st;
+    hipStream_t s = S(stream);
+    SeqDims d;
+    if ((st = seq_dims_base(ctx, A0, Ak_struct, spec, &d, s))) return st;
+    Carve wc(ws);
+    PatternWs w;
+    pattern_ws_layout(wc, d.n, d.nnzA, d.longest, d.p, &w);
+    if ((st = check_ws(ctx, ws, ws_bytes, wc.off, "pattern workspace"))) return st;
+    PatternLevels levels;
+    PatternResult res;
+    if ((st = seq_count(ctx, A0, Ak_struct, spec, n_src, replan_each_run, w, &levels, &d, &res, s))) return st;
+    Carve cv(nullptr);
+    *bytes = seq_layout(cv, d, nullptr, nullptr, nullptr, nullptr);
+    return SAM_OK;
+}
+
+sam_status sam_sequence_create(sam_ctx* ctx, const sam_csc* A0, const sam_csc* Ak_struct, const sam_pattern_spec* spec,
+                               int32_t n_src, sam_precision prec, int32_t replan_each_run, void* mem, size_t mem_bytes,
+                               sam_seq** out, sam_stream_t stream) {
+    if (check_ctx(ctx)) return SAM_ERR_ARG;
+    if (!out) return fail(ctx, SAM_ERR_ARG, "seq is NULL");
+    *out = nullptr;
+    sam_status st;
+    if ((st = seq_args(ctx, A0, Ak_struct, spec, n_src, prec))) return st;
+    if ((st = check_ws(ctx, mem, mem_bytes, 1, "sequence memory"))) return st;
     if ((st = need_device(ctx))) return st;
     hipStream_t s = S(stream);
     const int n = A0->n;
+    SeqDims d;
+    if ((st = seq_dims_base(ctx, A0, Ak_struct, spec, &d, s))) return st;
 
     sam_seq* q = new (std::nothrow) sam_seq();
     if (!q) return fail(ctx, SAM_ERR_NOMEM, "host allocation failed");
@@ -239,7 +379,6 @@ sam_status sam_sequence_create(sam_ctx* ctx, const sam_csc* A0, const sam_csc* A
     q->n_src = n_src;
     q->prec = prec == SAM_PREC_F32_REFINE ? 1 : 0;
     q->spec = *spec;
-    q->replan = replan_each_run != 0 || spec->kind != SAM_SPARSIFY_NONE;
     q->A0_cp = A0->colptr;
     q->A0_ri = A0->rowind;
     q->A0_val = A0->val;
@@ -247,106 +386,71 @@ sam_status sam_sequence_create(sam_ctx* ctx, const sam_csc* A0, const sam_csc* A
     q->Ak_cp = Ak_struct->colptr;
     q->Ak_ri = Ak_struct->rowind;
     q->nnzA = Ak_struct->nnz;
+    q->mem = mem;
+    q->mem_bytes = mem_bytes;
     auto bail = [&](sam_status code) {
         sam_sequence_destroy(q);
         return code;
     };
 
-    // structural pattern: S((I + S(A_k))^p), the bound of every sparsified one
-    sam_pattern_spec structural = *spec;
-    structural.kind = SAM_SPARSIFY_NONE;
-    sam_csc skel = *Ak_struct;
-    skel.val = nullptr;
-    q->levels.cp = &q->lev_cp;
-    if ((st = compute_pattern(ctx, &skel, &structural, q->S_cp, q->S_ri, &q->nnzS, s, &q->levels))) return bail(st);
-    if ((st = sam_plan_create(ctx, &skel, A0, (const int*)q->S_cp.p, (const int*)q->S_ri.p, q->nnzS, &q->plan, stream)))
-        return bail(st);
+    // the structural pattern S((I + S(A_k))^p), the bound of every
+    // sparsified one, counted in the workspace at the start of the memory
+    Carve wc(mem);
+    PatternWs w;
+    pattern_ws_layout(wc, n, d.nnzA, d.longest, d.p, &w);
+    if (wc.off > mem_bytes) return bail(fail(ctx, SAM_ERR_ARG, "sequence memory: %zu bytes given, more needed", mem_bytes));
+    PatternResult res;
+    // level column pointers: counted once without a copy target, then the
+    // layout is known and the count is repeated with the copies
+    PatternLevels probe;
+    if ((st = seq_count(ctx, A0, Ak_struct, spec, n_src, replan_each_run, w, &probe, &d, &res, s))) return bail(st);
+    q->replan = d.replan;
+    Carve cv(mem);
+    void* plan_mem = nullptr;
+    size_t plan_sz = 0;
+    const size_t need = seq_layout(cv, d, q, nullptr, &plan_mem, &plan_sz);
+    if (need > mem_bytes)
+        return bail(fail(ctx, SAM_ERR_ARG, "sequence memory: %zu bytes given, %zu needed", mem_bytes, need));
+    {
+        sam_pattern_spec structural = *spec;
+        structural.kind = SAM_SPARSIFY_NONE;
+        sam_csc skel = *Ak_struct;
+        skel.val = nullptr;
+        if ((st = compute_pattern(ctx, &skel, &structural, w, &res, s, &q->levels))) return bail(st);
+        if (res.nnz != d.nnzS) return bail(fail(ctx, SAM_ERR_HIP, "structural pattern changed between two counts"));
+        if ((st = pattern_fill(ctx, n, res, q->S_cp, q->S_ri, s))) return bail(st);
+        q->nnzS = res.nnz;
+    }
+    {
+        sam_csc skel = *Ak_struct;
+        skel.val = nullptr;
+        sam_plan* pl = new (std::nothrow) sam_plan();
+        if (!pl) return bail(fail(ctx, SAM_ERR_NOMEM, "host allocation failed"));
+        q->plan = pl;
+        if ((st = plan_init(ctx, pl, &skel, A0, q->S_cp, q->S_ri, q->nnzS, plan_mem, plan_sz, s))) return bail(st);
+        if (pl->E > d.Ebound) return bail(fail(ctx, SAM_ERR_HIP, "gathered entries exceed their bound"));
+    }
     if (!q->plan->combo[q->prec][0].ok)
         return bail(fail(ctx, SAM_ERR_UNSUPPORTED, "%s", q->plan->combo[q->prec][0].why.c_str()));
 
     if (q->replan) {
-        // slot sizes: the structural level sizes (level 0 is B, the last is S)
-        const int p = std::max(spec->power, 1);
-        if ((int)q->levels.nnz.size() < p) {   // n = 0
-            q->levels.nnz.resize((size_t)p, 0);
-            q->levels.maxcol.resize((size_t)p, 0);
-        }
-        auto lev_nnz = [&](int lev) { return std::max<int64_t>(q->levels.nnz[(size_t)lev], 1); };
-        int64_t mid_max = 1;
-        for (int lev = 1; lev + 1 < p; ++lev) mid_max = std::max(mid_max, lev_nnz(lev));
-        const int64_t E = std::max<int64_t>(q->plan->E, 1);
-        size_t need_set = 0;   // one scratch set
-        auto add = [&](size_t b) { need_set += align256(b); };
-        add((size_t)(n + 1) * 8);                // off
-        add(samk::scan_temp_bytes(n));           // stemp
-        add(samk::bucket_temp_bytes(n));         // btemp
-        add((size_t)n * 8);                      // D
-        add((size_t)lev_nnz(0) * 4);             // B slots
-        add((size_t)n * 4);                      // B lengths
-        for (int i = 0; i < 2; ++i) {
-            add((size_t)mid_max * 4);            // intermediate level slots
-            add((size_t)n * 4);
-        }
-        add((size_t)lev_nnz(p - 1) * 4);         // final level slots
-        add((size_t)n * 4);
-        add((size_t)n * 4);                      // nI
-        add((size_t)E);                          // posA
-        add((size_t)std::max(q->nnzA0, 1));      // posB
-        add((size_t)n * 4);                      // queue
-        add(64 * 4);                             // bstart
-        add((size_t)n * 8);                      // colbuf
-        add((size_t)partial_capacity(ctx) * 8);  // partial sums
-        add(samk::reduce_temp_bytes(std::max(n, partial_capacity(ctx))));
-        const size_t need_src = (size_t)n_src * (align256((size_t)(n + 1) * 4) +
-                                                 align256((size_t)std::max<int64_t>(q->nnzS, 1) * 4));
-        const size_t need = kBranches * need_set + need_src;
-        hipError_t he = grow(q->dyn, need + 4096);
-        if (he != hipSuccess) return bail(fail(ctx, SAM_ERR_NOMEM, "sequence buffers (%zu bytes): %s", need,
-                                               hipGetErrorString(he)));
-        Carve cv(q->dyn.p);
-        for (int k = 0; k < n_src; ++k) {
-            q->Sk_cp.push_back(cv.take<int>(n + 1));
-            q->Sk_ri.push_back(cv.take<int>((size_t)std::max<int64_t>(q->nnzS, 1)));
-        }
         for (sam_seq::Scratch& R : q->part) {
-            R.off = cv.take<int64_t>(n + 1);
-            R.stemp = cv.take<char>(samk::scan_temp_bytes(n));
-            R.btemp = cv.take<char>(samk::bucket_temp_bytes(n));
-            R.D = cv.take<double>(n);
-            R.B_ri = cv.take<int>((size_t)lev_nnz(0));
-            R.B_cnt = cv.take<int>(n);
-            for (int i = 0; i < 2; ++i) {
-                R.L_ri[i] = cv.take<int>((size_t)mid_max);
-                R.L_cnt[i] = cv.take<int>(n);
-            }
-            R.F_ri = cv.take<int>((size_t)lev_nnz(p - 1));
-            R.F_cnt = cv.take<int>(n);
-            sam_plan& d = R.dplan;
-            d.ctx = ctx;
-            d.n = n;
-            d.nnzA = q->nnzA;
-            d.nnzA0 = q->nnzA0;
-            d.nnzS = q->nnzS;
-            d.E = q->plan->E;
-            d.max_cols = q->plan->max_cols;
-            d.max_len_A = q->plan->max_len_A;
-            d.Ak_cp = q->Ak_cp;
-            d.Ak_ri = q->Ak_ri;
-            d.A0_cp = q->A0_cp;
-            d.A0_ri = q->A0_ri;
-            d.nI = cv.take<int>(n);
-            d.eoff = q->plan->eoff;   // structural offsets of the gathered entries
-            d.posA = cv.take<unsigned char>((size_t)E);
-            d.posB = cv.take<unsigned char>((size_t)std::max(q->nnzA0, 1));
-            Combo& cb = d.combo[q->prec][0];
-            cb.queue = cv.take<int>(n);
-            cb.bstart = cv.take<int>(64);
-            cb.ok = true;
-            d.colbuf = cv.take<double>(n);
-            d.partcap = partial_capacity(ctx);
-            d.partbuf = cv.take<double>((size_t)d.partcap);
-            d.rtemp = cv.take<char>(samk::reduce_temp_bytes(std::max(n, d.partcap)));
-            d.device_counts = true;
+            sam_plan& dp = R.dplan;
+            dp.ctx = ctx;
+            dp.n = n;
+            dp.nnzA = q->nnzA;
+            dp.nnzA0 = q->nnzA0;
+            dp.nnzS = q->nnzS;
+            dp.E = q->plan->E;
+            dp.max_cols = q->plan->max_cols;
+            dp.max_len_A = q->plan->max_len_A;
+            dp.Ak_cp = q->Ak_cp;
+            dp.Ak_ri = q->Ak_ri;
+            dp.A0_cp = q->A0_cp;
+            dp.A0_ri = q->A0_ri;
+            dp.eoff = q->plan->eoff;   // structural offsets of the gathered entries
+            dp.combo[q->prec][0].ok = true;
+            dp.device_counts = true;
         }
         for (hipStream_t& x : q->side)
             if (hipStreamCreateWithFlags(&x, hipStreamNonBlocking) != hipSuccess)
@@ -359,8 +463,8 @@ sam_status sam_sequence_create(sam_ctx* ctx, const sam_csc* A0, const sam_csc* A
     if (hipStreamCreateWithFlags(&q->cap, hipStreamNonBlocking) != hipSuccess)
         return bail(fail(ctx, SAM_ERR_HIP, "stream creation failed"));
     if (q->replan) {
-        sam_status st = set_bounds(q, q->cap);
-        if (st) return bail(st);
+        sam_status st2 = set_bounds(q, s);
+        if (st2) return bail(st2);
     }
     *out = q;
     return SAM_OK;
@@ -378,11 +482,7 @@ sam_status sam_sequence_destroy(sam_seq* q) {
         if (x) (void)hipStreamDestroy(x);
     for (hipEvent_t e : q->ev)
         if (e) (void)hipEventDestroy(e);
-    if (q->plan) sam_plan_destroy(q->plan);
-    release(q->S_cp);
-    release(q->S_ri);
-    release(q->dyn);
-    release(q->lev_cp);
+    delete q->plan;   // host record: its arrays live in the sequence memory
     delete q;
     return SAM_OK;
 }
@@ -403,8 +503,8 @@ sam_status sam_sequence_pattern(sam_seq* q, int32_t k, int32_t* S_colptr, int32_
     sam_status st = need_device(ctx);
     if (st) return st;
     hipStream_t s = S(stream);
-    const int* cp = q->replan ? q->Sk_cp[k] : (const int*)q->S_cp.p;
-    const int* ri = q->replan ? q->Sk_ri[k] : (const int*)q->S_ri.p;
+    const int* cp = q->replan ? q->Sk_cp[k] : q->S_cp;
+    const int* ri = q->replan ? q->Sk_ri[k] : q->S_ri;
     int last = 0;
     HIP_TRY(ctx, hipMemcpyAsync(&last, cp + q->n, sizeof(int), hipMemcpyDeviceToHost, s));
     HIP_TRY(ctx, hipStreamSynchronize(s));

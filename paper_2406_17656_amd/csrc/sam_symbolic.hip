@@ -711,6 +711,30 @@ hipError_t plan_gather_count(int n, const int* S_cp, const int* S_ri, const int*
     return hipGetLastError();
 }
 
+// *total += sum_j sum_{l in S(:,j)} nnz(A_k(:,l)): a column per thread, the
+// wave's sum added once (integer, so the order does not matter).
+__global__ void k_gather_total(int n, const int* S_cp, const int* S_ri, const int* Ak_cp,
+                               unsigned long long* total) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    long long s = 0;
+    if (j < n) {
+        for (int e = S_cp[j]; e < S_cp[j + 1]; ++e) {
+            const int l = S_ri[e];
+            if (l >= 0 && l < n) s += Ak_cp[l + 1] - Ak_cp[l];
+        }
+    }
+    for (int d = 32; d >= 1; d >>= 1) s += __shfl_xor(s, d);
+    if ((threadIdx.x & 63) == 0 && s != 0) atomicAdd(total, (unsigned long long)s);
+}
+
+hipError_t plan_gather_total(int n, const int* S_cp, const int* S_ri, const int* Ak_cp, unsigned long long* total,
+                             hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gather_total, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s, n, S_cp, S_ri, Ak_cp,
+                       total);
+    return hipGetLastError();
+}
+
 // Row set I_j of every column as a bitmap sweep; every gathered A_k entry (in
 // the order: entries of A_k(:, J_j[0]), then of A_k(:, J_j[1]), ...) gets its
 // rank inside I_j, and so does every entry of A_0(:, j) (0xFF when its row is

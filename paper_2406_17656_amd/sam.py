@@ -34,6 +34,21 @@ def _ptr(t):
     return None if t is None else ctypes.c_void_p(t.data_ptr())
 
 
+def _buf(nbytes: int, device) -> torch.Tensor:
+    """Device memory for the library (torch allocations are 512-byte aligned;
+    freed tensors return to torch's pool in stream order, after the kernels
+    already enqueued on the same stream)."""
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+
+
+def _size(fn, *args) -> int:
+    nb = ctypes.c_size_t()
+    st = fn(*args, ctypes.byref(nb))
+    if st != C.SAM_OK:
+        raise SamError(st, fn.__name__)
+    return nb.value
+
+
 def _prec(p) -> int:
     if isinstance(p, str):
         return PREC[p]
@@ -124,14 +139,18 @@ class Context:
     def pattern(self, Ak: DeviceCSC, power=1, kind="none", **kw):
         s = Ak.struct()
         sp = _spec(kind, power, **kw)
-        nnz = ctypes.c_int64()
-        self.check(self.lib.sam_pattern_count(self.h, ctypes.byref(s), ctypes.byref(sp),
-                                              ctypes.byref(nnz), self.stream()))
         dev = Ak.colptr.device
+        nb = ctypes.c_size_t()
+        self.check(self.lib.sam_pattern_workspace_size(self.h, ctypes.byref(s), ctypes.byref(sp), ctypes.byref(nb),
+                                                       self.stream()))
+        ws = _buf(nb.value, dev)
+        nnz = ctypes.c_int64()
+        self.check(self.lib.sam_pattern_count(self.h, ctypes.byref(s), ctypes.byref(sp), _ptr(ws), nb.value,
+                                              ctypes.byref(nnz), self.stream()))
         cp = torch.empty(Ak.n + 1, dtype=torch.int32, device=dev)
         ri = torch.empty(max(nnz.value, 1), dtype=torch.int32, device=dev)
-        self.check(self.lib.sam_pattern_fill(self.h, ctypes.byref(s), ctypes.byref(sp), _ptr(cp),
-                                             _ptr(ri), self.stream()))
+        self.check(self.lib.sam_pattern_fill(self.h, ctypes.byref(s), ctypes.byref(sp), _ptr(ws), nb.value,
+                                             _ptr(cp), _ptr(ri), self.stream()))
         return cp, ri[:nnz.value]
 
     # -- build (Section 2)
@@ -146,9 +165,13 @@ class Context:
         cols = torch.empty(max(Ak.n, 1), dtype=torch.float64, device=dev) if want_cols else None
         res2 = torch.empty(1, dtype=torch.float64, device=dev)
         a, b = Ak.struct(), A0.struct()
+        nb = ctypes.c_size_t()
+        self.check(self.lib.sam_workspace_size(self.h, ctypes.byref(a), ctypes.byref(b), _ptr(S_colptr),
+                                               _ptr(S_rowind), nnz, p, ctypes.byref(nb), self.stream()))
+        ws = _buf(nb.value, dev)
         self.check(self.lib.sam_build(self.h, ctypes.byref(a), ctypes.byref(b), _ptr(S_colptr),
                                       _ptr(S_rowind), nnz, p, _ptr(M), _ptr(cols), _ptr(res2),
-                                      self.stream()))
+                                      _ptr(ws), nb.value, self.stream()))
         return M[:nnz], (cols[:Ak.n] if cols is not None else None), res2
 
     # -- residual (Section 2 eq. res)
@@ -158,9 +181,11 @@ class Context:
         res2 = torch.empty(1, dtype=torch.float64, device=dev)
         a02 = torch.empty(1, dtype=torch.float64, device=dev)
         a, b = Ak.struct(), A0.struct()
+        nb = _size(self.lib.sam_residual_workspace_size, Ak.n, A0.nnz)
+        ws = _buf(nb, dev)
         self.check(self.lib.sam_residual(self.h, ctypes.byref(a), ctypes.byref(b), _ptr(M_colptr),
                                          _ptr(M_rowind), int(M_rowind.numel()), _ptr(M_val), p,
-                                         _ptr(res2), _ptr(a02), self.stream()))
+                                         _ptr(res2), _ptr(a02), _ptr(ws), nb, self.stream()))
         return res2, a02
 
     # -- y = M x
@@ -170,8 +195,10 @@ class Context:
         rp = torch.empty(n + 1, dtype=torch.int32, device=dev)
         ci = torch.empty(max(nnz, 1), dtype=torch.int32, device=dev)
         pm = torch.empty(max(nnz, 1), dtype=torch.int32, device=dev)
+        nb = _size(self.lib.sam_apply_workspace_size, n)
+        ws = _buf(nb, dev)
         self.check(self.lib.sam_apply_prepare(self.h, n, _ptr(M_colptr), _ptr(M_rowind), nnz, _ptr(rp),
-                                              _ptr(ci), _ptr(pm), self.stream()))
+                                              _ptr(ci), _ptr(pm), _ptr(ws), nb, self.stream()))
         return rp, ci, pm
 
     def apply(self, T, M_val, x, prec="f64", y=None):
@@ -201,15 +228,21 @@ class Context:
         cp = torch.empty(n + 1, dtype=torch.int32, device=dev)
         ri = torch.empty(max(nnz, 1), dtype=torch.int32, device=dev)
         out = ctypes.c_int64()
+        nb = _size(self.lib.sam_topk_workspace_size, n)
+        ws = _buf(nb, dev)
         self.check(self.lib.sam_pattern_topk(self.h, n, _ptr(S_colptr), _ptr(S_rowind), nnz, _ptr(w), _ptr(grad),
-                                             int(k), _ptr(cp), _ptr(ri), ctypes.byref(out), self.stream()))
+                                             int(k), _ptr(cp), _ptr(ri), ctypes.byref(out), _ptr(ws), nb,
+                                             self.stream()))
         return cp, ri[:out.value]
 
     def penalty_scale(self, Ak: DeviceCSC) -> float:
         """sam_penalty_scale: ||A_k||_F^2 / n."""
         a = Ak.struct()
         mu = ctypes.c_double()
-        self.check(self.lib.sam_penalty_scale(self.h, ctypes.byref(a), ctypes.byref(mu), self.stream()))
+        nb = _size(self.lib.sam_penalty_workspace_size, Ak.nnz)
+        ws = _buf(nb, Ak.colptr.device)
+        self.check(self.lib.sam_penalty_scale(self.h, ctypes.byref(a), ctypes.byref(mu), _ptr(ws), nb,
+                                              self.stream()))
         return mu.value
 
     # -- sequence
@@ -228,10 +261,16 @@ class Plan:
         self.S_colptr, self.S_rowind = S_colptr, S_rowind
         self.n = Ak.n
         self.nnz_S = int(S_rowind.numel())
+        self._bwd = None                   # backward workspace, prepared on first use
         h = ctypes.c_void_p()
         a, b = Ak.struct(), A0.struct()
+        nb = ctypes.c_size_t()
+        ctx.check(ctx.lib.sam_plan_size(ctx.h, ctypes.byref(a), ctypes.byref(b), _ptr(S_colptr), _ptr(S_rowind),
+                                        self.nnz_S, ctypes.byref(nb), ctx.stream()))
+        self.mem = _buf(nb.value, Ak.colptr.device)   # owned by the plan until close()
         ctx.check(ctx.lib.sam_plan_create(ctx.h, ctypes.byref(a), ctypes.byref(b), _ptr(S_colptr),
-                                          _ptr(S_rowind), self.nnz_S, ctypes.byref(h), ctx.stream()))
+                                          _ptr(S_rowind), self.nnz_S, _ptr(self.mem), nb.value, ctypes.byref(h),
+                                          ctx.stream()))
         self.h = h
 
     def close(self):
@@ -239,6 +278,8 @@ class Plan:
             torch.cuda.synchronize(self.ctx.device)
             self.ctx.lib.sam_plan_destroy(self.h)
             self.h = None
+            self.mem = None
+            self._bwd = None
 
     def __del__(self):
         try:
@@ -297,9 +338,16 @@ class Plan:
         gA0 = torch.empty_like(A0_val)
         gw = torch.empty(max(self.nnz_S, 1), dtype=torch.float64, device=dev) if want_gw else None
         loss = torch.empty(1, dtype=torch.float64, device=dev)
+        if self._bwd is None:
+            nb = ctypes.c_size_t()
+            self.ctx.check(self.ctx.lib.sam_backward_workspace_size(self.h, ctypes.byref(nb)))
+            ws = _buf(nb.value, dev)
+            self.ctx.check(self.ctx.lib.sam_backward_prepare(self.h, _ptr(ws), nb.value, self.ctx.stream()))
+            self._bwd = (ws, nb.value)
+        ws, nb = self._bwd
         self.ctx.check(self.ctx.lib.sam_backward(self.h, _ptr(Ak_val), _ptr(A0_val), _ptr(w), float(mu),
                                                  float(dL), p, _ptr(gAk), _ptr(gA0), _ptr(gw), _ptr(loss),
-                                                 self.ctx.stream()))
+                                                 _ptr(ws), nb, self.ctx.stream()))
         return gAk, gA0, (gw[:self.nnz_S] if gw is not None else None), loss
 
 
@@ -315,8 +363,19 @@ class Sequence:
         self.spec = spec
         h = ctypes.c_void_p()
         a, b = A0.struct(), Ak_struct.struct()
+        dev = A0.colptr.device
+        replan = 1 if replan_each_run else 0
+        nb = ctypes.c_size_t()
+        ctx.check(ctx.lib.sam_pattern_workspace_size(ctx.h, ctypes.byref(b), ctypes.byref(spec), ctypes.byref(nb),
+                                                     ctx.stream()))
+        ws = _buf(nb.value, dev)
+        total = ctypes.c_size_t()
+        ctx.check(ctx.lib.sam_sequence_size(ctx.h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(spec), n_src,
+                                            prec, replan, _ptr(ws), nb.value, ctypes.byref(total), ctx.stream()))
+        del ws
+        self.mem = _buf(total.value, dev)   # owned by the sequence until close()
         ctx.check(ctx.lib.sam_sequence_create(ctx.h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(spec),
-                                              n_src, prec, 1 if replan_each_run else 0, ctypes.byref(h),
+                                              n_src, prec, replan, _ptr(self.mem), total.value, ctypes.byref(h),
                                               ctx.stream()))
         self.h = h
         nb = ctypes.c_int64()
@@ -328,6 +387,7 @@ class Sequence:
             torch.cuda.synchronize(self.ctx.device)
             self.ctx.lib.sam_sequence_destroy(self.h)
             self.h = None
+            self.mem = None
 
     def __del__(self):
         try:
