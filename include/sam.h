@@ -301,6 +301,24 @@ sam_status sam_build(sam_ctx* ctx, const sam_csc* Ak, const sam_csc* A0,
                      sam_precision prec, void* M_val, double* col_res2, double* res2,
                      void* ws, size_t ws_bytes, sam_stream_t stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): sam_build
+ * with the plan of the column problems in a fixed 48 MiB device array of the
+ * library instead of a caller workspace.  Each GPU the library runs on holds
+ * one such array until the process ends.  Problems whose plan needs more
+ * (sam_workspace_size > 48 MiB; the 512 x 512 level-2 map needs about
+ * 31 MiB) are refused with SAM_ERR_UNSUPPORTED before any kernel runs.
+ * Arguments, outputs and the synchronising planning are those of sam_build;
+ * the numeric launches read the array until the stream reaches them.  Every
+ * call on a GPU shares that GPU's array, which keeps the last call's
+ * contents: calls on one stream are ordered, but calls that overlap on one
+ * GPU (other streams, threads or contexts) race on it.  Not capturable (the
+ * planning synchronises).  Allocates nothing. */
+sam_status sam_build_noalloc(sam_ctx* ctx, const sam_csc* Ak, const sam_csc* A0,
+                             const int32_t* S_colptr, const int32_t* S_rowind, int64_t nnz_S,
+                             sam_precision prec, void* M_val, double* col_res2, double* res2,
+                             sam_stream_t stream);
+
 /* --------------------------------------------------------------- residual */
 
 /* Bytes of the workspace of sam_residual for order n and nnz(A_0) (host

@@ -74,6 +74,7 @@ SIGNATURES = {
     "sam_build_planned": (c_int32, [P, P, P, c_int32, P, P, P, P]),
     "sam_workspace_size": (c_int32, [P, CSCP, CSCP, P, P, c_int64, c_int32, SZ, P]),
     "sam_build": (c_int32, [P, CSCP, CSCP, P, P, c_int64, c_int32, P, P, P, P, c_size_t, P]),
+    "sam_build_noalloc": (c_int32, [P, CSCP, CSCP, P, P, c_int64, c_int32, P, P, P, P]),
     "sam_residual_workspace_size": (c_int32, [c_int32, c_int32, SZ]),
     "sam_residual": (c_int32, [P, CSCP, CSCP, P, P, c_int64, P, c_int32, P, P, P, c_size_t, P]),
     "sam_apply_workspace_size": (c_int32, [c_int32, SZ]),

@@ -604,6 +604,9 @@ sam_status sam_create(sam_ctx** out, int device) {
             delete ctx;
             return SAM_ERR_NOMEM;
         }
+        // sam_build_noalloc's fixed array: its address on this device (a
+        // failure is kept and reported by that call, which alone needs it)
+        (void)scratch_setup(device);
         ctx->d_status = (unsigned long long*)ctx->block;
         ctx->d_bad = (int*)((char*)ctx->block + 64);
         ctx->d_total = (unsigned long long*)((char*)ctx->block + 128);

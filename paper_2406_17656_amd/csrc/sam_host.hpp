@@ -233,6 +233,9 @@ sam_status plan_select(sam_plan* pl, int prec, const std::vector<const samk::Num
 // Capacity of a plan's partial-sum buffer: every bucket's launch at the
 // largest resident grid of the menu.
 int partial_capacity(const sam_ctx* ctx);
+// Device address of sam_build_noalloc's fixed scratch array on `device`
+// (current), looked up once per device; called by sam_create.
+hipError_t scratch_setup(int device);
 sam_status run_numeric(sam_plan* pl, const double* Ak_val, const double* A0_val, const double* w, double mu, int prec,
                        int weighted, void* M_val, double* col_res2, double* res2, hipStream_t s);
 
