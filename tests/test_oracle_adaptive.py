@@ -50,14 +50,20 @@ def test_topk_brute_force(seed, k):
 
 
 def test_candidate_weights_membership():
+    """Membership by sparse-matrix algebra instead of per-column sets: the
+    entries of S shared with B are where the elementwise product of the two
+    0/1 patterns is nonzero."""
+    import scipy.sparse as sp
     rng = np.random.default_rng(4)
     B = random_pattern(25, 4, rng)
     S = random_pattern(25, 8, rng, base=B)
     w = O.candidate_weights(S, B, 1.0, 0.3)
-    for j in range(S.n):
-        base = set(B.rowind[B.colptr[j]:B.colptr[j + 1]].tolist())
-        for e in range(S.colptr[j], S.colptr[j + 1]):
-            assert w[e] == (1.0 if int(S.rowind[e]) in base else 0.3)
+    Sm = sp.csc_matrix((np.arange(1, S.nnz + 1, dtype=np.float64), S.rowind, S.colptr), shape=(S.n, S.n))
+    Bm = sp.csc_matrix((np.ones(B.nnz), B.rowind, B.colptr), shape=(B.n, B.n))
+    shared = Sm.multiply(Bm).tocsc()
+    expect = np.full(S.nnz, 0.3)
+    expect[shared.data.astype(np.int64) - 1] = 1.0    # the data carry S's entry numbers
+    assert np.array_equal(w, expect)
     assert (w == 1.0).sum() == B.nnz          # B is a subset of S
 
 

@@ -30,6 +30,32 @@ def central(f, x, idx, h):
     return (f(xp) - f(xm)) / (2 * h)
 
 
+@pytest.mark.parametrize("seed", [0, 3])
+def test_weighted_map_solves_penalised_normal_equations(seed):
+    """Direct pin of the soft-weighted map: for every column, m solves
+    (A^T A + P) m = A^T b with A = A_k(:, J_j) taken whole (all n rows, so no
+    row set is involved), b = A_0(:, j) and P = diag(mu (1/w - 1)), by
+    numpy's dense solver; the column residual is ||A m - b||^2 without the
+    penalty."""
+    import scipy.sparse as sp
+    A0, A1, S, w, mu = small_problem(seed)
+    M, rho, _, _ = O.sam_build(A1, A0, S, weights=w, mu=mu)
+    Ak = sp.csc_matrix((A1.val, A1.rowind, A1.colptr), shape=(A1.n, A1.n)).toarray()
+    A0d = sp.csc_matrix((A0.val, A0.rowind, A0.colptr), shape=(A0.n, A0.n)).toarray()
+    worst = 0.0
+    for j in range(A1.n):
+        a, b = S.colptr[j], S.colptr[j + 1]
+        J = S.rowind[a:b]
+        A = Ak[:, J]
+        p = mu * (1.0 / w[a:b] - 1.0)
+        m = np.linalg.solve(A.T @ A + np.diag(p), A.T @ A0d[:, j])
+        worst = max(worst, np.abs(M[a:b] - m).max() / np.abs(m).max())
+        r = A @ m - A0d[:, j]
+        assert np.isclose(rho[j], r @ r, rtol=1e-9, atol=1e-15)
+    assert worst <= 1e-10, worst
+    assert (w < 1.0).any() and (w > 0.0).all()    # the penalty is active on the candidates
+
+
 def test_loss_equals_build_residual():
     A0, A1, S, w, mu = small_problem(1)
     gAk, gA0, gw, L = O.backward(A1, A0, S, w, mu)
