@@ -14,6 +14,8 @@ one JSON line; progress goes to stderr.
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
     python bench.py --copy-calibration   # plain copy of known size, for PMC scaling
     python bench.py --roofline-only      # only the dominant kernel's timed launches
+    python bench.py --adjoint-only       # only the 48^3 weighted forward and adjoint
+    python bench.py --level1-cold        # level-1 builds over separate copies of 7 maps (HBM, not MALL)
 
 The roofline object describes the dominant kernel: the numeric variant that
 serves the most columns, launched alone over every column of one map (all of
@@ -110,6 +112,90 @@ def step_sequence(ctx, dA0, dAk0, nmaps, prec, power, spec, order, replan=True):
     return seq
 
 
+def adjoint_variant(ctx, P, torch, log, reps=10):
+    """The 48^3 adjoint workload: 7-point diffusion with lognormal(0, 0.5)
+    coefficients, soft weights on the level-2 candidates (1 on S(A) and the
+    diagonal); the weighted forward and the backward timed with HIP events on
+    the library's stream, with their algorithmic flops."""
+    from paper_2406_17656_amd import DeviceCSC
+    log("timing: adjoint, 48^3 diffusion, weighted forward and backward")
+    A0c, A1c = P.config5()
+    dA0c, dA1c = DeviceCSC.from_host(A0c), DeviceCSC.from_host(A1c)
+    cp5, ri5 = ctx.pattern(dA1c, 2)
+    w5 = torch.as_tensor(P.candidate_weights(A1c.n, cp5.cpu().numpy(), ri5.cpu().numpy(), A1c),
+                         dtype=torch.float64, device="cuda")
+    mu5 = P.penalty_scale(A1c)
+    pl5 = ctx.plan(dA1c, dA0c, cp5, ri5)
+    timing = {}
+    for name, call in (("forward", lambda: pl5.build_weighted(dA1c.val, dA0c.val, w5, mu5, "f32")),
+                       ("backward", lambda: pl5.backward(dA1c.val, dA0c.val, w5, mu5, 1.0, "f32"))):
+        call()
+        ctx.sync_status()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)   # the library runs on torch's current stream
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            call()
+        e1.record()
+        torch.cuda.synchronize()
+        timing[name] = e0.elapsed_time(e1) / reps * 1e-3
+    ctx.sync_status()
+    adj = {"n": A1c.n, "nnz_S": int(ri5.numel())}
+    for name, bwd in (("forward", False), ("backward", True)):
+        c = pl5.cost_weighted("f32", backward=bwd)
+        fl = c["flops32"] + c["flops64"]
+        tf = fl / timing[name] / 1e12
+        adj[f"{name}_ms"] = timing[name] * 1e3
+        adj[f"{name}_cols_per_s"] = A1c.n / timing[name]
+        adj[f"{name}_algorithmic_flops"] = fl
+        adj[f"{name}_TFLOPs"] = tf
+        adj[f"{name}_frac_fp32_peak"] = tf / PEAK["fp32_TFs"]
+    adj["backward_over_forward"] = timing["backward"] / timing["forward"]
+    pl5.close()
+    return adj
+
+
+def level1_cold(ctx, P, torch, log, copies=7, rounds=6):
+    """The level-1 (13 x 5 blocks) numeric build, the HBM-class case, on a
+    working set larger than the 256 MB last-level cache: `copies` maps of the
+    512 x 512 sequence, each with its own structure arrays, pattern, plan and
+    output (about 47 MB of compulsory bytes each), built round-robin, so every
+    launch finds its data evicted by the launches in between."""
+    from paper_2406_17656_amd import DeviceCSC
+    A0h, Ash = P.config2(m=512, nmat=copies + 1)
+    maps = []
+    for A in Ash[:copies]:
+        dA, dA0 = DeviceCSC.from_host(A), DeviceCSC.from_host(A0h)   # separate copies of every array
+        cp, ri = ctx.pattern(dA, 1)
+        pl = ctx.plan(dA, dA0, cp, ri)
+        maps.append((dA, dA0, cp, ri, pl))
+    order = tune_order(ctx, maps[0][0], maps[0][1], "f32", 1, {})["order"]
+    outs = []
+    for dA, dA0, cp, ri, pl in maps:
+        pl.select(order, "f32")
+        outs.append(torch.empty(max(ri.numel(), 1), dtype=torch.float32, device="cuda"))
+    for (dA, dA0, cp, ri, pl), M in zip(maps, outs):
+        pl.build(dA.val, dA0.val, "f32", M=M, fro=False)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(rounds):
+        for (dA, dA0, cp, ri, pl), M in zip(maps, outs):
+            pl.build(dA.val, dA0.val, "f32", M=M, fro=False)
+    e1.record()
+    torch.cuda.synchronize()
+    us = e0.elapsed_time(e1) / (rounds * copies) * 1e3
+    by = maps[0][4].cost("f32")["bytes"]
+    out = {"maps": copies, "launches": rounds * copies, "us_per_build": us, "algorithmic_bytes": by,
+           "hbm_GBs": by / us / 1e3, "hbm_frac": by / us / 1e3 / PEAK["hbm_GBs"], "order": order[:3]}
+    for m in maps:
+        m[4].close()
+    log(f"level-1 cold: {us:.1f} us per build, {out['hbm_GBs']:.0f} GB/s")
+    return out
+
+
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
@@ -137,6 +223,8 @@ def main():
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--roofline-only", action="store_true")
+    ap.add_argument("--adjoint-only", action="store_true")
+    ap.add_argument("--level1-cold", action="store_true")
     ap.add_argument("--grid", type=int, default=512)
     ap.add_argument("--workload", choices=sorted(WORKLOADS), default="diffusion2d")
     args = ap.parse_args()
@@ -154,6 +242,16 @@ def main():
 
     import pde_inputs as P
     from paper_2406_17656_amd import Context, DeviceCSC
+
+    if args.adjoint_only or args.level1_cold:
+        ctx = Context(0)
+        if args.adjoint_only:
+            print(json.dumps({"adjoint_48cubed": adjoint_variant(ctx, P, torch, log)}), flush=True)
+        else:
+            print(json.dumps({"f32_level1_cold": level1_cold(ctx, P, torch, log)}), flush=True)
+        torch.cuda.synchronize()
+        ctx.close()
+        return
 
     m = args.grid
     wl = WORKLOADS[args.workload]
@@ -393,35 +491,7 @@ def main():
             ad[f"level1_plus_top{kk}"] = {"nnz": int(ri.numel()), "rel_res": float(np.sqrt(float(r2a.cpu()[0]) / a02)),
                                           "ms_whole_pipeline": dt * 1e3}
         variants["adaptive_map0"] = ad
-        # the adjoint: 48^3 7-point diffusion with lognormal coefficients,
-        # soft weights on the level-2 candidates (1 on S(A) and the diagonal)
-        log("timing: adjoint, 48^3 diffusion, weighted forward and backward")
-        A0c, A1c = P.config5()
-        dA0c, dA1c = DeviceCSC.from_host(A0c), DeviceCSC.from_host(A1c)
-        cp5, ri5 = ctx.pattern(dA1c, 2)
-        w5 = torch.as_tensor(P.candidate_weights(A1c.n, cp5.cpu().numpy(), ri5.cpu().numpy(), A1c),
-                             dtype=torch.float64, device="cuda")
-        mu5 = P.penalty_scale(A1c)
-        pl5 = ctx.plan(dA1c, dA0c, cp5, ri5)
-        timing = {}
-        for name, call in (("forward", lambda: pl5.build_weighted(dA1c.val, dA0c.val, w5, mu5, "f32")),
-                           ("backward", lambda: pl5.backward(dA1c.val, dA0c.val, w5, mu5, 1.0, "f32"))):
-            call()
-            ctx.sync_status()
-            torch.cuda.synchronize()
-            reps = 5
-            t0 = time.perf_counter()
-            for _ in range(reps):
-                call()
-            torch.cuda.synchronize()
-            timing[name] = (time.perf_counter() - t0) / reps
-        ctx.sync_status()
-        pl5.close()
-        variants["adjoint_48cubed"] = {"n": A1c.n, "nnz_S": int(ri5.numel()),
-                                       "forward_cols_per_s": A1c.n / timing["forward"],
-                                       "backward_cols_per_s": A1c.n / timing["backward"],
-                                       "forward_ms": timing["forward"] * 1e3,
-                                       "backward_ms": timing["backward"] * 1e3}
+        variants["adjoint_48cubed"] = adjoint_variant(ctx, P, torch, log)
     else:
         plan.close()
     rel_res = [float(np.sqrt(r / a02)) for r in r2_f32]

@@ -91,6 +91,8 @@ typedef enum {
  *   step's decrease (exact up to rounding in the FP32 factor R); M values
  *   stored FP32. */
 typedef enum { SAM_PREC_F64 = 0, SAM_PREC_F32_REFINE = 1 } sam_precision;
+/* Calls take the precision as an int32_t holding one of these values (any
+ * other value is SAM_ERR_ARG). */
 
 /* Sparsification of A_k before the level expansion (Section 4).  The
  * diagonal is always kept, also when it is not stored. */
@@ -245,8 +247,18 @@ sam_status sam_plan_info(const sam_plan* plan, int32_t* n, int32_t* max_rows, in
  * c = |J_j| summed over columns; and compulsory HBM bytes
  * 12 nnz(A_k) + 12 nnz(A_0) + 4 nnz(S) + 12 (n+1) + v nnz(S) + 8 n, with
  * v = 4 (FP32 map) or 8 (FP64 map). */
-sam_status sam_plan_cost(const sam_plan* plan, sam_precision prec, double* flops32, double* flops64,
+sam_status sam_plan_cost(const sam_plan* plan, int32_t prec, double* flops32, double* flops64,
                          double* bytes);
+
+/* Algorithmic cost of one sam_build_weighted (backward = 0) or one
+ * sam_backward (backward = 1) on this plan (host outputs, may be NULL):
+ * flops of the stacked (|I_j| + |J_j|) x |J_j| Householder QR, Q^T b and the
+ * solves (FP32 in SAM_PREC_F32_REFINE), and of the FP64 refinement passes
+ * (two steps: r = b - A m, ||r||^2, A^T r, P m).  The adjoint adds the
+ * three normal-equation solves of lambda, its residual passes and five
+ * flops per gathered entry for the A_k contributions. */
+sam_status sam_plan_cost_weighted(const sam_plan* plan, int32_t prec, int32_t backward, double* flops32,
+                                  double* flops64);
 
 /* The numeric kernel variants compiled for `prec` (weighted = 0: plain maps,
  * 1: soft-weighted), in their default order.  Each serves column blocks of
@@ -254,7 +266,7 @@ sam_status sam_plan_cost(const sam_plan* plan, sam_precision prec, double* flops
  * columns; G lanes of a wave64 own one column problem, TC columns are staged
  * per LDS pass.  Host outputs of `capacity` entries (any may be NULL);
  * *count receives the number of variants.  Needs no context and no device. */
-sam_status sam_menu(sam_precision prec, int32_t weighted, int32_t capacity, int32_t* count, int32_t* G,
+sam_status sam_menu(int32_t prec, int32_t weighted, int32_t capacity, int32_t* count, int32_t* G,
                     int32_t* R, int32_t* NC, int32_t* TC);
 
 /* Choose the variants of the plan's plain builds in precision `prec`:
@@ -263,7 +275,7 @@ sam_status sam_menu(sam_precision prec, int32_t weighted, int32_t capacity, int3
  * are formed).  Re-sorts the plan's buckets; synchronising.  Errors:
  * SAM_ERR_ARG (bad index or count), SAM_ERR_UNSUPPORTED (some column fits no
  * listed variant; the previous choice stays). */
-sam_status sam_plan_select(sam_plan* plan, sam_precision prec, const int32_t* order, int32_t count,
+sam_status sam_plan_select(sam_plan* plan, int32_t prec, const int32_t* order, int32_t count,
                            sam_stream_t stream);
 
 /* Numeric SAM build on a plan (Section 2): for every column j solve
@@ -281,7 +293,7 @@ sam_status sam_plan_select(sam_plan* plan, sam_precision prec, const int32_t* or
  * sum's partials).
  * Async errors (sam_sync_status): SAM_ERR_RANK, SAM_ERR_NONFINITE. */
 sam_status sam_build_planned(sam_plan* plan, const double* Ak_val, const double* A0_val,
-                             sam_precision prec, void* M_val, double* col_res2, double* res2,
+                             int32_t prec, void* M_val, double* col_res2, double* res2,
                              sam_stream_t stream);
 
 /* Bytes of the workspace sam_build needs (host output): the plan of the
@@ -289,7 +301,7 @@ sam_status sam_build_planned(sam_plan* plan, const double* Ak_val, const double*
  * Synchronising. */
 sam_status sam_workspace_size(sam_ctx* ctx, const sam_csc* Ak, const sam_csc* A0,
                               const int32_t* S_colptr, const int32_t* S_rowind, int64_t nnz_S,
-                              sam_precision prec, size_t* bytes, sam_stream_t stream);
+                              int32_t prec, size_t* bytes, sam_stream_t stream);
 
 /* One-shot build (Section 2): sam_plan_create in `ws` (ws_bytes >=
  * sam_workspace_size), then sam_build_planned.  The planning is synchronising
@@ -298,7 +310,7 @@ sam_status sam_workspace_size(sam_ctx* ctx, const sam_csc* Ak, const sam_csc* A0
  * sam_build_planned. */
 sam_status sam_build(sam_ctx* ctx, const sam_csc* Ak, const sam_csc* A0,
                      const int32_t* S_colptr, const int32_t* S_rowind, int64_t nnz_S,
-                     sam_precision prec, void* M_val, double* col_res2, double* res2,
+                     int32_t prec, void* M_val, double* col_res2, double* res2,
                      void* ws, size_t ws_bytes, sam_stream_t stream);
 
 /* For callers that cannot allocate device memory (code under HIP graph
@@ -316,7 +328,7 @@ sam_status sam_build(sam_ctx* ctx, const sam_csc* Ak, const sam_csc* A0,
  * planning synchronises).  Allocates nothing. */
 sam_status sam_build_noalloc(sam_ctx* ctx, const sam_csc* Ak, const sam_csc* A0,
                              const int32_t* S_colptr, const int32_t* S_rowind, int64_t nnz_S,
-                             sam_precision prec, void* M_val, double* col_res2, double* res2,
+                             int32_t prec, void* M_val, double* col_res2, double* res2,
                              sam_stream_t stream);
 
 /* --------------------------------------------------------------- residual */
@@ -335,7 +347,7 @@ sam_status sam_residual_workspace_size(int32_t n, int32_t nnz_A0, size_t* bytes)
  * outside [0, n) is reported through the status word. */
 sam_status sam_residual(sam_ctx* ctx, const sam_csc* Ak, const sam_csc* A0,
                         const int32_t* M_colptr, const int32_t* M_rowind, int64_t nnz_M,
-                        const void* M_val, sam_precision prec, double* res2, double* a02,
+                        const void* M_val, int32_t prec, double* res2, double* a02,
                         void* ws, size_t ws_bytes, sam_stream_t stream);
 
 /* ------------------------------------------------------------------ apply */
@@ -357,7 +369,7 @@ sam_status sam_apply_prepare(sam_ctx* ctx, int32_t n, const int32_t* M_colptr,
  * ascending column order per row (bitwise reproducible).  M_val is double or
  * float per prec.  Allocates nothing. */
 sam_status sam_apply(sam_ctx* ctx, int32_t n, const int32_t* T_rowptr, const int32_t* T_colind,
-                     const int32_t* T_perm, const void* M_val, sam_precision prec,
+                     const int32_t* T_perm, const void* M_val, int32_t prec,
                      const double* x, double* y, sam_stream_t stream);
 
 /* --------------------------------------------------------------- sequence */
@@ -368,7 +380,7 @@ sam_status sam_apply(sam_ctx* ctx, int32_t n, const int32_t* T_rowptr, const int
  * S((I + S(A_k))^p) is counted, the bound of every source's pattern.  Checks
  * both structures.  Synchronising.  Errors as sam_sequence_create. */
 sam_status sam_sequence_size(sam_ctx* ctx, const sam_csc* A0, const sam_csc* Ak_struct,
-                             const sam_pattern_spec* spec, int32_t n_src, sam_precision prec,
+                             const sam_pattern_spec* spec, int32_t n_src, int32_t prec,
                              int32_t replan_each_run, void* ws, size_t ws_bytes, size_t* bytes,
                              sam_stream_t stream);
 
@@ -386,7 +398,7 @@ sam_status sam_sequence_size(sam_ctx* ctx, const sam_csc* A0, const sam_csc* Ak_
  * Errors: SAM_ERR_ARG also for n = 0 (nothing to map) and for memory too
  * small; SAM_ERR_UNSORTED (a bad structure).  Synchronising. */
 sam_status sam_sequence_create(sam_ctx* ctx, const sam_csc* A0, const sam_csc* Ak_struct,
-                               const sam_pattern_spec* spec, int32_t n_src, sam_precision prec,
+                               const sam_pattern_spec* spec, int32_t n_src, int32_t prec,
                                int32_t replan_each_run, void* mem, size_t mem_bytes, sam_seq** seq,
                                sam_stream_t stream);
 
@@ -422,7 +434,7 @@ sam_status sam_sequence_run(sam_seq* seq, const double* const* Ak_vals, void* co
  * penalty.  Only SAM_PREC_F32_REFINE (with two refinement steps) and
  * SAM_PREC_F64 are accepted.  Allocates nothing. */
 sam_status sam_build_weighted(sam_plan* plan, const double* Ak_val, const double* A0_val,
-                              const double* w, double mu, sam_precision prec, void* M_val,
+                              const double* w, double mu, int32_t prec, void* M_val,
                               double* col_res2, double* res2, sam_stream_t stream);
 
 /* Bytes of the workspace of sam_backward on this plan (host output): a
@@ -450,7 +462,7 @@ sam_status sam_backward_prepare(sam_plan* plan, void* ws, size_t ws_bytes, sam_s
  * since (else SAM_ERR_ARG); its staging part is rewritten by every call.
  * Asynchronous; calls on one plan must not overlap in time. */
 sam_status sam_backward(sam_plan* plan, const double* Ak_val, const double* A0_val,
-                        const double* w, double mu, double dL, sam_precision prec,
+                        const double* w, double mu, double dL, int32_t prec,
                         double* gAk, double* gA0, double* gw, double* loss,
                         void* ws, size_t ws_bytes, sam_stream_t stream);
 

@@ -41,14 +41,22 @@ KIND = {"none": 0, "global": 1, "column": 2, "lfil": 3}
 STATUS = {0: "ok", 1: "bad argument", 5: "rank deficient", 6: "non-finite"}
 
 
-def build(force: bool = False) -> str:
-    """Compile sam_oracle.c with gcc into liboracle.so (in place)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        tmp = _LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared",
-                               "-o", tmp, _SRC, "-lm"])
-        os.replace(tmp, _LIB)
-    return _LIB
+_LIB_ASAN = os.path.join(_HERE, "liboracle_asan.so")
+
+
+def build(force: bool = False, sanitize: bool = False) -> str:
+    """Compile sam_oracle.c with gcc into liboracle.so (in place); with
+    sanitize=True into liboracle_asan.so with AddressSanitizer and
+    UndefinedBehaviorSanitizer (any report aborts)."""
+    out = _LIB_ASAN if sanitize else _LIB
+    if force or not os.path.exists(out) or os.path.getmtime(out) < os.path.getmtime(_SRC):
+        tmp = out + ".tmp%d" % os.getpid()
+        flags = ["-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+                 "-fno-sanitize-recover=undefined"] if sanitize else ["-O2"]
+        subprocess.check_call(["gcc"] + flags + ["-std=c11", "-fopenmp", "-fPIC", "-shared",
+                                                 "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, out)
+    return out
 
 
 _lib = None
@@ -57,7 +65,8 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        _lib = ctypes.CDLL(build())
+        # SAM_ORACLE_LIB: another build of the same source (the sanitizer test)
+        _lib = ctypes.CDLL(os.environ.get("SAM_ORACLE_LIB") or build())
         P = ctypes.c_void_p
         I = ctypes.c_int
         D = ctypes.c_double

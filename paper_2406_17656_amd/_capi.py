@@ -8,7 +8,8 @@ import os
 import re
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libsam_mi355x.so")
+# SAM_MI355X_LIB: another build of the library (the host-sanitizer build)
+LIB_PATH = os.environ.get("SAM_MI355X_LIB") or os.path.join(HERE, "libsam_mi355x.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "sam.h")
 
 c_int32 = ctypes.c_int32
@@ -68,6 +69,7 @@ SIGNATURES = {
                                 ctypes.POINTER(c_int32), ctypes.POINTER(c_int32)]),
     "sam_plan_cost": (c_int32, [P, c_int32, ctypes.POINTER(c_double), ctypes.POINTER(c_double),
                                 ctypes.POINTER(c_double)]),
+    "sam_plan_cost_weighted": (c_int32, [P, c_int32, c_int32, ctypes.POINTER(c_double), ctypes.POINTER(c_double)]),
     "sam_menu": (c_int32, [c_int32, c_int32, c_int32, ctypes.POINTER(c_int32), P, P, P, P]),
     "sam_plan_select": (c_int32, [P, c_int32, P, c_int32, P]),
     "sam_sequence_select": (c_int32, [P, P, c_int32, P]),

@@ -93,5 +93,40 @@ def build(force: bool = False, jobs: int = 4) -> str:
     return LIB
 
 
+HOST_SOURCES = ["sam_capi.cpp", "sam_sequence.cpp", "sam_backward.cpp", "sam_adaptive_api.cpp", "sam_noalloc.cpp"]
+ASAN_DIR = os.path.join(OBJDIR, "asan")
+ASAN_LIB = os.path.join(ASAN_DIR, "libsam_mi355x_asan.so")
+
+
+def build_host_sanitized(jobs: int = 5) -> str:
+    """The library with its host code (the C ABI translation units) built
+    with AddressSanitizer and UndefinedBehaviorSanitizer, linked with the
+    regular kernel objects: for the host-side tests, which run without a
+    GPU.  The sanitizers apply to host code only (each -fsanitize= follows
+    -Xarch_host)."""
+    build()
+    os.makedirs(ASAN_DIR, exist_ok=True)
+    san = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+           "-Xarch_host", "-fno-sanitize-recover=undefined", "-Xarch_host", "-fno-omit-frame-pointer", "-g"]
+
+    def one(src):
+        obj = os.path.join(ASAN_DIR, os.path.splitext(src)[0] + ".o")
+        cmd = [HIPCC] + CFLAGS + san + ["-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError(f"hipcc (sanitized) failed for {src}:\n{r.stdout}\n{r.stderr}")
+        return obj
+
+    with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
+        objs = list(ex.map(one, HOST_SOURCES))
+    kernels = [os.path.join(OBJDIR, os.path.splitext(s)[0] + ".o") for s in SOURCES if s not in HOST_SOURCES]
+    cmd = [HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-Xarch_host", "-fsanitize=address",
+           "-Xarch_host", "-fsanitize=undefined", "-o", ASAN_LIB] + objs + kernels
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"link (sanitized) failed:\n{r.stdout}\n{r.stderr}")
+    return ASAN_LIB
+
+
 if __name__ == "__main__":
     print(build(force="--force" in sys.argv))

@@ -10,16 +10,35 @@ namespace samk {
 
 namespace {
 
+// One thread per column l of A_k: for every column j whose pattern holds l
+// (the row view of S, ascending j) the staged contributions of j to the
+// entries of A_k(:, l) are contiguous, so each j costs one offset lookup
+// (prefetched one step ahead) and one contiguous read per entry, added into
+// per-entry registers in ascending j.  Columns longer than kChunk entries
+// take several passes.
+constexpr int kChunk = 8;
+
 __global__ void k_backward_scatter(int n, const int* Ak_cp, const int* ST_rowptr, const int* ST_perm,
                                    const int64_t* segoff, const double* contrib, double* gAk) {
     const int l = blockIdx.x * blockDim.x + threadIdx.x;
     if (l >= n) return;
-    const int fa = Ak_cp[l], fb = Ak_cp[l + 1];
+    const int fa = Ak_cp[l], len = Ak_cp[l + 1] - fa;
     const int sa = ST_rowptr[l], sb = ST_rowptr[l + 1];
-    for (int f = fa; f < fb; ++f) {
-        double acc = 0.0;
-        for (int e = sa; e < sb; ++e) acc += contrib[segoff[ST_perm[e]] + (f - fa)];
-        gAk[f] = acc;
+    for (int f0 = 0; f0 < len; f0 += kChunk) {
+        double acc[kChunk];
+#pragma unroll
+        for (int i = 0; i < kChunk; ++i) acc[i] = 0.0;
+        int64_t next = sa < sb ? segoff[ST_perm[sa]] : 0;
+        for (int e = sa; e < sb; ++e) {
+            const double* src = contrib + next + f0;
+            if (e + 1 < sb) next = segoff[ST_perm[e + 1]];
+#pragma unroll
+            for (int i = 0; i < kChunk; ++i)
+                if (f0 + i < len) acc[i] += src[i];
+        }
+#pragma unroll
+        for (int i = 0; i < kChunk; ++i)
+            if (f0 + i < len) gAk[fa + f0 + i] = acc[i];
     }
 }
 

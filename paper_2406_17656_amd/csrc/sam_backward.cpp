@@ -72,7 +72,7 @@ sam_status sam_backward_prepare(sam_plan* plan, void* ws, size_t ws_bytes, sam_s
 }
 
 sam_status sam_backward(sam_plan* plan, const double* Ak_val, const double* A0_val, const double* w, double mu,
-                        double dL, sam_precision prec, double* gAk, double* gA0, double* gw, double* loss, void* ws,
+                        double dL, int32_t prec, double* gAk, double* gA0, double* gw, double* loss, void* ws,
                         size_t ws_bytes, sam_stream_t stream) {
     if (!plan || !plan->ctx) return SAM_ERR_ARG;
     sam_ctx* ctx = plan->ctx;

@@ -459,6 +459,11 @@ sam_status plan_init(sam_ctx* ctx, sam_plan* pl, const sam_csc* Ak, const sam_cs
             pl->fl_ref64 += 6.0 * r * c + 2.0 * r;   // r = b - Am, A^T r, final residual
             // FP64 mode: QR, Q^T b, one triangular solve, explicit residual
             pl->fl_f64 += 2.0 * r * c * c - 2.0 / 3.0 * c * c * c + 4.0 * r * c + c * c + 2.0 * r * c + 2.0 * r;
+            pl->m_rc2 += r * c * c;
+            pl->m_c3 += c * c * c;
+            pl->m_rc += r * c;
+            pl->m_c2 += c * c;
+            pl->m_r += r;
         }
         for (int p = 0; p < 2; ++p)
             for (int w = 0; w < 2; ++w)
@@ -800,7 +805,7 @@ sam_status sam_plan_destroy(sam_plan* plan) {
     return SAM_OK;
 }
 
-sam_status sam_plan_cost(const sam_plan* plan, sam_precision prec, double* flops32, double* flops64,
+sam_status sam_plan_cost(const sam_plan* plan, int32_t prec, double* flops32, double* flops64,
                          double* bytes) {
     if (!plan || !prec_ok(prec)) return SAM_ERR_ARG;
     const bool f32 = prec == SAM_PREC_F32_REFINE;
@@ -811,6 +816,35 @@ sam_status sam_plan_cost(const sam_plan* plan, sam_precision prec, double* flops
         *bytes = 12.0 * plan->nnzA + 12.0 * plan->nnzA0 + 4.0 * (double)plan->nnzS + 12.0 * (plan->n + 1.0) +
                  vb * (double)plan->nnzS + 8.0 * plan->n;
     }
+    return SAM_OK;
+}
+
+sam_status sam_plan_cost_weighted(const sam_plan* plan, int32_t prec, int32_t backward, double* flops32,
+                                  double* flops64) {
+    if (!plan || !prec_ok(prec) || (backward != 0 && backward != 1)) return SAM_ERR_ARG;
+    const bool f32 = prec == SAM_PREC_F32_REFINE;
+    const double nS = (double)plan->nnzS;
+    // QR of the stacked (r + c) x c block and Q^T b, then one triangular
+    // solve; FP32 + refinement adds two steps of two solves (FP32) and of
+    // r = b - A m, ||r||^2, A^T r and P m (FP64)
+    const double qr = 2.0 * (plan->m_rc2 + plan->m_c3) - 2.0 / 3.0 * plan->m_c3 + 4.0 * (plan->m_rc + plan->m_c2);
+    double q32 = f32 ? qr + 5.0 * plan->m_c2 : 0.0;
+    double q64 = f32 ? 8.0 * plan->m_rc + 4.0 * plan->m_r + 4.0 * nS : qr + plan->m_c2;
+    if (backward) {
+        // lambda: three normal-equation solves (two refinement steps), the
+        // residual and A^T r, two scatter/gather pairs, the final A lambda,
+        // and five flops per gathered entry for the contributions
+        const double s32 = 6.0 * plan->m_c2;
+        const double s64 = 14.0 * plan->m_rc + 4.0 * nS + 5.0 * (double)plan->E;
+        if (f32) {
+            q32 += s32;
+            q64 += s64;
+        } else {
+            q64 += s32 + s64;
+        }
+    }
+    if (flops32) *flops32 = q32;
+    if (flops64) *flops64 = q64;
     return SAM_OK;
 }
 
@@ -830,7 +864,7 @@ sam_status sam_plan_info(const sam_plan* plan, int32_t* n, int32_t* max_rows, in
 
 // ------------------------------------------------------------------ build
 
-sam_status sam_build_planned(sam_plan* plan, const double* Ak_val, const double* A0_val, sam_precision prec,
+sam_status sam_build_planned(sam_plan* plan, const double* Ak_val, const double* A0_val, int32_t prec,
                              void* M_val, double* col_res2, double* res2, sam_stream_t stream) {
     if (!plan || !plan->ctx) return SAM_ERR_ARG;
     sam_ctx* ctx = plan->ctx;
@@ -845,7 +879,7 @@ sam_status sam_build_planned(sam_plan* plan, const double* Ak_val, const double*
 }
 
 sam_status sam_workspace_size(sam_ctx* ctx, const sam_csc* Ak, const sam_csc* A0, const int32_t* S_colptr,
-                              const int32_t* S_rowind, int64_t nnz_S, sam_precision prec, size_t* bytes,
+                              const int32_t* S_rowind, int64_t nnz_S, int32_t prec, size_t* bytes,
                               sam_stream_t stream) {
     if (check_ctx(ctx)) return SAM_ERR_ARG;
     if (!prec_ok(prec)) return fail(ctx, SAM_ERR_ARG, "unknown precision %d", (int)prec);
@@ -853,7 +887,7 @@ sam_status sam_workspace_size(sam_ctx* ctx, const sam_csc* Ak, const sam_csc* A0
 }
 
 sam_status sam_build(sam_ctx* ctx, const sam_csc* Ak, const sam_csc* A0, const int32_t* S_colptr,
-                     const int32_t* S_rowind, int64_t nnz_S, sam_precision prec, void* M_val, double* col_res2,
+                     const int32_t* S_rowind, int64_t nnz_S, int32_t prec, void* M_val, double* col_res2,
                      double* res2, void* ws, size_t ws_bytes, sam_stream_t stream) {
     if (check_ctx(ctx)) return SAM_ERR_ARG;
     sam_status st;
@@ -878,7 +912,7 @@ sam_status sam_residual_workspace_size(int32_t n, int32_t nnz_A0, size_t* bytes)
 }
 
 sam_status sam_residual(sam_ctx* ctx, const sam_csc* Ak, const sam_csc* A0, const int32_t* M_colptr,
-                        const int32_t* M_rowind, int64_t nnz_M, const void* M_val, sam_precision prec, double* res2,
+                        const int32_t* M_rowind, int64_t nnz_M, const void* M_val, int32_t prec, double* res2,
                         double* a02, void* ws, size_t ws_bytes, sam_stream_t stream) {
     if (check_ctx(ctx)) return SAM_ERR_ARG;
     sam_status st;
@@ -942,7 +976,7 @@ sam_status sam_apply_prepare(sam_ctx* ctx, int32_t n, const int32_t* M_colptr, c
 }
 
 sam_status sam_apply(sam_ctx* ctx, int32_t n, const int32_t* T_rowptr, const int32_t* T_colind, const int32_t* T_perm,
-                     const void* M_val, sam_precision prec, const double* x, double* y, sam_stream_t stream) {
+                     const void* M_val, int32_t prec, const double* x, double* y, sam_stream_t stream) {
     if (check_ctx(ctx)) return SAM_ERR_ARG;
     if (n < 0) return fail(ctx, SAM_ERR_ARG, "negative size");
     if (!prec_ok(prec)) return fail(ctx, SAM_ERR_ARG, "unknown precision %d", (int)prec);
@@ -954,7 +988,7 @@ sam_status sam_apply(sam_ctx* ctx, int32_t n, const int32_t* T_rowptr, const int
 }
 
 sam_status sam_build_weighted(sam_plan* plan, const double* Ak_val, const double* A0_val, const double* w, double mu,
-                              sam_precision prec, void* M_val, double* col_res2, double* res2, sam_stream_t stream) {
+                              int32_t prec, void* M_val, double* col_res2, double* res2, sam_stream_t stream) {
     if (!plan || !plan->ctx) return SAM_ERR_ARG;
     sam_ctx* ctx = plan->ctx;
     check_ctx(ctx);
@@ -1005,7 +1039,7 @@ sam_status plan_select(sam_plan* pl, int prec, const std::vector<const NumericVa
 
 extern "C" {
 
-sam_status sam_menu(sam_precision prec, int32_t weighted, int32_t capacity, int32_t* count, int32_t* G, int32_t* R,
+sam_status sam_menu(int32_t prec, int32_t weighted, int32_t capacity, int32_t* count, int32_t* G, int32_t* R,
                     int32_t* NC, int32_t* TC) {
     if (!prec_ok(prec) || (weighted != 0 && weighted != 1) || !count || capacity < 0) return SAM_ERR_ARG;
     std::vector<const NumericVariant*> all;
@@ -1020,7 +1054,7 @@ sam_status sam_menu(sam_precision prec, int32_t weighted, int32_t capacity, int3
     return SAM_OK;
 }
 
-sam_status sam_plan_select(sam_plan* plan, sam_precision prec, const int32_t* order, int32_t count,
+sam_status sam_plan_select(sam_plan* plan, int32_t prec, const int32_t* order, int32_t count,
                            sam_stream_t stream) {
     if (!plan || !plan->ctx) return SAM_ERR_ARG;
     sam_ctx* ctx = plan->ctx;

@@ -148,8 +148,11 @@ struct sam_plan {
     int* flags = nullptr;       // device ints for the bucket sort
     int64_t E = 0;
     int max_rows = 0, max_cols = 0;
-    // algorithmic flop counts of one build (dense column blocks)
+    // algorithmic flop counts of one build (dense column blocks), and the
+    // shape moments sum_j r c^2, c^3, r c, c^2, r (r = |I_j|, c = |J_j|) the
+    // weighted and adjoint counts follow from
     double fl_qr32 = 0.0, fl_ref64 = 0.0, fl_f64 = 0.0;
+    double m_rc2 = 0.0, m_c3 = 0.0, m_rc = 0.0, m_c2 = 0.0, m_r = 0.0;
     Combo combo[2][2];  // [prec][weighted]
     // the workspace sam_backward_prepare built the row view of S in
     const void* bwd_ws = nullptr;
@@ -181,7 +184,9 @@ sam_status check_csc_args(sam_ctx* ctx, const sam_csc* A, const char* name, bool
 sam_status check_spec(sam_ctx* ctx, const sam_pattern_spec* spec);
 sam_status check_ws(sam_ctx* ctx, const void* ws, size_t ws_bytes, size_t need, const char* what);
 samk::SparsifySpec to_sp(const sam_pattern_spec* spec);
-inline bool prec_ok(sam_precision p) { return p == SAM_PREC_F64 || p == SAM_PREC_F32_REFINE; }
+// precision arguments are int32_t (one of sam_precision): any value a C
+// caller passes is well defined and checked here
+inline bool prec_ok(int32_t p) { return p == SAM_PREC_F64 || p == SAM_PREC_F32_REFINE; }
 
 template <typename T>
 hipError_t read_back(const T* dptr, T* host, hipStream_t s) {

@@ -48,7 +48,7 @@ hipError_t scratch_setup(int device) {
 extern "C" {
 
 sam_status sam_build_noalloc(sam_ctx* ctx, const sam_csc* Ak, const sam_csc* A0, const int32_t* S_colptr,
-                             const int32_t* S_rowind, int64_t nnz_S, sam_precision prec, void* M_val,
+                             const int32_t* S_rowind, int64_t nnz_S, int32_t prec, void* M_val,
                              double* col_res2, double* res2, sam_stream_t stream) {
     if (check_ctx(ctx)) return SAM_ERR_ARG;
     sam_status st;

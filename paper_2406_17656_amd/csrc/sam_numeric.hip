@@ -125,6 +125,13 @@ k_numeric(NumericArgs a) {
     __shared__ double alsh[BACKWARD ? P * RS : 1];  // A lambda (adjoint)
     __shared__ double racc;               // the block's running sum of column residuals
     __shared__ double pen_sh[WEIGHTED ? P * NC : 1];  // penalties p_c of the group's problems
+    // The weighted and adjoint forms keep their length-NC FP64 vectors (m,
+    // A^T r, the corrections, lambda and its right side) in LDS: one slot per
+    // problem and column, which every lane of the group reads at once (a
+    // broadcast), instead of a copy in every lane's registers.
+    constexpr int kNV = BACKWARD ? 5 : (WEIGHTED ? 4 : 1);
+    __shared__ double vsh[WEIGHTED ? P * kNV * NC : 1];
+    __shared__ TQ rinv_sh[WEIGHTED ? P * NC : 1];  // weighted forms: 1 / R_kk
 
     const int lane = threadIdx.x;
     const int g = lane % G;
@@ -360,7 +367,17 @@ k_numeric(NumericArgs a) {
 
         // ---- Householder QR (dgeqr2's sign convention, beta = -sign(alpha) ||x||),
         //      applied to b as well
-        TQ rdiag[NC], rinv[NC];
+        // 1 / R_kk: in registers for the plain map, in LDS for the weighted
+        // forms (whose solves run beside the adjoint's FP64 passes)
+        TQ rinv[WEIGHTED ? 1 : NC];
+        auto RINV = [&](int k) -> TQ {
+            if constexpr (WEIGHTED) return rinv_sh[q * NC + k];
+            else return rinv[k];
+        };
+        // |R_kk| over the live columns, for the rank test: largest, smallest,
+        // and whether one is NaN (of the last stage when there are two)
+        TQ dmax = 0, dmin = (TQ)INFINITY;
+        bool dnan = false;
         // Soft weights: the penalised problem min ||A m - b||^2 + m^T P m is
         // the least-squares problem of the stacked [A; diag(sqrt p)].  Its QR
         // is taken in two stages: the QR of A, then the QR of
@@ -411,16 +428,17 @@ k_numeric(NumericArgs a) {
                     __builtin_amdgcn_sched_barrier(0);
                 }
                 const int tk = k / G, gk = k % G;
-                TQ sig = 0, alp = 0;
+                TQ sig = 0;
 #pragma unroll
                 for (int t = tk; t < R; ++t) {
                     const TQ x = A[t][k];
                     const bool below = (t > tk) || (g > gk);
                     sig += below ? x * x : (TQ)0;
-                    if (t == tk) alp = (g == gk) ? x : (TQ)0;
                 }
                 sig = group_sum<G>(sig);
-                alp = group_sum<G>(alp);
+                // the diagonal entry, from the lane that holds row k (one
+                // quad-permute move for groups of up to four lanes)
+                const TQ alp = group_bcast<G>(A[tk][k], g, gk);
                 const bool zero = !(sig > (TQ)0);
                 const TQ nrm = root<TQ>(alp * alp + sig);
                 const TQ beta = zero ? alp : -copysign(nrm, alp);
@@ -432,8 +450,18 @@ k_numeric(NumericArgs a) {
                 // already a multiple of e_k.  Entries below the diagonal are not
                 // read again.
                 const TQ sigma = zero ? (TQ)0 : recip<TQ>(beta * (beta - alp));
-                rdiag[k] = beta;
-                rinv[k] = ib;
+                if (stage == (WEIGHTED ? 1 : 0)) {
+                    const TQ ab = fabs(beta);
+                    const bool live = k < nJ;
+                    dmax = live ? fmax(dmax, ab) : dmax;
+                    dmin = live ? fmin(dmin, ab) : dmin;
+                    dnan |= live && !(ab == ab);
+                }
+                if constexpr (WEIGHTED) {
+                    if (g == 0) rinv_sh[q * NC + k] = ib;
+                } else {
+                    rinv[k] = ib;
+                }
                 TQ v[R];
 #pragma unroll
                 for (int t = tk; t < R; ++t) {
@@ -474,15 +502,11 @@ k_numeric(NumericArgs a) {
         // ---- rank test: |R_kk| <= 10 * rows * eps * max |R_ii|
         bool bad_rank = false;
         {
-            TQ mx = 0;
-#pragma unroll
-            for (int k = 0; k < NC; ++k) mx = fmax(mx, k < nJ ? fabs(rdiag[k]) : (TQ)0);
             const TQ eps = std::is_same<TQ, float>::value ? (TQ)1.1920928955078125e-07
                                                           : (TQ)2.220446049250313e-16;
-            const TQ tol = (TQ)10 * (TQ)nrows * eps * mx;
-            if (nJ > 0 && !(mx > (TQ)0)) bad_rank = true;
-#pragma unroll
-            for (int k = 0; k < NC; ++k) bad_rank |= (k < nJ) && !(fabs(rdiag[k]) > tol);
+            const TQ tol = (TQ)10 * (TQ)nrows * eps * dmax;
+            // some live |R_kk| <= tol (or NaN), or all of them zero
+            if (nJ > 0) bad_rank = dnan || !(dmax > (TQ)0) || !(dmin > tol);
         }
 
         // ||c2||^2 = rows nJ.. of Q^T b, before the back substitution consumes b
@@ -507,15 +531,29 @@ k_numeric(NumericArgs a) {
 #pragma unroll
             for (int k = NC - 1; k >= 0; --k) {
                 const int tk = k / G, gk = k % G;
-                const TQ xk = group_bcast<G>(z[tk] * rinv[k], g, gk);
+                const TQ xk = group_bcast<G>(z[tk] * RINV(k), g, gk);
                 x[k] = (k < nJ) ? xk : (TQ)0;
 #pragma unroll
                 for (int t = 0; t <= tk; ++t) z[t] -= A[t][k] * x[k];
             }
         };
-        // ---- R m = c1
-        TQ m[NC];
-        back_solve(bq, m);
+        // x = R^{-1} z into an LDS vector (the weighted forms): as back_solve,
+        // with x_k stored by one lane of the group
+        auto back_solve_v = [&](TQ (&z)[R], double* x_sh) {
+#pragma unroll
+            for (int k = NC - 1; k >= 0; --k) {
+                const int tk = k / G, gk = k % G;
+                TQ xk = group_bcast<G>(z[tk] * RINV(k), g, gk);
+                xk = (k < nJ) ? xk : (TQ)0;
+                if (g == 0) x_sh[k] = (double)xk;
+#pragma unroll
+                for (int t = 0; t <= tk; ++t) z[t] -= A[t][k] * xk;
+            }
+            wave_sync();
+        };
+        // ---- R m = c1 (the weighted forms solve it into their LDS slot below)
+        TQ m[WEIGHTED ? 1 : NC];
+        if constexpr (!WEIGHTED) back_solve(bq, m);
 
         double* rsh = lds_tile + q * RS;  // residual vector (the tile is free now)
 
@@ -543,54 +581,59 @@ k_numeric(NumericArgs a) {
                 }
             }
         };
-        // vec += sgn * A x
-        auto scatter = [&](double* vec, const double (&x)[NC], double sgn) {
+        // vec += sgn * A x, x an LDS vector.  Entries past the register
+        // cache of a long column are taken in one loop over the columns
+        // (not unrolled: one copy of the memory path).
+        auto scatter_v = [&](double* vec, const double* x_sh, double sgn) {
 #pragma unroll
             for (int c = 0; c < NC; ++c) {
-                const double xc = sgn * x[c];
+                const double xc = sgn * x_sh[c];
 #pragma unroll
                 for (int u = 0; u < LPL; ++u) lds_add(&vec[pp[c][u]], pv[c][u] * xc);
             }
-            if (longc) {  // long columns: the rest straight from memory
-#pragma unroll
+            if (longc) {
+#pragma unroll 1
                 for (int c = 0; c < NC; ++c) {
                     const int len = cln[q][c];
-                    const double xc = sgn * x[c];
+                    const double xc = sgn * x_sh[c];
                     const int e0 = cst[q][c], vb = vbs[q][c];
                     for (int e = g + LPL * G; e < len; e += G) lds_add(&vec[a.posA[eo + e0 + e]], a.Ak_v[vb + e] * xc);
                 }
             }
             wave_sync();
         };
-        // out = A^T vec (summed over the group)
-        auto gather = [&](const double* vec, double (&out)[NC]) {
+        // out = A^T vec (summed over the group) into an LDS vector; a long
+        // column's remaining entries are added in a second, rolled loop
+        auto gather_v = [&](const double* vec, double* out_sh) {
 #pragma unroll
             for (int c = 0; c < NC; ++c) {
                 double sacc = 0.0;
 #pragma unroll
                 for (int u = 0; u < LPL; ++u) sacc += pv[c][u] * vec[pp[c][u]];
-                out[c] = sacc;
+                sacc = group_sum<G>(sacc);
+                if (g == 0) out_sh[c] = sacc;
             }
             if (longc) {
-#pragma unroll
+                wave_sync();
+#pragma unroll 1
                 for (int c = 0; c < NC; ++c) {
                     const int len = cln[q][c];
                     const int e0 = cst[q][c], vb = vbs[q][c];
                     double sacc = 0.0;
                     for (int e = g + LPL * G; e < len; e += G) sacc += a.Ak_v[vb + e] * vec[a.posA[eo + e0 + e]];
-                    out[c] += sacc;
+                    sacc = group_sum<G>(sacc);
+                    if (g == 0) out_sh[c] += sacc;
                 }
             }
-#pragma unroll
-            for (int c = 0; c < NC; ++c) out[c] = group_sum<G>(out[c]);
+            wave_sync();
         };
-        // x = R^{-1} R^{-T} rhs in the QR's precision (R^T R = A^T A + P);
-        // returns ||y||^2 for y = R^{-T} rhs
-        auto solve_normal = [&](const double (&rhs)[NC], double (&x)[NC]) {
+        // x = R^{-1} R^{-T} rhs in the QR's precision (R^T R = A^T A + P), rhs
+        // and x LDS vectors; returns ||y||^2 for y = R^{-T} rhs
+        auto solve_normal_v = [&](const double* rhs_sh, double* x_sh) {
             TQ ydist[R];
-            TQ yrep[NC];
 #pragma unroll
             for (int t = 0; t < R; ++t) ydist[t] = 0;
+            double yy = 0.0;
 #pragma unroll
             for (int c = 0; c < NC; ++c) {
                 TQ part = 0;
@@ -600,19 +643,12 @@ k_numeric(NumericArgs a) {
                     if (t * G < c) part += (row < c) ? A[t][c] * ydist[t] : (TQ)0;
                 }
                 part = group_sum<G>(part);
-                TQ yc = ((TQ)rhs[c] - part) * rinv[c];
+                TQ yc = ((TQ)rhs_sh[c] - part) * RINV(c);
                 yc = (c < nJ) ? yc : (TQ)0;
-                yrep[c] = yc;
+                yy += (double)yc * (double)yc;
                 if (g == c % G) ydist[c / G] = yc;
             }
-            TQ dl[NC];
-            back_solve(ydist, dl);
-            double yy = 0.0;
-#pragma unroll
-            for (int c = 0; c < NC; ++c) {
-                x[c] = (double)dl[c];
-                yy += (double)yrep[c] * (double)yrep[c];
-            }
+            back_solve_v(ydist, x_sh);
             return yy;
         };
         auto reset = [&](double* vec, bool from_b) {
@@ -631,8 +667,9 @@ k_numeric(NumericArgs a) {
             wave_sync();
         }
 
-        double mfin[NC];
+        double mfin[WEIGHTED ? 1 : NC];
         double rr;
+        double* msh = vsh + q * kNV * NC;      // weighted forms: m
         if constexpr (REFINE && MODE == 0) {
             // One seminormal refinement step, residual in FP64, taken in
             // column chunks so that one chunk of entries at a time is held in
@@ -731,7 +768,7 @@ k_numeric(NumericArgs a) {
                             if (t * G < c) part += (row < c) ? A[t][c] * ydist[t] : (TQ)0;
                         }
                         const double sc = group_sum<G>(gp - (double)part);
-                        TQ yc = (TQ)sc * rinv[c];
+                        TQ yc = (TQ)sc * RINV(c);
                         yc = (c < nJ) ? yc : (TQ)0;
                         yrep[c] = yc;
                         if (g == c % G) ydist[c / G] = yc;
@@ -740,99 +777,109 @@ k_numeric(NumericArgs a) {
             }
             TQ dl[NC];
             back_solve(ydist, dl);
-            double yy = 0.0;
+            // ||y||^2 is the step's decrease of the residual, (u kappa)^2 of
+            // it at most: the QR's precision is ample.  The map is stored in
+            // FP32, so m + d is formed there too (the correctly rounded sum
+            // of the two floats).
+            TQ yy = 0;
 #pragma unroll
             for (int c = 0; c < NC; ++c) {
-                yy += (double)yrep[c] * (double)yrep[c];
-                mfin[c] = (double)m[c] + (double)dl[c];
+                yy += yrep[c] * yrep[c];
+                mfin[c] = (double)(m[c] + dl[c]);
             }
-            rr = rr0 - yy + outj;
-        } else if constexpr (REFINE) {
-            // refinement on the normal equations (A^T A + P) m = A^T b with the
-            // residual in FP64:  r = b - A m,  m += R^{-1} R^{-T} (A^T r - P m)
-            double m64[NC];
-#pragma unroll
-            for (int c = 0; c < NC; ++c) m64[c] = (double)m[c];
-            double rr_it = 0.0;
-#pragma unroll
-            for (int it = 0; it < (WEIGHTED ? 2 : 1); ++it) {
-                // the plain map needs b no more after this step: r = b - A m
-                // is formed in place (scratch row cleared)
-                double* rv = (WEIGHTED || BACKWARD) ? rsh : bsh + q * RS;
-                if constexpr (WEIGHTED || BACKWARD) reset(rv, true);
-                else rv[trash] = 0.0;
-                load_entries();
-                wave_sync();
-                scatter(rv, m64, -1.0);
-                double r2 = 0.0;
-#pragma unroll
-                for (int t = 0; t < R; ++t) {
-                    const double x = rv[t * G + g];
-                    r2 += (t * G + g < nIj) ? x * x : 0.0;
-                }
-                rr_it = group_sum<G>(r2);
-                double gA[NC], gc[NC], dl[NC];
-                gather(rv, gA);
-#pragma unroll
-                for (int c = 0; c < NC; ++c) gc[c] = WEIGHTED ? gA[c] - pen[c] * m64[c] : gA[c];
-                const double yy = solve_normal(gc, dl);
-                // ||b - A(m + d)||^2 = ||r||^2 - 2 d^T A^T r + ||A d||^2, and
-                // ||A d||^2 = ||R d||^2 - d^T P d with R d = y (second order in d)
-                double dg = 0.0, pdd = 0.0;
-#pragma unroll
-                for (int c = 0; c < NC; ++c) {
-                    dg += dl[c] * gA[c];
-                    if constexpr (WEIGHTED) pdd += pen[c] * dl[c] * dl[c];
-                    m64[c] += dl[c];
-                }
-                rr_it = rr_it - 2.0 * dg + (yy - pdd);
-            }
-#pragma unroll
-            for (int c = 0; c < NC; ++c) mfin[c] = m64[c];
-            rr = rr_it + outj;
-        } else {
+            rr = rr0 - (double)yy + outj;
+        } else if constexpr (!WEIGHTED) {
 #pragma unroll
             for (int c = 0; c < NC; ++c) mfin[c] = (double)m[c];
-            // ||c2||^2 (the stacked form adds m^T P m)
-            rr = c2sq;
-            if constexpr (WEIGHTED) {
+            rr = c2sq + outj;   // ||c2||^2
+        } else {
+            // soft-weighted forms: m, A^T r, the correction and A^T r - P m
+            // in the problem's LDS slots
+            double* gsh = msh + NC;
+            double* dsh = msh + 2 * NC;
+            double* csh = msh + 3 * NC;
+            back_solve_v(bq, msh);          // R m = c1
+            if constexpr (REFINE) {
+                // two refinement steps on the normal equations
+                // (A^T A + P) m = A^T b with the residual in FP64:
+                // r = b - A m,  m += R^{-1} R^{-T} (A^T r - P m)
+                double rr_it = 0.0;
 #pragma unroll
-                for (int c = 0; c < NC; ++c) rr -= pen[c] * mfin[c] * mfin[c];
+                for (int it = 0; it < 2; ++it) {
+                    reset(rsh, true);
+                    load_entries();
+                    wave_sync();
+                    scatter_v(rsh, msh, -1.0);
+                    double r2 = 0.0;
+#pragma unroll
+                    for (int t = 0; t < R; ++t) {
+                        const double x = rsh[t * G + g];
+                        r2 += (t * G + g < nIj) ? x * x : 0.0;
+                    }
+                    rr_it = group_sum<G>(r2);
+                    gather_v(rsh, gsh);
+                    for (int c = g; c < NC; c += G) csh[c] = gsh[c] - pen[c] * msh[c];
+                    wave_sync();
+                    const double yy = solve_normal_v(csh, dsh);
+                    // ||b - A(m + d)||^2 = ||r||^2 - 2 d^T A^T r + ||A d||^2, and
+                    // ||A d||^2 = ||R d||^2 - d^T P d with R d = y (second order in d)
+                    double dg = 0.0, pdd = 0.0;
+                    for (int c = g; c < NC; c += G) {
+                        const double d = dsh[c];
+                        dg += d * gsh[c];
+                        pdd += pen[c] * d * d;
+                        msh[c] += d;
+                    }
+                    dg = group_sum<G>(dg);
+                    pdd = group_sum<G>(pdd);
+                    wave_sync();
+                    rr_it = rr_it - 2.0 * dg + (yy - pdd);
+                }
+                rr = rr_it + outj;
+            } else {
+                // ||c2||^2 of the stacked form less m^T P m
+                double pm = 0.0;
+                for (int c = g; c < NC; c += G) pm += pen[c] * msh[c] * msh[c];
+                rr = c2sq - group_sum<G>(pm) + outj;
             }
-            rr += outj;
         }
 
         if constexpr (BACKWARD) {
+            __builtin_amdgcn_sched_barrier(0);
             // r = A m - b is held as rsh = b - A m = -r
+            double* hsh = msh + NC;         // h = 2 A^T r
+            double* dsh = msh + 2 * NC;     // correction of lambda
+            double* tsh = msh + 3 * NC;     // its right side
+            double* lsh = msh + 4 * NC;     // lambda
             double* al = alsh + q * RS;
             reset(rsh, true);
             load_entries();
             wave_sync();
-            scatter(rsh, mfin, -1.0);
+            scatter_v(rsh, msh, -1.0);
             // h = 2 A^T r,  lambda = (A^T A + P)^{-1} h
-            double h[NC], lam[NC];
-            gather(rsh, h);
-#pragma unroll
-            for (int c = 0; c < NC; ++c) h[c] = -2.0 * h[c];
-            solve_normal(h, lam);
+            gather_v(rsh, hsh);
+            for (int c = g; c < NC; c += G) hsh[c] *= -2.0;
+            wave_sync();
+            solve_normal_v(hsh, lsh);
             if constexpr (REFINE) {
 #pragma unroll
                 for (int it = 0; it < 2; ++it) {  // FP64-residual refinement of lambda
                     reset(al, false);
+                    load_entries();   // reloaded per pass: no entries held across the solves
                     wave_sync();
-                    scatter(al, lam, 1.0);
-                    double res[NC], dl[NC];
-                    gather(al, res);
-#pragma unroll
-                    for (int c = 0; c < NC; ++c) res[c] = h[c] - res[c] - pen[c] * lam[c];
-                    solve_normal(res, dl);
-#pragma unroll
-                    for (int c = 0; c < NC; ++c) lam[c] += dl[c];
+                    scatter_v(al, lsh, 1.0);
+                    gather_v(al, tsh);
+                    for (int c = g; c < NC; c += G) tsh[c] = hsh[c] - tsh[c] - pen[c] * lsh[c];
+                    wave_sync();
+                    solve_normal_v(tsh, dsh);
+                    for (int c = g; c < NC; c += G) lsh[c] += dsh[c];
+                    wave_sync();
                 }
             }
             reset(al, false);
+            load_entries();
             wave_sync();
-            scatter(al, lam, 1.0);
+            scatter_v(al, lsh, 1.0);
             // dL/dA at the gathered entries: 2 r m^T - r lambda^T - (A lambda) m^T
             const double dL = a.dL;
             double* cj = a.contrib + eo;
@@ -840,17 +887,22 @@ k_numeric(NumericArgs a) {
             for (int c = 0; c < NC; ++c) {
                 const int e0 = cst[q][c];
                 const int clen = cln[q][c];
+                const double mc = msh[c], lc = lsh[c];
 #pragma unroll
                 for (int u = 0; u < LPL; ++u) {
                     const int p = pp[c][u];
-                    if (g + u * G < clen)
-                        cj[e0 + g + u * G] = dL * (-2.0 * rsh[p] * mfin[c] + rsh[p] * lam[c] - al[p] * mfin[c]);
+                    if (g + u * G < clen) cj[e0 + g + u * G] = dL * (-2.0 * rsh[p] * mc + rsh[p] * lc - al[p] * mc);
                 }
-                const int len = longc ? clen : 0;
-                if (len > LPL * G) {
+            }
+            if (longc) {
+#pragma unroll 1
+                for (int c = 0; c < NC; ++c) {
+                    const int e0 = cst[q][c];
+                    const int len = cln[q][c];
+                    const double mc = msh[c], lc = lsh[c];
                     for (int e = g + LPL * G; e < len; e += G) {
                         const int p = a.posA[eo + e0 + e];
-                        cj[e0 + e] = dL * (-2.0 * rsh[p] * mfin[c] + rsh[p] * lam[c] - al[p] * mfin[c]);
+                        cj[e0 + e] = dL * (-2.0 * rsh[p] * mc + rsh[p] * lc - al[p] * mc);
                     }
                 }
             }
@@ -860,13 +912,12 @@ k_numeric(NumericArgs a) {
                 a.gA0[e] = p != 0xFF ? dL * (2.0 * rsh[p] + al[p]) : dL * 2.0 * a.A0_v[e];
             }
             if (valid) {
-#pragma unroll
-                for (int c = 0; c < NC; ++c) {
-                    if (c < nJ && (c % G) == g) {
+                for (int c = g; c < NC; c += G) {
+                    if (c < nJ) {
                         a.segoff[scol + c] = eo + cst[q][c];
                         if (a.gw) {
                             const double wl = a.w[scol + c];
-                            a.gw[scol + c] = dL * a.mu * lam[c] * mfin[c] / (wl * wl);
+                            a.gw[scol + c] = dL * a.mu * lsh[c] * msh[c] / (wl * wl);
                         }
                     }
                 }
@@ -876,15 +927,28 @@ k_numeric(NumericArgs a) {
 
         // ---- outputs
         bool nonfinite = !isfinite(rr);
+        if constexpr (WEIGHTED) {
+            float bad = 0.f;
+            for (int c = g; c < NC; c += G) bad = (c < nJ && !isfinite(msh[c])) ? 1.f : bad;
+            nonfinite |= group_max<G>(bad) > 0.f;
+        } else {
 #pragma unroll
-        for (int c = 0; c < NC; ++c) nonfinite |= (c < nJ) && !isfinite(mfin[c]);
+            for (int c = 0; c < NC; ++c) nonfinite |= (c < nJ) && !isfinite(mfin[c]);
+        }
         if (valid) {
             if (a.M) {
+                if constexpr (WEIGHTED) {
+                    for (int c = g; c < nJ; c += G) {
+                        if constexpr (REFINE) static_cast<float*>(a.M)[scol + c] = (float)msh[c];
+                        else static_cast<double*>(a.M)[scol + c] = msh[c];
+                    }
+                } else {
 #pragma unroll
-                for (int c = 0; c < NC; ++c) {
-                    if (c < nJ && (c % G) == g) {
-                        if constexpr (REFINE) static_cast<float*>(a.M)[scol + c] = (float)mfin[c];
-                        else static_cast<double*>(a.M)[scol + c] = mfin[c];
+                    for (int c = 0; c < NC; ++c) {
+                        if (c < nJ && (c % G) == g) {
+                            if constexpr (REFINE) static_cast<float*>(a.M)[scol + c] = (float)mfin[c];
+                            else static_cast<double*>(a.M)[scol + c] = mfin[c];
+                        }
                     }
                 }
             }

@@ -283,7 +283,7 @@ size_t seq_layout(Carve& cv, const SeqDims& d, sam_seq* q, PatternWs* pw, void**
 }
 
 sam_status seq_args(sam_ctx* ctx, const sam_csc* A0, const sam_csc* Ak_struct, const sam_pattern_spec* spec,
-                    int32_t n_src, sam_precision prec) {
+                    int32_t n_src, int32_t prec) {
     sam_status st;
     if ((st = check_csc_args(ctx, A0, "A0", true))) return st;
     if ((st = check_csc_args(ctx, Ak_struct, "Ak_struct", false))) return st;
@@ -335,7 +335,7 @@ sam_status seq_dims_base(sam_ctx* ctx, const sam_csc* A0, const sam_csc* Ak_stru
 extern "C" {
 
 sam_status sam_sequence_size(sam_ctx* ctx, const sam_csc* A0, const sam_csc* Ak_struct, const sam_pattern_spec* spec,
-                             int32_t n_src, sam_precision prec, int32_t replan_each_run, void* ws, size_t ws_bytes,
+                             int32_t n_src, int32_t prec, int32_t replan_each_run, void* ws, size_t ws_bytes,
                              size_t* bytes, sam_stream_t stream) {
     if (check_ctx(ctx)) return SAM_ERR_ARG;
     sam_status st;
@@ -358,7 +358,7 @@ sam_status sam_sequence_size(sam_ctx* ctx, const sam_csc* A0, const sam_csc* Ak_
 }
 
 sam_status sam_sequence_create(sam_ctx* ctx, const sam_csc* A0, const sam_csc* Ak_struct, const sam_pattern_spec* spec,
-                               int32_t n_src, sam_precision prec, int32_t replan_each_run, void* mem, size_t mem_bytes,
+                               int32_t n_src, int32_t prec, int32_t replan_each_run, void* mem, size_t mem_bytes,
                                sam_seq** out, sam_stream_t stream) {
     if (check_ctx(ctx)) return SAM_ERR_ARG;
     if (!out) return fail(ctx, SAM_ERR_ARG, "seq is NULL");

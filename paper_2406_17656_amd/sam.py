@@ -306,6 +306,14 @@ class Plan:
                                                   ctypes.byref(by)))
         return {"flops32": f32.value, "flops64": f64.value, "bytes": by.value}
 
+    def cost_weighted(self, prec="f32", backward=False) -> dict:
+        """sam_plan_cost_weighted: algorithmic flops of one weighted build or
+        one adjoint on this plan."""
+        f32 = ctypes.c_double(); f64 = ctypes.c_double()
+        self.ctx.check(self.ctx.lib.sam_plan_cost_weighted(self.h, _prec(prec), 1 if backward else 0,
+                                                           ctypes.byref(f32), ctypes.byref(f64)))
+        return {"flops32": f32.value, "flops64": f64.value}
+
     def _outs(self, prec, M, cols, res2, fro=True):
         dev = self.S_colptr.device
         if M is None:
