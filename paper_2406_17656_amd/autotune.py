@@ -5,8 +5,9 @@ column problem G, rows per lane R, columns NC, LDS tile chunk TC; see
 sam_menu).  A plan buckets each column into the first variant of an ordered
 list that its block fits.  ``tune`` times candidate orders on the plan's own
 shape histogram -- the default order and, for every variant, the order that
-puts it first -- keeps the fastest (sam_plan_select) and caches the choice
-per device, precision and shape signature in a JSON file
+puts it first -- then refines the class boundaries of the fastest by leaving
+classes out and swapping neighbours, keeps the fastest (sam_plan_select) and
+caches the choice per device, precision and shape signature in a JSON file
 ($SAM_TUNE_CACHE, default ~/.cache/sam_mi355x_tune.json).
 """
 from __future__ import annotations
@@ -45,6 +46,14 @@ def candidate_orders(n_variants: int) -> list[list[int]]:
         if o not in out:
             out.append(o)
     return [o[:16] for o in out]
+
+
+def complete(order, prec="f32") -> list[int]:
+    """The order with the menu's other variants appended (at most 16): the
+    listed classes keep every column they fit, and a wider pattern (e.g. the
+    unsparsified bound of a replanned sequence) still finds a class."""
+    rest = [i for i in range(len(menu(prec))) if i not in order]
+    return (list(order) + rest)[:16]
 
 
 def signature(plan, prec) -> str:
@@ -91,7 +100,7 @@ def _store_cache(d: dict) -> None:
         pass
 
 
-def tune(plan, Ak_val, A0_val, prec="f32", reps=10, use_cache=True) -> dict:
+def tune(plan, Ak_val, A0_val, prec="f32", reps=10, use_cache=True, refine=True) -> dict:
     """Pick the fastest variant order for this plan; returns
     {"order", "us", "timings", "cached"} and leaves the plan selected."""
     sig = signature(plan, prec)
@@ -103,16 +112,41 @@ def tune(plan, Ak_val, A0_val, prec="f32", reps=10, use_cache=True) -> dict:
                 "cached": True}
     n_var = len(menu(prec))
     timings = {}
-    best = None
-    for order in candidate_orders(n_var):
+
+    def trial(order):
         try:
             plan.select(order, prec)
         except SamError:
-            continue  # some column fits none of the listed variants
+            return None  # some column fits none of the listed variants
         us = _time(plan, Ak_val, A0_val, prec, reps)
-        timings[",".join(map(str, order[:3]))] = us
-        if best is None or us < best[1]:
+        timings[",".join(map(str, order[:4])) + ("" if len(order) == n_var else f"/{len(order)}")] = us
+        return us
+
+    best = None
+    for order in candidate_orders(n_var):
+        us = trial(order)
+        if us is not None and (best is None or us < best[1]):
             best = (order, us)
+    if refine and best is not None:
+        # Class boundaries: a column goes to the first listed class it fits,
+        # so leaving a class out hands its columns to the next wider one and
+        # swapping two neighbours moves the boundary between them.  Greedy
+        # passes keep a change that is faster by more than 2 %.
+        for _ in range(2):
+            changed = False
+            for v in list(best[0][1:]):
+                cand = [x for x in best[0] if x != v]
+                us = trial(cand)
+                if us is not None and us < 0.98 * best[1]:
+                    best, changed = (cand, us), True
+            for i in range(1, len(best[0]) - 1):
+                cand = list(best[0])
+                cand[i], cand[i + 1] = cand[i + 1], cand[i]
+                us = trial(cand)
+                if us is not None and us < 0.98 * best[1]:
+                    best, changed = (cand, us), True
+            if not changed:
+                break
     plan.select(best[0], prec)
     if use_cache:
         cache[sig] = {"order": best[0], "us": best[1], "timings": timings}

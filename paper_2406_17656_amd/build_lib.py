@@ -23,7 +23,7 @@ ARCH = "gfx950"
 
 SOURCES = ["sam_symbolic.hip", "sam_numeric.hip", "sam_aux.hip", "sam_adjoint.hip", "sam_adaptive.hip", "sam_capi.cpp",
            "sam_sequence.cpp", "sam_backward.cpp", "sam_adaptive_api.cpp", "sam_noalloc.cpp"]
-HEADERS = ["sam_device.hpp", "sam_kernels.hpp", "sam_numeric_args.hpp"]
+HEADERS = ["sam_device.hpp", "sam_kernels.hpp", "sam_numeric_args.hpp", "sam_host.hpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 CFLAGS = [
