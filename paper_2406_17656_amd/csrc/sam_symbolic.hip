@@ -330,13 +330,16 @@ hipError_t sparsify_slots(int n, const int* cp, const int* ri, const double* v, 
 // candidates of column j are the rows of Q(:, l) for l in P(:, j); lane g of
 // the group owns the lists l = P(:, j)[g], P(:, j)[g + GS], ...  The window
 // of candidate rows is swept in chunks of kChunk rows: each chunk gets an
-// LDS bitmap (128 words per column), set with ds_or, counted with popcount
+// LDS bitmap (128 or 256 words per column), set with ds_or, counted with popcount
 // and a prefix scan over the group.  After a chunk the sweep jumps to the
 // smallest candidate beyond it, so only occupied chunks cost anything,
 // whatever the bandwidth.
 
-constexpr int kChunkWords = 128;
-constexpr int kChunk = kChunkWords * 32;  // 4096 rows
+// Chunk of the sweep: 4096 rows for eight lanes per column, 8192 for
+// sixteen (the 9-point and 3D stencils, whose level-2 row sets span six grid
+// lines or planes: at 4096 rows a 1024^2 9-point column took two chunks).
+template <int GS>
+constexpr int chunk_words() { return GS == 16 ? 256 : 128; }
 constexpr int kSymThreads = 256;
 
 template <int CTRL>
@@ -435,6 +438,8 @@ template <int MODE, int GS, int ROUNDS, int kListLen>
 __global__ void __launch_bounds__(kSymThreads)
 k_union(UnionArgs a) {
     constexpr int kGroups = kSymThreads / GS;
+    constexpr int kChunkWords = chunk_words<GS>();
+    constexpr int kChunk = kChunkWords * 32;
     constexpr int kWPL = kChunkWords / GS;   // bitmap words per lane
     // group stride padded by GS words: the groups of a wave start on
     // different banks
@@ -630,7 +635,7 @@ k_union(UnionArgs a) {
 // columns per wave either way, the most a CU's LDS holds at once); then 16
 // lanes with two lists each (32 lists in registers); beyond that the memory
 // loops.  The rows held per list follow the longest list
-// (5, 8 or 12; longer lists take the memory loops).  Bounds <= 0: unknown.
+// (5, 8, 9 or 12; longer lists take the memory loops).  Bounds <= 0: unknown.
 template <int MODE, int LEN>
 static hipError_t launch_union_len(const UnionArgs& a, int max_lists, hipStream_t s) {
     auto grid = [&](int gs) {
@@ -650,6 +655,7 @@ template <int MODE>
 static hipError_t launch_union(const UnionArgs& a, int max_lists, int max_len, hipStream_t s) {
     if constexpr (MODE != kModeCount) {   // the count pass (one-shot patterns) keeps 8 rows
         if (max_len > 0 && max_len <= 5) return launch_union_len<MODE, 5>(a, max_lists, s);
+        if (max_len == 9) return launch_union_len<MODE, 9>(a, max_lists, s);   // 9-point stencils
         if (max_len > 8) return launch_union_len<MODE, 12>(a, max_lists, s);
     }
     return launch_union_len<MODE, 8>(a, max_lists, s);
