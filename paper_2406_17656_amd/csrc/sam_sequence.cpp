@@ -28,6 +28,10 @@ struct sam_seq {
     int prec = 1;  // 0 FP64, 1 FP32 + refinement
     sam_pattern_spec spec{};
     bool replan = false;
+    // B = S(A~_k) is A_k's own structure: nothing is dropped (no
+    // sparsification) and every column of A_k holds its diagonal, so the
+    // level expansion reads A_k's column lists directly
+    bool b_is_a = false;
     const int *A0_cp = nullptr, *A0_ri = nullptr, *Ak_cp = nullptr, *Ak_ri = nullptr;
     const double* A0_val = nullptr;
     int nnzA = 0, nnzA0 = 0;
@@ -139,16 +143,22 @@ sam_status enqueue_symbolic(sam_seq* q, int k, sam_seq::Scratch& R, const double
     auto level_cp = [&](int lev) { return lcp + (size_t)lev * (n + 1); };
     int* Scp = q->Sk_cp[k];
     int* Sri = q->Sk_ri[k];
-    // B = S(A~_k) plus the diagonal, in the slots of the structural B
+    // B = S(A~_k) plus the diagonal, in the slots of the structural B (whose
+    // column pointers are A_k's when B is A_k's structure: its lists are
+    // then read in place, lengths from the column pointers)
     int* b_ri = p == 1 ? R.F_ri : R.B_ri;
     int* b_cnt = p == 1 ? R.F_cnt : R.B_cnt;
-    HIP_TRY(ctx, samk::sparsify_slots(n, q->Ak_cp, q->Ak_ri, vals, sp, R.D, level_cp(0), b_ri, b_cnt, s));
-    const int* cur_ri = b_ri;
-    const int* cur_cnt = b_cnt;
+    const bool direct = q->b_is_a && p > 1;
+    if (!direct)
+        HIP_TRY(ctx, samk::sparsify_slots(n, q->Ak_cp, q->Ak_ri, vals, sp, R.D, level_cp(0), b_ri, b_cnt, s));
+    const int* Bq_ri = direct ? q->Ak_ri : R.B_ri;
+    const int* Bq_cnt = direct ? nullptr : R.B_cnt;
+    const int* cur_ri = direct ? q->Ak_ri : b_ri;
+    const int* cur_cnt = direct ? nullptr : b_cnt;
     for (int lev = 1; lev < p; ++lev) {
         int* dri = lev == p - 1 ? R.F_ri : R.L_ri[lev & 1];
         int* dcnt = lev == p - 1 ? R.F_cnt : R.L_cnt[lev & 1];
-        HIP_TRY(ctx, samk::expand_slots(n, level_cp(lev - 1), cur_cnt, cur_ri, level_cp(0), R.B_cnt, R.B_ri,
+        HIP_TRY(ctx, samk::expand_slots(n, level_cp(lev - 1), cur_cnt, cur_ri, level_cp(0), Bq_cnt, Bq_ri,
                                         level_cp(lev), dri, dcnt, q->levels.maxcol[(size_t)lev - 1],
                                         q->levels.maxcol[0], s));
         cur_ri = dri;
@@ -420,6 +430,11 @@ sam_status sam_sequence_create(sam_ctx* ctx, const sam_csc* A0, const sam_csc* A
         if (res.nnz != d.nnzS) return bail(fail(ctx, SAM_ERR_HIP, "structural pattern changed between two counts"));
         if ((st = pattern_fill(ctx, n, res, q->S_cp, q->S_ri, s))) return bail(st);
         q->nnzS = res.nnz;
+        // B = A_k's structure plus the diagonal: as many entries as A_k
+        // means no diagonal was added, and the level-0 column pointers are
+        // A_k's (both ascending, the same rows)
+        q->b_is_a = spec->kind == SAM_SPARSIFY_NONE && !q->levels.nnz.empty() &&
+                    q->levels.nnz[0] == (int64_t)Ak_struct->nnz;
     }
     {
         sam_csc skel = *Ak_struct;
