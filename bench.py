@@ -157,6 +157,37 @@ def adjoint_variant(ctx, P, torch, log, reps=10):
     return adj
 
 
+def ninepoint_variant(ctx, P, torch, log, steps=5, warmup=2):
+    """The ragged workload: the 1024^2 9-point sequence of 16 matrices (15
+    sources), global threshold 0.1 then level 2, replanned per source in one
+    HIP graph with the autotuned size classes, timed like the step."""
+    from paper_2406_17656_amd import DeviceCSC
+    spec = WORKLOADS["ninepoint2d"]["spec"]
+    A0h, Ash = P.config4()
+    dA0 = DeviceCSC.from_host(A0h)
+    dAk = [DeviceCSC.from_host(A) for A in Ash]
+    vals = [d.val for d in dAk]
+    res = tune_order(ctx, dAk[0], dA0, "f32", 2, spec)
+    seq = step_sequence(ctx, dA0, dAk[0], len(Ash), "f32", 2, spec, res["order"])
+    Ms = seq.alloc_maps()
+    res2 = torch.zeros(len(Ash), dtype=torch.float64, device="cuda")
+    for _ in range(warmup):
+        seq.run(vals, Ms, res2)
+    ctx.sync_status()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        seq.run(vals, Ms, res2)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / steps
+    ctx.sync_status()
+    seq.close()
+    cols = A0h.n * len(Ash)
+    log(f"9-point 1024^2: {wall * 1e3:.2f} ms per step, {cols / wall / 1e6:.1f} M columns/s")
+    return {"n": A0h.n, "maps": len(Ash), "cols_per_s": cols / wall, "ms_per_step": wall * 1e3,
+            "order": res["order"][:4]}
+
+
 def level1_cold(ctx, P, torch, log, copies=7, rounds=6):
     """The level-1 (13 x 5 blocks) numeric build, the HBM-class case, on a
     working set larger than the 256 MB last-level cache: `copies` maps of the
@@ -498,6 +529,8 @@ def main():
                                           "ms_whole_pipeline": dt * 1e3}
         variants["adaptive_map0"] = ad
         variants["adjoint_48cubed"] = adjoint_variant(ctx, P, torch, log)
+        log("timing: 1024^2 9-point sequence, global threshold 0.1 then level 2 (ragged classes)")
+        variants["f32_ninepoint_1024_replanned"] = ninepoint_variant(ctx, P, torch, log)
     else:
         plan.close()
     rel_res = [float(np.sqrt(r / a02)) for r in r2_f32]
