@@ -188,6 +188,40 @@ def ninepoint_variant(ctx, P, torch, log, steps=5, warmup=2):
             "order": res["order"][:4]}
 
 
+def apply_variant(ctx, plan, dA0, dAk0, Scp, Sri, torch, reps=50):
+    """y = M x for the first source's FP32 level-2 map (the product of a
+    Krylov iteration), timed with HIP events: with M's values read through
+    the row view's permutation, and with them put in row order once
+    (sam_apply_permute).  Bytes: row pointers, column indices, values
+    (and the permutation), x and y, each read or written once."""
+    n = dA0.n
+    M = torch.empty(max(Sri.numel(), 1), dtype=torch.float32, device="cuda")
+    plan.build(dAk0.val, dA0.val, "f32", M=M, fro=False)
+    T = ctx.apply_prepare(n, Scp, Sri)
+    Tv = ctx.apply_permute(T, M, "f32")
+    x = torch.ones(n, dtype=torch.float64, device="cuda")
+    y = torch.empty(n, dtype=torch.float64, device="cuda")
+    nnz = int(Sri.numel())
+    out = {"n": n, "nnz": nnz}
+    for name, vals, permuted in (("perm", M, False), ("row_order", Tv, True)):
+        ctx.apply(T, vals, x, "f32", y=y, permuted=permuted)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            ctx.apply(T, vals, x, "f32", y=y, permuted=permuted)
+        e1.record()
+        torch.cuda.synchronize()
+        us = e0.elapsed_time(e1) / reps * 1e3
+        by = 4 * (n + 1) + 4 * nnz + 4 * nnz + (0 if permuted else 4 * nnz) + 8 * n + 8 * n
+        out[f"{name}_us"] = us
+        out[f"{name}_algorithmic_bytes"] = by
+        out[f"{name}_hbm_frac"] = by / us / 1e3 / PEAK["hbm_GBs"]
+    ctx.sync_status()
+    return out
+
+
 def level1_cold(ctx, P, torch, log, copies=7, rounds=6):
     """The level-1 (13 x 5 blocks) numeric build, the HBM-class case, on a
     working set larger than the 256 MB last-level cache: `copies` maps of the
@@ -422,6 +456,9 @@ def main():
         plan.select(tuned_order("f64", 2), "f64")
         b64 = time_build("f64")
         variants["f64_level2_numeric_build_us"] = b64 * 1e3
+        plan.select(order32, "f32")
+        log("timing: y = M x on the first map (sam_apply)")
+        variants["f32_level2_apply"] = apply_variant(ctx, plan, dA0, dAk[0], Scp, Sri, torch)
         plan.close()
         for prec in ("f32", "f64"):
             for power in (1, 2):

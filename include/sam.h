@@ -365,9 +365,20 @@ sam_status sam_apply_prepare(sam_ctx* ctx, int32_t n, const int32_t* M_colptr,
                              int32_t* T_colind, int32_t* T_perm, void* ws, size_t ws_bytes,
                              sam_stream_t stream);
 
-/* y = M x (the map applied inside a Krylov iteration), FP64 accumulation in
- * ascending column order per row (bitwise reproducible).  M_val is double or
- * float per prec.  Allocates nothing. */
+/* T_val[e] = M_val[T_perm[e]] for e in [0, nnz): M's values in the row
+ * view's order, so that sam_apply with T_perm = NULL reads them as contiguous
+ * runs (one pass per map, before the Krylov iterations that apply it).
+ * M_val and T_val (nnz values, caller-owned) are double or float per prec.
+ * Asynchronous; allocates nothing. */
+sam_status sam_apply_permute(sam_ctx* ctx, int64_t nnz, const int32_t* T_perm,
+                             const void* M_val, int32_t prec, void* T_val, sam_stream_t stream);
+
+/* y = M x (the map applied inside a Krylov iteration; Section 1: the map
+ * updates a preconditioner), FP64 accumulation: four lanes per row, each
+ * summing every fourth entry of the row in ascending order, then the four
+ * partials in a fixed order (bitwise reproducible from call to call).  M_val
+ * is double or float per prec; T_perm = NULL means M_val is already in the
+ * row view's order (sam_apply_permute).  Allocates nothing. */
 sam_status sam_apply(sam_ctx* ctx, int32_t n, const int32_t* T_rowptr, const int32_t* T_colind,
                      const int32_t* T_perm, const void* M_val, int32_t prec,
                      const double* x, double* y, sam_stream_t stream);

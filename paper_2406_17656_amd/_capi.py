@@ -82,6 +82,7 @@ SIGNATURES = {
     "sam_apply_workspace_size": (c_int32, [c_int32, SZ]),
     "sam_apply_prepare": (c_int32, [P, c_int32, P, P, c_int64, P, P, P, P, c_size_t, P]),
     "sam_apply": (c_int32, [P, c_int32, P, P, P, P, c_int32, P, P, P]),
+    "sam_apply_permute": (c_int32, [P, c_int64, P, P, c_int32, P, P]),
     "sam_sequence_size": (c_int32, [P, CSCP, CSCP, SPECP, c_int32, c_int32, c_int32, P, c_size_t, SZ, P]),
     "sam_sequence_create": (c_int32, [P, CSCP, CSCP, SPECP, c_int32, c_int32, c_int32, P, c_size_t,
                                       ctypes.POINTER(c_void_p), P]),

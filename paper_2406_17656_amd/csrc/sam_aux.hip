@@ -201,13 +201,32 @@ __global__ void k_tsort(int n, const int* rowptr, int* colind, int* perm) {
     }
 }
 
-__global__ void k_spmv_rows(int n, const int* rowptr, const int* colind, const int* perm, const void* val,
-                            int f32, const double* x, double* y) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+// y = M x over the row view: kSpmvLanes lanes per row, so that the lanes of
+// a wave read each row's column indices (and values) as one contiguous run
+// instead of one entry of 64 different rows.  Lane g sums entries g, g + 4,
+// ... of its row in ascending order; the four partials are added by the
+// quad exchanges of group_sum (the same order on every call).  perm == null:
+// the values are in the row view's order.
+constexpr int kSpmvLanes = 4;
+__global__ void __launch_bounds__(256)
+k_spmv_rows(int n, const int* rowptr, const int* colind, const int* perm, const void* val, int f32,
+            const double* x, double* y) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = t / kSpmvLanes, g = t % kSpmvLanes;
     double s = 0.0;
-    for (int e = rowptr[i]; e < rowptr[i + 1]; ++e) s += mval(val, perm[e], f32) * x[colind[e]];
-    y[i] = s;
+    if (i < n) {
+        const int b = rowptr[i + 1];
+        for (int e = rowptr[i] + g; e < b; e += kSpmvLanes) s += mval(val, perm ? perm[e] : e, f32) * x[colind[e]];
+    }
+    s = group_sum<kSpmvLanes>(s);   // every lane takes part: rows past n add zeros
+    if (i < n && g == 0) y[i] = s;
+}
+
+__global__ void k_permute_vals(int64_t nnz, const int* perm, const void* val, int f32, void* out) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= nnz) return;
+    if (f32) static_cast<float*>(out)[e] = static_cast<const float*>(val)[perm[e]];
+    else static_cast<double*>(out)[e] = static_cast<const double*>(val)[perm[e]];
 }
 
 }  // namespace
@@ -263,8 +282,16 @@ hipError_t transpose_sort_rows(int n, const int* rowptr, int* colind, int* perm,
 hipError_t spmv_rows(int n, const int* rowptr, const int* colind, const int* perm, const void* val,
                      int val_f32, const double* x, double* y, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_spmv_rows, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, rowptr, colind,
+    const int64_t threads = (int64_t)n * kSpmvLanes;
+    hipLaunchKernelGGL(k_spmv_rows, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, n, rowptr, colind,
                        perm, val, val_f32, x, y);
+    return hipGetLastError();
+}
+
+hipError_t permute_vals(int64_t nnz, const int* perm, const void* val, int val_f32, void* out, hipStream_t s) {
+    if (nnz <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_permute_vals, dim3((unsigned)((nnz + 255) / 256)), dim3(256), 0, s, nnz, perm, val,
+                       val_f32, out);
     return hipGetLastError();
 }
 

@@ -975,12 +975,24 @@ sam_status sam_apply_prepare(sam_ctx* ctx, int32_t n, const int32_t* M_colptr, c
     return SAM_OK;
 }
 
+sam_status sam_apply_permute(sam_ctx* ctx, int64_t nnz, const int32_t* T_perm, const void* M_val, int32_t prec,
+                             void* T_val, sam_stream_t stream) {
+    if (check_ctx(ctx)) return SAM_ERR_ARG;
+    if (nnz < 0) return fail(ctx, SAM_ERR_ARG, "negative size");
+    if (!prec_ok(prec)) return fail(ctx, SAM_ERR_ARG, "unknown precision %d", (int)prec);
+    if (nnz > 0 && (!T_perm || !M_val || !T_val)) return fail(ctx, SAM_ERR_ARG, "NULL argument");
+    sam_status st = need_device(ctx);
+    if (st) return st;
+    HIP_TRY(ctx, samk::permute_vals(nnz, T_perm, M_val, prec == SAM_PREC_F32_REFINE, T_val, S(stream)));
+    return SAM_OK;
+}
+
 sam_status sam_apply(sam_ctx* ctx, int32_t n, const int32_t* T_rowptr, const int32_t* T_colind, const int32_t* T_perm,
                      const void* M_val, int32_t prec, const double* x, double* y, sam_stream_t stream) {
     if (check_ctx(ctx)) return SAM_ERR_ARG;
     if (n < 0) return fail(ctx, SAM_ERR_ARG, "negative size");
     if (!prec_ok(prec)) return fail(ctx, SAM_ERR_ARG, "unknown precision %d", (int)prec);
-    if (n > 0 && (!T_rowptr || !T_colind || !T_perm || !M_val || !x || !y)) return fail(ctx, SAM_ERR_ARG, "NULL argument");
+    if (n > 0 && (!T_rowptr || !T_colind || !M_val || !x || !y)) return fail(ctx, SAM_ERR_ARG, "NULL argument");
     sam_status st = need_device(ctx);
     if (st) return st;
     HIP_TRY(ctx, samk::spmv_rows(n, T_rowptr, T_colind, T_perm, M_val, prec == SAM_PREC_F32_REFINE, x, y, S(stream)));

@@ -125,6 +125,8 @@ hipError_t transpose_fill(int n, const int* cp, const int* ri, const int* rowptr
 hipError_t transpose_sort_rows(int n, const int* rowptr, int* colind, int* perm, hipStream_t s);
 hipError_t spmv_rows(int n, const int* rowptr, const int* colind, const int* perm,
                      const void* val, int val_f32, const double* x, double* y, hipStream_t s);
+hipError_t permute_vals(int64_t nnz, const int* perm, const void* val, int val_f32, void* out,
+                        hipStream_t s);
 
 // ---------------------------------------------------------------- adjoint
 // gAk[f] = sum over the S entries (l, j) with l the column of entry f, in

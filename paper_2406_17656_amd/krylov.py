@@ -20,14 +20,16 @@ from .sam import Context, DeviceCSC
 
 
 class SparseOp:
-    """y = A x for a CSC matrix held on the device (values double or float)."""
+    """y = A x for a CSC matrix held on the device (values double or float);
+    the values are put in the row view's order once (sam_apply_permute)."""
 
     def __init__(self, ctx: Context, n: int, colptr, rowind, val, prec="f64"):
-        self.ctx, self.val, self.prec = ctx, val, prec
+        self.ctx, self.prec = ctx, prec
         self.T = ctx.apply_prepare(n, colptr, rowind)
+        self.val = ctx.apply_permute(self.T, val, prec)
 
     def __call__(self, x):
-        return self.ctx.apply(self.T, self.val, x, self.prec)
+        return self.ctx.apply(self.T, self.val, x, self.prec, permuted=True)
 
 
 def jacobi_diag(A: DeviceCSC) -> torch.Tensor:

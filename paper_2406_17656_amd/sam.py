@@ -201,13 +201,24 @@ class Context:
                                               _ptr(ci), _ptr(pm), _ptr(ws), nb, self.stream()))
         return rp, ci, pm
 
-    def apply(self, T, M_val, x, prec="f64", y=None):
+    def apply_permute(self, T, M_val, prec="f64"):
+        """M's values in the row view's order (sam_apply_permute), for
+        apply(..., permuted=True)."""
+        pm = T[2]
+        nnz = int(M_val.numel())
+        out = torch.empty_like(M_val)
+        self.check(self.lib.sam_apply_permute(self.h, nnz, _ptr(pm), _ptr(M_val), _prec(prec), _ptr(out),
+                                              self.stream()))
+        return out
+
+    def apply(self, T, M_val, x, prec="f64", y=None, permuted=False):
+        """y = M x; permuted: M_val comes from apply_permute (row order)."""
         rp, ci, pm = T
         n = rp.numel() - 1
         if y is None:
             y = torch.empty(n, dtype=torch.float64, device=x.device)
-        self.check(self.lib.sam_apply(self.h, n, _ptr(rp), _ptr(ci), _ptr(pm), _ptr(M_val), _prec(prec),
-                                      _ptr(x), _ptr(y), self.stream()))
+        self.check(self.lib.sam_apply(self.h, n, _ptr(rp), _ptr(ci), None if permuted else _ptr(pm), _ptr(M_val),
+                                      _prec(prec), _ptr(x), _ptr(y), self.stream()))
         return y
 
     # -- adaptive patterns (future work of the paper, end of Section 2)

@@ -178,9 +178,17 @@ def test_apply(ctx, prec):
     Mt = torch.as_tensor(M.astype(np.float32 if prec == "f32" else np.float64)).cuda()
     x = np.random.default_rng(2).standard_normal(Ak.n)
     T = ctx.apply_prepare(Ak.n, Scp, Sri)
-    y = ctx.apply(T, Mt, torch.as_tensor(x).cuda(), prec)
+    xt = torch.as_tensor(x).cuda()
+    y = ctx.apply(T, Mt, xt, prec)
     Mref = host(Mt).astype(np.float64)
-    assert np.allclose(host(y), O.apply(Sp, Mref, x), rtol=1e-13, atol=1e-13)
+    yref = O.apply(Sp, Mref, x)
+    assert np.allclose(host(y), yref, rtol=1e-13, atol=1e-13)
+    # values in the row view's order: the same sums, bit for bit
+    Tv = ctx.apply_permute(T, Mt, prec)
+    assert np.array_equal(host(Tv), host(Mt)[host(T[2])])
+    y2 = ctx.apply(T, Tv, xt, prec, permuted=True)
+    assert np.array_equal(host(y2), host(y))
+    assert np.array_equal(host(ctx.apply(T, Mt, xt, prec)), host(y))   # reproducible
     # the row view is a permutation of the entries, columns ascending per row
     rp, ci, pm = (host(t) for t in T)
     assert np.array_equal(np.sort(pm), np.arange(Sp.nnz))
