@@ -63,11 +63,39 @@ def test_sequence_structural(ctx, prec, replan):
 
 @pytest.mark.parametrize("power", [1, 3])
 def test_sequence_replanned_powers(ctx, power):
-    """Power 1 (B is the pattern: no fused pass) and power 3 (an
-    intermediate level, then the last level fused with the row sets)."""
+    """Power 1 (B is the pattern) and power 3 (an intermediate level
+    between B and S)."""
     A0, As = P.config2(m=24, nmat=3)
     seq, dAs, Ms, res2 = run_seq(ctx, A0, As, "f32", replan=True, power=power)
     check_maps(ctx, seq, A0, As, Ms, res2, "f32", power)
+    seq.close()
+
+
+def drop_diagonals(A, cols):
+    """A copy of A without the stored diagonal entries of the given columns."""
+    keep = np.ones(A.nnz, dtype=bool)
+    for j in cols:
+        a, b = A.colptr[j], A.colptr[j + 1]
+        hit = np.nonzero(A.rowind[a:b] == j)[0]
+        keep[a + hit] = False
+    counts = np.diff(A.colptr) - np.bincount(np.repeat(np.arange(A.n), np.diff(A.colptr))[~keep], minlength=A.n)
+    return P.CSC(A.n, np.concatenate([[0], np.cumsum(counts)]).astype(np.int32),
+                 A.rowind[keep].copy(), A.val[keep].copy())
+
+
+@pytest.mark.parametrize("missing", [False, True])
+def test_sequence_replanned_diagonals(ctx, missing):
+    """No sparsification, replanned: with every diagonal stored B = S(A_k) is
+    A_k's own structure and its lists are read in place; with some diagonals
+    missing B adds them and goes through its slots.  Both against the
+    oracle, whose S(A~) always keeps the diagonal."""
+    A0, As = P.config2(m=20, nmat=5)
+    if missing:
+        cols = [0, 7, 55, 199, 399]
+        As = [drop_diagonals(A, cols) for A in As]
+        assert all(A.nnz == As[0].nnz for A in As)
+    seq, dAs, Ms, res2 = run_seq(ctx, A0, As, "f32", replan=True, power=2)
+    check_maps(ctx, seq, A0, As, Ms, res2, "f32", 2)
     seq.close()
 
 
