@@ -253,10 +253,10 @@ sam_status sam_plan_cost(const sam_plan* plan, int32_t prec, double* flops32, do
 /* Algorithmic cost of one sam_build_weighted (backward = 0) or one
  * sam_backward (backward = 1) on this plan (host outputs, may be NULL):
  * flops of the stacked (|I_j| + |J_j|) x |J_j| Householder QR, Q^T b and the
- * solves (FP32 in SAM_PREC_F32_REFINE), and of the FP64 refinement passes
- * (two steps: r = b - A m, ||r||^2, A^T r, P m).  The adjoint adds the
- * three normal-equation solves of lambda, its residual passes and five
- * flops per gathered entry for the A_k contributions. */
+ * solves (FP32 in SAM_PREC_F32_REFINE), and of the FP64 refinement pass
+ * (one step: r = b - A m, ||r||^2, A^T r, P m).  The adjoint adds the two
+ * normal-equation solves of lambda, its residual passes and five flops per
+ * gathered entry for the A_k contributions. */
 sam_status sam_plan_cost_weighted(const sam_plan* plan, int32_t prec, int32_t backward, double* flops32,
                                   double* flops64);
 
@@ -442,7 +442,7 @@ sam_status sam_sequence_run(sam_seq* seq, const double* const* Ak_vals, void* co
  *     p_l = mu (1/w_l - 1),  w in (0, 1] aligned with S's entries,
  * as the stacked least-squares problem [A; diag(sqrt p)] (w = 1 leaves an
  * entry unpenalised, w -> 0 removes it).  col_res2 / res2 exclude the
- * penalty.  Only SAM_PREC_F32_REFINE (with two refinement steps) and
+ * penalty.  Only SAM_PREC_F32_REFINE (with one refinement step) and
  * SAM_PREC_F64 are accepted.  Allocates nothing. */
 sam_status sam_build_weighted(sam_plan* plan, const double* Ak_val, const double* A0_val,
                               const double* w, double mu, int32_t prec, void* M_val,

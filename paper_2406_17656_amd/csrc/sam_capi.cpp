@@ -825,17 +825,17 @@ sam_status sam_plan_cost_weighted(const sam_plan* plan, int32_t prec, int32_t ba
     const bool f32 = prec == SAM_PREC_F32_REFINE;
     const double nS = (double)plan->nnzS;
     // QR of the stacked (r + c) x c block and Q^T b, then one triangular
-    // solve; FP32 + refinement adds two steps of two solves (FP32) and of
+    // solve; FP32 + refinement adds one step of two solves (FP32) and of
     // r = b - A m, ||r||^2, A^T r and P m (FP64)
     const double qr = 2.0 * (plan->m_rc2 + plan->m_c3) - 2.0 / 3.0 * plan->m_c3 + 4.0 * (plan->m_rc + plan->m_c2);
-    double q32 = f32 ? qr + 5.0 * plan->m_c2 : 0.0;
-    double q64 = f32 ? 8.0 * plan->m_rc + 4.0 * plan->m_r + 4.0 * nS : qr + plan->m_c2;
+    double q32 = f32 ? qr + 3.0 * plan->m_c2 : 0.0;
+    double q64 = f32 ? 4.0 * plan->m_rc + 2.0 * plan->m_r + 2.0 * nS : qr + plan->m_c2;
     if (backward) {
-        // lambda: three normal-equation solves (two refinement steps), the
-        // residual and A^T r, two scatter/gather pairs, the final A lambda,
+        // lambda: two normal-equation solves (one refinement step), the
+        // residual and A^T r, one scatter/gather pair, the final A lambda,
         // and five flops per gathered entry for the contributions
-        const double s32 = 6.0 * plan->m_c2;
-        const double s64 = 14.0 * plan->m_rc + 4.0 * nS + 5.0 * (double)plan->E;
+        const double s32 = 4.0 * plan->m_c2;
+        const double s64 = 10.0 * plan->m_rc + 3.0 * nS + 5.0 * (double)plan->E;
         if (f32) {
             q32 += s32;
             q64 += s64;

@@ -110,6 +110,9 @@ k_numeric(NumericArgs a) {
     // of the plain map (see the stages below); only they double-buffer the
     // column extents.
     constexpr bool PIPE = NC >= 8 && NC <= 13 && MODE == 0;
+    // FP64-residual refinement steps of the weighted forms (m, and the
+    // adjoint's lambda)
+    constexpr int kWSteps = 1;
     // gather staging in the QR's precision; afterwards the weighted and
     // adjoint forms reuse the same memory for the FP64 residual vector
     // (P * RS doubles; the plain map forms its residual over b instead)
@@ -800,12 +803,12 @@ k_numeric(NumericArgs a) {
             double* csh = msh + 3 * NC;
             back_solve_v(bq, msh);          // R m = c1
             if constexpr (REFINE) {
-                // two refinement steps on the normal equations
+                // refinement steps on the normal equations
                 // (A^T A + P) m = A^T b with the residual in FP64:
                 // r = b - A m,  m += R^{-1} R^{-T} (A^T r - P m)
                 double rr_it = 0.0;
 #pragma unroll
-                for (int it = 0; it < 2; ++it) {
+                for (int it = 0; it < kWSteps; ++it) {
                     reset(rsh, true);
                     load_entries();
                     wave_sync();
@@ -863,7 +866,7 @@ k_numeric(NumericArgs a) {
             solve_normal_v(hsh, lsh);
             if constexpr (REFINE) {
 #pragma unroll
-                for (int it = 0; it < 2; ++it) {  // FP64-residual refinement of lambda
+                for (int it = 0; it < kWSteps; ++it) {  // FP64-residual refinement of lambda
                     reset(al, false);
                     load_entries();   // reloaded per pass: no entries held across the solves
                     wave_sync();
