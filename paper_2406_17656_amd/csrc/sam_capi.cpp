@@ -512,7 +512,10 @@ sam_status run_numeric(sam_plan* pl, const double* Ak_val, const double* A0_val,
         const NumericVariant* v = cb.variants[b];
         a.bucket = (int)b;
         int groups = (cnt + v->per_wave() - 1) / v->per_wave();
-        int grid = std::min(groups, ctx->CUs * resident_blocks(ctx, v));
+        // one round of resident blocks for the plain maps; the weighted
+        // forms run faster over two rounds (as the adjoint's launch)
+        const int per_cu = weighted ? std::min(16, 2 * resident_blocks(ctx, v)) : resident_blocks(ctx, v);
+        int grid = std::min(groups, ctx->CUs * per_cu);
         if (grid >= 64) grid = grid / 8 * 8;
         if (res2 && parts + grid > pl->partcap)
             return fail(ctx, SAM_ERR_HIP, "partial-sum buffer too small (%d blocks)", parts + grid);

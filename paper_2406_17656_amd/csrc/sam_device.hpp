@@ -52,6 +52,12 @@ __device__ inline double dpp(double v) {
     return *reinterpret_cast<double*>(&q);
 }
 
+// xor-8 exchange inside 32-lane halves (ds_swizzle bitmask mode:
+// and_mask = 0x1F, or_mask = 0, xor_mask = 0x08): the LDS pipe's form of the
+// last exchange of a 16-lane sum.
+__device__ inline float xor8(float v) {
+    return __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), 0x201F));
+}
 // xor-16 exchange inside 32-lane halves (ds_swizzle bitmask mode:
 // and_mask = 0x1F, or_mask = 0, xor_mask = 0x10).
 __device__ inline float xor16(float v) {
@@ -87,6 +93,23 @@ __device__ inline T group_sum(T v) {
     if constexpr (G >= 32) v += xor16(v);
     if constexpr (G >= 64) v += xor32(v);
     return v;
+}
+
+// group_sum for FP32 with the exchange between the two 8-lane halves of a
+// 16-lane group taken through the LDS pipe (ds_swizzle) instead of a DPP move
+// and an add on the VALU: for kernels whose VALU is saturated and whose sums
+// are not on the critical path.  The result equals group_sum's (each lane
+// adds the same two half sums).
+template <int G>
+__device__ inline float group_sum_x(float v) {
+    if constexpr (G == 16) {
+        v += dpp<0xB1>(v);
+        v += dpp<0x4E>(v);
+        v += dpp<0x141>(v);
+        return v + xor8(v);
+    } else {
+        return group_sum<G>(v);
+    }
 }
 
 template <int G, typename T>

@@ -484,9 +484,24 @@ k_numeric(NumericArgs a) {
                 TQ wb = 0;
 #pragma unroll
                 for (int t = tk; t < R; ++t) wb += v[t] * bq[t];
+                // sigma scales whichever is shorter: the reduced dot products
+                // (one per trailing column and b) or this lane's rows of v.
+                // FP64 blocks, and FP32 blocks of more than 100 entries per
+                // lane, keep the per-column scaling: scaling v changes their
+                // schedule and costs them a wave slot or scratch.
+                const bool scale_v = REFINE && R * NC <= 100 && (NC - k) > (R - tk);
 #pragma unroll
-                for (int c = k + 1; c < NC; ++c) w[c] = group_sum<G>(w[c]) * sigma;
-                wb = group_sum<G>(wb) * sigma;
+                for (int c = k + 1; c < NC; ++c) {
+                    TQ wc;
+                    if constexpr (REFINE && MODE == 1) wc = group_sum_x<G>(w[c]);
+                    else wc = group_sum<G>(w[c]);
+                    w[c] = scale_v ? wc : wc * sigma;
+                }
+                wb = scale_v ? group_sum<G>(wb) : group_sum<G>(wb) * sigma;
+                if (scale_v) {
+#pragma unroll
+                    for (int t = tk; t < R; ++t) v[t] *= sigma;
+                }
 #pragma unroll
                 for (int c = k + 1; c < NC; ++c)
 #pragma unroll
