@@ -26,8 +26,8 @@
 //
 // Soft weights (WEIGHTED): the block is extended by the rows diag(sqrt(p_l)),
 // p_l = mu (1/w_l - 1); the QR of the stacked matrix is taken in two stages
-// (A, then R_1 on the penalty rows), so a variant must have
-// G*R >= max(|I_j|, 2|J_j|); the residual excludes the penalty.
+// (A, then R_1 with the penalty of column c on row NC + c), so a variant
+// must have G*R >= max(|I_j|, 2 NC); the residual excludes the penalty.
 #include "sam_device.hpp"
 #include "sam_kernels.hpp"
 
@@ -106,6 +106,7 @@ k_numeric(NumericArgs a) {
     constexpr int RS = RX + (((G - RX) % 16) + 16) % 16;
     constexpr bool REFINE = std::is_same<TQ, float>::value;
     static_assert(TC >= 1, "tile chunk");
+    static_assert(!WEIGHTED || 2 * NC <= RM, "penalty rows NC .. 2 NC - 1");
     // Per-group metadata is software-pipelined for blocks of 8 to 13 columns
     // of the plain map (see the stages below); only they double-buffer the
     // column extents.
@@ -384,13 +385,14 @@ k_numeric(NumericArgs a) {
         // Soft weights: the penalised problem min ||A m - b||^2 + m^T P m is
         // the least-squares problem of the stacked [A; diag(sqrt p)].  Its QR
         // is taken in two stages: the QR of A, then the QR of
-        // [R_1; diag(sqrt p)] (rows 0..|J_j|-1: R_1 without the reflectors
-        // below its diagonal; rows |J_j|..2|J_j|-1: the penalty rows), so a
-        // block needs max(|I_j|, 2|J_j|) rows, not |I_j| + |J_j|.  The right
+        // [R_1; diag(sqrt p)] (rows 0..|J_j|-1: R_1, zero below its diagonal;
+        // rows NC..NC+|J_j|-1: the penalty rows; zero rows between them change
+        // no reflector), so a block needs max(|I_j|, 2 NC) rows, not
+        // |I_j| + |J_j|.  The right
         // side keeps c_1 and drops c_2, whose norm is the first stage's share
         // of the penalised residual.
         double c2s1 = 0.0;
-#pragma unroll
+#pragma unroll 1
         for (int stage = 0; stage < (WEIGHTED ? 2 : 1); ++stage) {
             if (stage == 1) {
                 double r2 = 0.0;
@@ -402,23 +404,27 @@ k_numeric(NumericArgs a) {
                     if (row >= nJ) bq[t] = (TQ)0;
                 }
                 c2s1 = group_sum<G>(r2);
-                // sqrt(p_c) through the (now free) LDS tile: lane g computes the
-                // columns g, g+G, ...; a lane reads the one its penalty row needs
+                // p_c into the group's LDS slots and sqrt(p_c) through the (now
+                // free) LDS tile: lane g computes the columns g, g+G, ...
                 TQ* sp = tile + q * RS * TC;
+                double* pen0 = pen_sh + q * NC;
 #pragma unroll
-                for (int c = g; c < NC; c += G)
-                    sp[c] = (valid && c < nJ) ? (TQ)sqrt(a.mu * (1.0 / a.w[scol + c] - 1.0)) : (TQ)0;
+                for (int c = g; c < NC; c += G) {
+                    const double p = (valid && c < nJ) ? a.mu * (1.0 / a.w[scol + c] - 1.0) : 0.0;
+                    pen0[c] = p;
+                    sp[c] = (TQ)sqrt(p);
+                }
                 wave_sync();
+                // The first stage left R_1 in rows 0..|J_j|-1 and zeros below
+                // (its reflectors clear the entries under the diagonal), so only
+                // the penalty entries go in: sqrt(p_c) at row NC + c, a row fixed
+                // at compile time (rows |J_j|..NC-1 stay zero, which changes no
+                // reflector), held by one lane of the group.
 #pragma unroll
-                for (int t = 0; t < R; ++t) {
-                    const int row = t * G + g;
-                    const int pc = row - nJ;  // penalty row of column pc
-                    const TQ pv_t = (pc >= 0 && pc < nJ) ? sp[pc] : (TQ)0;
-#pragma unroll
-                    for (int c = 0; c < NC; ++c) {
-                        const TQ keep = row <= c ? A[t][c] : (TQ)0;
-                        A[t][c] = row < nJ ? keep : (pc == c ? pv_t : (TQ)0);
-                    }
+                for (int c = 0; c < NC; ++c) {
+                    const int rc = NC + c;
+                    const TQ s = sp[c];
+                    A[rc / G][c] = (g == rc % G) ? s : A[rc / G][c];
                 }
                 wave_sync();
             }
@@ -472,6 +478,9 @@ k_numeric(NumericArgs a) {
                     const bool diag = (t == tk) && (g == gk);
                     v[t] = below ? A[t][k] : (diag ? alp - beta : (TQ)0);
                     if (diag) A[t][k] = beta;
+                    // weighted forms: exact zeros under the diagonal (what the
+                    // second stage needs below R_1; nothing else reads them)
+                    if (WEIGHTED && below) A[t][k] = (TQ)0;
                 }
                 TQ w[NC + 1];
 #pragma unroll
@@ -656,10 +665,10 @@ k_numeric(NumericArgs a) {
             for (int c = 0; c < NC; ++c) {
                 TQ part = 0;
 #pragma unroll
-                for (int t = 0; t < R; ++t) {
-                    const int row = t * G + g;
-                    if (t * G < c) part += (row < c) ? A[t][c] * ydist[t] : (TQ)0;
-                }
+                // rows at or past c hold ydist = 0 (not solved yet), so they
+                // add nothing and need no mask
+                for (int t = 0; t < R; ++t)
+                    if (t * G < c) part += A[t][c] * ydist[t];
                 part = group_sum<G>(part);
                 TQ yc = ((TQ)rhs_sh[c] - part) * RINV(c);
                 yc = (c < nJ) ? yc : (TQ)0;
@@ -675,15 +684,10 @@ k_numeric(NumericArgs a) {
             vec[trash] = 0.0;
         };
 
-        // penalties p_c = mu (1/w_c - 1) in LDS (read by every lane of the
-        // group, so they hold no registers across the refinement and the
-        // adjoint)
+        // penalties p_c = mu (1/w_c - 1) in LDS, written before the second
+        // QR stage (read by every lane of the group, so they hold no
+        // registers across the refinement and the adjoint)
         double* pen = pen_sh + q * NC;
-        if constexpr (WEIGHTED) {
-#pragma unroll
-            for (int c = g; c < NC; c += G) pen[c] = (valid && c < nJ) ? a.mu * (1.0 / a.w[scol + c] - 1.0) : 0.0;
-            wave_sync();
-        }
 
         double mfin[WEIGHTED ? 1 : NC];
         double rr;
@@ -781,10 +785,8 @@ k_numeric(NumericArgs a) {
                         }
                         TQ part = 0;
 #pragma unroll
-                        for (int t = 0; t < R; ++t) {
-                            const int row = t * G + g;
-                            if (t * G < c) part += (row < c) ? A[t][c] * ydist[t] : (TQ)0;
-                        }
+                        for (int t = 0; t < R; ++t)  // rows >= c: ydist = 0
+                            if (t * G < c) part += A[t][c] * ydist[t];
                         const double sc = group_sum<G>(gp - (double)part);
                         TQ yc = (TQ)sc * RINV(c);
                         yc = (c < nJ) ? yc : (TQ)0;
