@@ -10,35 +10,40 @@ namespace samk {
 
 namespace {
 
-// One thread per column l of A_k: for every column j whose pattern holds l
+// kLanes threads per column l of A_k, thread i0 taking the entries i0,
+// i0 + kLanes, ... of A_k(:, l): for every column j whose pattern holds l
 // (the row view of S, ascending j) the staged contributions of j to the
-// entries of A_k(:, l) are contiguous, so each j costs one offset lookup
-// (prefetched one step ahead) and one contiguous read per entry, added into
-// per-entry registers in ascending j.  Columns longer than kChunk entries
-// take several passes.
-constexpr int kChunk = 8;
+// entries of A_k(:, l) are contiguous, so the threads of one column read one
+// contiguous run per j.  Each entry's sum runs over j in ascending order;
+// the index lookups and reads of kUnroll consecutive j are issued before
+// their additions, which keep that order.
+constexpr int kLanes = 8;
+constexpr int kUnroll = 4;
 
-__global__ void k_backward_scatter(int n, const int* Ak_cp, const int* ST_rowptr, const int* ST_perm,
-                                   const int64_t* segoff, const double* contrib, double* gAk) {
-    const int l = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void __launch_bounds__(256)
+k_backward_scatter(int n, const int* Ak_cp, const int* ST_rowptr, const int* ST_perm, const int64_t* segoff,
+                   const double* contrib, double* gAk) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int l = (int)(t / kLanes);
+    const int i0 = (int)(t % kLanes);
     if (l >= n) return;
     const int fa = Ak_cp[l], len = Ak_cp[l + 1] - fa;
     const int sa = ST_rowptr[l], sb = ST_rowptr[l + 1];
-    for (int f0 = 0; f0 < len; f0 += kChunk) {
-        double acc[kChunk];
+    for (int i = i0; i < len; i += kLanes) {
+        double acc = 0.0;
+        int e = sa;
+        for (; e + kUnroll <= sb; e += kUnroll) {
+            int64_t off[kUnroll];
+            double v[kUnroll];
 #pragma unroll
-        for (int i = 0; i < kChunk; ++i) acc[i] = 0.0;
-        int64_t next = sa < sb ? segoff[ST_perm[sa]] : 0;
-        for (int e = sa; e < sb; ++e) {
-            const double* src = contrib + next + f0;
-            if (e + 1 < sb) next = segoff[ST_perm[e + 1]];
+            for (int u = 0; u < kUnroll; ++u) off[u] = segoff[ST_perm[e + u]];
 #pragma unroll
-            for (int i = 0; i < kChunk; ++i)
-                if (f0 + i < len) acc[i] += src[i];
+            for (int u = 0; u < kUnroll; ++u) v[u] = contrib[off[u] + i];
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) acc += v[u];
         }
-#pragma unroll
-        for (int i = 0; i < kChunk; ++i)
-            if (f0 + i < len) gAk[fa + f0 + i] = acc[i];
+        for (; e < sb; ++e) acc += contrib[segoff[ST_perm[e]] + i];
+        gAk[fa + i] = acc;
     }
 }
 
@@ -47,7 +52,8 @@ __global__ void k_backward_scatter(int n, const int* Ak_cp, const int* ST_rowptr
 hipError_t backward_scatter(int n, const int* Ak_cp, const int* ST_rowptr, const int* ST_perm,
                             const int64_t* segoff, const double* contrib, double* gAk, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_backward_scatter, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, Ak_cp,
+    const int64_t threads = (int64_t)n * kLanes;
+    hipLaunchKernelGGL(k_backward_scatter, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, n, Ak_cp,
                        ST_rowptr, ST_perm, segoff, contrib, gAk);
     return hipGetLastError();
 }
