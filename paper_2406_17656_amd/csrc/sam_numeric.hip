@@ -169,10 +169,14 @@ k_numeric(NumericArgs a) {
     int n_j = 0, n_cp0 = 0, n_cp1 = 0, n_nI = 0, n_a0 = 0, n_a1 = 0;
     int64_t n_eo = 0;
     int n_l[NCG], n_v0[NCG], n_v1[NCG];
+    // A bucket that holds all n columns lists them in column order (the
+    // bucket sort is stable, and a single class gets the identity queue), so
+    // its queue entry is the slot itself: one dependent load less per group.
+    const bool ident = b0 == 0 && count == a.n;
     auto stage1 = [&](int gr) {  // queue entry
         const int slot = gr * P + q;
         n_valid = gr < grp_hi && slot < count;
-        n_j = n_valid ? a.queue[b0 + slot] : 0;
+        n_j = n_valid ? (ident ? slot : a.queue[b0 + slot]) : 0;
     };
     auto stage2 = [&]() {  // pattern and row-set data of column j
         n_cp0 = n_cp1 = n_nI = n_a0 = n_a1 = 0;
