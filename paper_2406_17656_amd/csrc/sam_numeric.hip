@@ -122,7 +122,7 @@ k_numeric(NumericArgs a) {
     __shared__ double lds_tile[kTileD > kResD ? kTileD : kResD];
     TQ* tile = reinterpret_cast<TQ*>(lds_tile);
     __shared__ double bsh[P * RS];        // b = A_0(I_j, j)
-    __shared__ int cst[P][NC + 1];        // entry offset of column c in the block
+    __shared__ int cst[P][NC];            // entry offset of column c in the block
     __shared__ int vbs2[PIPE ? 2 : 1][P][NC];  // start of A_k(:, J_j[c]) in the value array
     __shared__ int cln2[PIPE ? 2 : 1][P][NC];  // nnz of A_k(:, J_j[c])
     __shared__ int mta[P][9];             // next group: valid, j, scol, nJ, nIj, eo (2), a0, a1
@@ -162,8 +162,8 @@ k_numeric(NumericArgs a) {
     // outstanding.  Lane g resolves columns g, g+G, ... of J_j.
     // Blocks of 8 to 13 columns of the plain map prefetch; wider blocks and
     // the weighted forms have no registers to spare (and the narrowest lose
-    // a wave slot per SIMD): they run the same stages for their own group at
-    // its top.
+    // a wave slot per SIMD, or gain nothing): they run the same stages for
+    // their own group at its top.
     constexpr int NCG = (NC + G - 1) / G;
     bool n_valid = false;
     int n_j = 0, n_cp0 = 0, n_cp1 = 0, n_nI = 0, n_a0 = 0, n_a1 = 0;
@@ -290,7 +290,6 @@ k_numeric(NumericArgs a) {
                 cst[q][c] = acc;
                 acc += cln[q][c];
             }
-            cst[q][NC] = acc;
         }
         double outj = 0.0;
 #pragma unroll
