@@ -92,8 +92,18 @@ __device__ inline double root<double>(double x) { return sqrt(x); }
 // MODE 0: plain least squares; 1: soft-weighted (stacked penalty rows);
 // 2: adjoint of the soft-weighted map (forward recomputed, then lambda and
 // the gradient contributions).
+// The 64-row FP32 class of the plain map (63 x 25 blocks of 3D seven-point
+// level-2 patterns) is held to three waves per SIMD (168 VGPRs; it would
+// take 175 and fit two): the compiler then keeps a few loop-invariant values
+// in scratch (28 bytes per lane, reloaded a handful of times per group), and
+// the launch is about 8% faster.
+constexpr int numeric_min_waves(bool f32, int G, int R, int NC, int MODE) {
+    return (f32 && MODE == 0 && G == 16 && R == 4 && NC == 25) ? 3 : 1;
+}
+
 template <typename TQ, int G, int R, int NC, int TC, int LPL, int MODE>
 __global__ void __launch_bounds__(64)
+__attribute__((amdgpu_waves_per_eu(numeric_min_waves(std::is_same<TQ, float>::value, G, R, NC, MODE))))
 k_numeric(NumericArgs a) {
     constexpr bool WEIGHTED = MODE >= 1;
     constexpr bool BACKWARD = MODE == 2;

@@ -39,11 +39,24 @@ def test_every_numeric_variant_was_recorded():
     assert ("f", 4, 7, 13, 1, 2, 0) in v and ("f", 16, 4, 25, 1, 1, 0) in v
 
 
+# Held to three waves per SIMD on purpose: a few loop-invariant values go to
+# scratch, which costs less than the third wave gains.
+THREE_WAVES = {("f", 16, 4, 25, 1, 1, 0): 32}
+
+
 def test_numeric_kernels_do_not_spill():
     """No variant of any mode (plain, soft-weighted forward, adjoint) spills
-    to scratch."""
-    bad = {k: r["ScratchSize"] for k, r in numeric_variants().items() if r["ScratchSize"]}
+    to scratch, except the bounded spill of the classes held to three waves
+    per SIMD."""
+    bad = {k: r["ScratchSize"] for k, r in numeric_variants().items()
+           if r["ScratchSize"] > THREE_WAVES.get(k, 0)}
     assert not bad, bad
+
+
+def test_classes_held_to_three_waves():
+    v = numeric_variants()
+    for k in THREE_WAVES:
+        assert v[k]["Occupancy"] == 3 and v[k]["VGPRs"] <= 168, (k, v[k])
 
 
 def test_fp32_weighted_and_adjoint_kernels_hold_two_waves_per_simd():
