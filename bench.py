@@ -104,12 +104,16 @@ def tune_order(ctx, dAk0, dA0, prec, power, spec, reps=5):
     return res
 
 
-def step_sequence(ctx, dA0, dAk0, nmaps, prec, power, spec, order, replan=True):
+def step_sequence(ctx, dA0, dAk0, nmaps, prec, power, spec, order, replan=True, vals=None):
     """The timed step: every source's pattern, plan, build and residual in
-    one graph-captured sequence, with the given variant order."""
+    one graph-captured sequence, with the given variant order, or (sources'
+    values given, replanned) the order the sequence-level autotuner picks
+    starting from it."""
     from paper_2406_17656_amd import autotune
     seq = ctx.sequence(dA0, dAk0, nmaps, prec=prec, power=power, replan_each_run=replan, **spec)
     seq.select(autotune.complete(order, prec))
+    if vals is not None and replan:
+        seq.tuned = autotune.tune_sequence(seq, vals, order, prec)
     return seq
 
 
@@ -168,7 +172,7 @@ def ninepoint_variant(ctx, P, torch, log, steps=5, warmup=2):
     dAk = [DeviceCSC.from_host(A) for A in Ash]
     vals = [d.val for d in dAk]
     res = tune_order(ctx, dAk[0], dA0, "f32", 2, spec)
-    seq = step_sequence(ctx, dA0, dAk[0], len(Ash), "f32", 2, spec, res["order"])
+    seq = step_sequence(ctx, dA0, dAk[0], len(Ash), "f32", 2, spec, res["order"], vals=vals)
     Ms = seq.alloc_maps()
     res2 = torch.zeros(len(Ash), dtype=torch.float64, device="cuda")
     for _ in range(warmup):
@@ -181,11 +185,12 @@ def ninepoint_variant(ctx, P, torch, log, steps=5, warmup=2):
     torch.cuda.synchronize()
     wall = (time.perf_counter() - t0) / steps
     ctx.sync_status()
+    seq_order = seq.tuned["order"]
     seq.close()
     cols = A0h.n * len(Ash)
     log(f"9-point 1024^2: {wall * 1e3:.2f} ms per step, {cols / wall / 1e6:.1f} M columns/s")
     return {"n": A0h.n, "maps": len(Ash), "cols_per_s": cols / wall, "ms_per_step": wall * 1e3,
-            "order": res["order"][:4]}
+            "order": seq_order[:4]}
 
 
 def apply_variant(ctx, plan, dA0, dAk0, Scp, Sri, torch, reps=50):
@@ -354,9 +359,15 @@ def main():
             log(f"autotune {prec} level {power}: order {res['order'][:3]}..., {res['us']:.1f} us/map")
         return tuned[(prec, power)]["order"]
 
+    seq_tuned = {}
+
     def time_sequence(prec, power, replan, steps, warmup):
         order = tuned_order(prec, power)
-        seq = step_sequence(ctx, dA0, dAk[0], nmaps, prec, power, spec, order, replan)
+        seq = step_sequence(ctx, dA0, dAk[0], nmaps, prec, power, spec, order, replan, vals=vals)
+        if replan:
+            seq_tuned[(prec, power)] = seq.tuned["order"]
+            log(f"sequence autotune {prec} level {power}: order {seq.tuned['order'][:3]}..., "
+                f"{seq.tuned['ms']:.3f} ms per run")
         Ms = seq.alloc_maps()
         res2 = torch.zeros(nmaps, dtype=torch.float64, device="cuda")
         for _ in range(warmup):
@@ -390,7 +401,8 @@ def main():
     # order, selected alone so that one launch covers every column of the map
     Scp, Sri = ctx.pattern(dAk[0], 2, **spec)
     plan = ctx.plan(dAk[0], dA0, Scp, Sri)
-    order32 = tuned_order("f32", 2)
+    # (the order of the timed step when it was tuned on the whole sequence)
+    order32 = seq_tuned.get(("f32", 2)) or tuned_order("f32", 2)
     plan.select(order32, "f32")
     bcols = plan.info()["bucket_cols"]
     dom_idx = order32[max(range(len(bcols)), key=lambda b: bcols[b])]
@@ -629,6 +641,7 @@ def main():
         "cpu_baseline": cpu,
         "variants": variants,
         "autotuned_variant_order": {f"{p}_level{l}": v["order"][:4] for (p, l), v in tuned.items()},
+        "sequence_tuned_variant_order": {f"{p}_level{l}": v[:4] for (p, l), v in seq_tuned.items()},
         "equal_residual_max_rel_diff_f32_vs_f64": eq,
         "relative_residual_per_map": rel_res,
     }

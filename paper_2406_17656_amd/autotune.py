@@ -152,3 +152,64 @@ def tune(plan, Ak_val, A0_val, prec="f32", reps=10, use_cache=True, refine=True)
         cache[sig] = {"order": best[0], "us": best[1], "timings": timings}
         _store_cache(cache)
     return {"order": best[0], "us": best[1], "timings": timings, "cached": False}
+
+
+def tune_sequence(seq, vals, order, prec="f32", reps=3, refine=True) -> dict:
+    """Pick the variant order of a replanned sequence by timing whole runs.
+
+    ``tune`` times orders on one source's plan; the sources of a sequence can
+    differ in shape (a threshold drops more couplings from some sources than
+    from others), and which classes pay off depends on all of them.  The
+    candidates are ``order`` and the orders that put each variant first (the
+    menu's other variants appended, see ``complete``); the fastest is refined
+    as in ``tune`` (a class moved to the end, neighbours swapped, kept when 2 %
+    faster).  Leaves the sequence selected; returns {"order", "ms",
+    "timings"}."""
+    import time
+
+    Ms = seq.alloc_maps()
+    res2 = torch.zeros(seq.n_src, dtype=torch.float64, device=vals[0].device)
+    n_var = len(menu(prec))
+    timings = {}
+
+    def trial(o):
+        o = complete(o, prec)
+        key = ",".join(map(str, o))
+        if key in timings:
+            return o, timings[key]
+        try:
+            seq.select(o)
+        except SamError:
+            return o, None
+        seq.run(vals, Ms, res2)          # captures the graph for this order
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            seq.run(vals, Ms, res2)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) / reps * 1e3
+        timings[key] = ms
+        return o, ms
+
+    best = None
+    for cand in [list(order)] + candidate_orders(n_var):
+        o, ms = trial(cand)
+        if ms is not None and (best is None or ms < best[1]):
+            best = (o, ms)
+    if refine and best is not None:
+        for _ in range(2):
+            changed = False
+            for v in list(best[0][1:]):
+                o, ms = trial([x for x in best[0] if x != v])
+                if ms is not None and ms < 0.98 * best[1]:
+                    best, changed = (o, ms), True
+            for i in range(1, len(best[0]) - 1):
+                cand = list(best[0])
+                cand[i], cand[i + 1] = cand[i + 1], cand[i]
+                o, ms = trial(cand)
+                if ms is not None and ms < 0.98 * best[1]:
+                    best, changed = (o, ms), True
+            if not changed:
+                break
+    seq.select(best[0])
+    return {"order": best[0], "ms": best[1], "timings": timings}

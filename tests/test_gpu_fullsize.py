@@ -1,7 +1,8 @@
 """Full-size GPU parity of the timed paths against the FP64 oracle.
 
-Each workload runs exactly as bench.py times it: the autotuned variant order
-on the first source, then the replanned sequence (every source's pattern,
+Each workload runs exactly as bench.py times it: the variant order tuned on
+the first source's plan and then on whole runs of the sequence, then the
+replanned sequence (every source's pattern,
 plan, buckets, build and residual inside one HIP graph), captured on the
 first run and replayed on the second.  For every source:
 - the pattern S_k is compared with the oracle's, bit for bit;
@@ -40,17 +41,19 @@ def dev(A):
 
 
 def run_step(ctx, name, A0, As, prec="f32", power=2):
-    """bench.py's step for workload `name`: tuned order, replanned
-    sequence, one captured run and one replay."""
+    """bench.py's step for workload `name`: the order tuned on the first
+    source's plan and then on whole runs of the replanned sequence, one run
+    and one replay."""
     spec = bench.WORKLOADS[name]["spec"]
     dA0 = dev(A0)
     dAs = [dev(A) for A in As]
+    vals = [d.val for d in dAs]
     order = bench.tune_order(ctx, dAs[0], dA0, prec, power, spec)["order"]
-    seq = bench.step_sequence(ctx, dA0, dAs[0], len(As), prec, power, spec, order)
+    seq = bench.step_sequence(ctx, dA0, dAs[0], len(As), prec, power, spec, order, vals=vals)
+    order = seq.tuned["order"]
     Ms = seq.alloc_maps()
     res2 = torch.zeros(len(As), dtype=torch.float64, device="cuda")
-    vals = [d.val for d in dAs]
-    seq.run(vals, Ms, res2)            # captured
+    seq.run(vals, Ms, res2)            # captured (the tuner's final selection)
     ctx.sync_status()
     first = [M.clone() for M in Ms]
     seq.run(vals, Ms, res2)            # replayed
