@@ -211,5 +211,7 @@ def tune_sequence(seq, vals, order, prec="f32", reps=3, refine=True) -> dict:
                     best, changed = (o, ms), True
             if not changed:
                 break
+    if best is None:
+        raise SamError(C.SAM_ERR_UNSUPPORTED, "no variant order fits every column of the sequence")
     seq.select(best[0])
     return {"order": best[0], "ms": best[1], "timings": timings}
