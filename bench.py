@@ -161,13 +161,15 @@ def adjoint_variant(ctx, P, torch, log, reps=10):
     return adj
 
 
-def ninepoint_variant(ctx, P, torch, log, steps=5, warmup=2):
-    """The ragged workload: the 1024^2 9-point sequence of 16 matrices (15
-    sources), global threshold 0.1 then level 2, replanned per source in one
-    HIP graph with the autotuned size classes, timed like the step."""
+def workload_variant(ctx, P, torch, log, name, steps=5, warmup=2):
+    """Another replanned workload, timed like the step: the 1024^2 9-point
+    sequence of 16 matrices (15 sources, global threshold 0.1 then level 2,
+    ragged classes) or the 64^3 upwind convection-diffusion sequence (5
+    sources, level 2, with or without the column threshold 0.85), with the
+    autotuned classes, in one HIP graph."""
     from paper_2406_17656_amd import DeviceCSC
-    spec = WORKLOADS["ninepoint2d"]["spec"]
-    A0h, Ash = P.config4()
+    spec = WORKLOADS[name]["spec"]
+    A0h, Ash = make_inputs(P, name)
     dA0 = DeviceCSC.from_host(A0h)
     dAk = [DeviceCSC.from_host(A) for A in Ash]
     vals = [d.val for d in dAk]
@@ -188,7 +190,7 @@ def ninepoint_variant(ctx, P, torch, log, steps=5, warmup=2):
     seq_order = seq.tuned["order"]
     seq.close()
     cols = A0h.n * len(Ash)
-    log(f"9-point 1024^2: {wall * 1e3:.2f} ms per step, {cols / wall / 1e6:.1f} M columns/s")
+    log(f"{name}: {wall * 1e3:.2f} ms per step, {cols / wall / 1e6:.1f} M columns/s")
     return {"n": A0h.n, "maps": len(Ash), "cols_per_s": cols / wall, "ms_per_step": wall * 1e3,
             "order": seq_order[:4]}
 
@@ -579,7 +581,10 @@ def main():
         variants["adaptive_map0"] = ad
         variants["adjoint_48cubed"] = adjoint_variant(ctx, P, torch, log)
         log("timing: 1024^2 9-point sequence, global threshold 0.1 then level 2 (ragged classes)")
-        variants["f32_ninepoint_1024_replanned"] = ninepoint_variant(ctx, P, torch, log)
+        variants["f32_ninepoint_1024_replanned"] = workload_variant(ctx, P, torch, log, "ninepoint2d")
+        log("timing: 64^3 upwind convection-diffusion sequence, level 2, without and with tau = 0.85")
+        variants["f32_convdiff3d_64_replanned"] = workload_variant(ctx, P, torch, log, "convdiff3d")
+        variants["f32_convdiff3d_tau_64_replanned"] = workload_variant(ctx, P, torch, log, "convdiff3d_tau")
     else:
         plan.close()
     rel_res = [float(np.sqrt(r / a02)) for r in r2_f32]
