@@ -205,18 +205,40 @@ __global__ void k_tsort(int n, const int* rowptr, int* colind, int* perm) {
 // a wave read each row's column indices (and values) as one contiguous run
 // instead of one entry of 64 different rows.  Lane g sums entries g, g + 4,
 // ... of its row in ascending order; the four partials are added by the
-// quad exchanges of group_sum (the same order on every call).  perm == null:
-// the values are in the row view's order.
+// quad exchanges of group_sum (the same order on every call).  Each lane
+// issues the loads of kSpmvUnroll of its entries (indices and values, then
+// the x values they select) before it adds them, so a row of up to 16
+// entries costs two dependent round trips instead of two per entry; slots
+// past the row's end load a valid entry of the row with a zero value, which
+// adds an exact zero.
+// PERM: the values are read through the row view's permutation (else they
+// are in the row view's order).
 constexpr int kSpmvLanes = 4;
+constexpr int kSpmvUnroll = 4;
+template <bool F32, bool PERM>
 __global__ void __launch_bounds__(256)
-k_spmv_rows(int n, const int* rowptr, const int* colind, const int* perm, const void* val, int f32,
-            const double* x, double* y) {
+k_spmv_rows(int n, const int* rowptr, const int* colind, const int* perm, const void* val, const double* x,
+            double* y) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     const int i = t / kSpmvLanes, g = t % kSpmvLanes;
     double s = 0.0;
     if (i < n) {
         const int b = rowptr[i + 1];
-        for (int e = rowptr[i] + g; e < b; e += kSpmvLanes) s += mval(val, perm ? perm[e] : e, f32) * x[colind[e]];
+        for (int e = rowptr[i] + g; e < b; e += kSpmvLanes * kSpmvUnroll) {
+            int c[kSpmvUnroll];
+            double v[kSpmvUnroll], xv[kSpmvUnroll];
+#pragma unroll
+            for (int u = 0; u < kSpmvUnroll; ++u) {
+                const int eu = e + u * kSpmvLanes < b ? e + u * kSpmvLanes : e;   // e < b: in the row
+                c[u] = colind[eu];
+                const int ev = PERM ? perm[eu] : eu;
+                v[u] = F32 ? (double)static_cast<const float*>(val)[ev] : static_cast<const double*>(val)[ev];
+            }
+#pragma unroll
+            for (int u = 0; u < kSpmvUnroll; ++u) xv[u] = x[c[u]];
+#pragma unroll
+            for (int u = 0; u < kSpmvUnroll; ++u) s = fma(e + u * kSpmvLanes < b ? v[u] : 0.0, xv[u], s);
+        }
     }
     s = group_sum<kSpmvLanes>(s);   // every lane takes part: rows past n add zeros
     if (i < n && g == 0) y[i] = s;
@@ -283,8 +305,11 @@ hipError_t spmv_rows(int n, const int* rowptr, const int* colind, const int* per
                      int val_f32, const double* x, double* y, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     const int64_t threads = (int64_t)n * kSpmvLanes;
-    hipLaunchKernelGGL(k_spmv_rows, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, n, rowptr, colind,
-                       perm, val, val_f32, x, y);
+    const dim3 grid((unsigned)((threads + 255) / 256)), block(256);
+    if (val_f32 && perm) hipLaunchKernelGGL((k_spmv_rows<true, true>), grid, block, 0, s, n, rowptr, colind, perm, val, x, y);
+    else if (val_f32) hipLaunchKernelGGL((k_spmv_rows<true, false>), grid, block, 0, s, n, rowptr, colind, perm, val, x, y);
+    else if (perm) hipLaunchKernelGGL((k_spmv_rows<false, true>), grid, block, 0, s, n, rowptr, colind, perm, val, x, y);
+    else hipLaunchKernelGGL((k_spmv_rows<false, false>), grid, block, 0, s, n, rowptr, colind, perm, val, x, y);
     return hipGetLastError();
 }
 

@@ -170,9 +170,10 @@ def test_residual_arbitrary_map(ctx):
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
-def test_apply(ctx, prec):
+@pytest.mark.parametrize("power", [2, 3])   # rows of about 13 and 25 entries: one and two unrolled chunks
+def test_apply(ctx, prec, power):
     _, A0, Ak = CASES[1]
-    Sp = O.pattern(Ak, 2)
+    Sp = O.pattern(Ak, power)
     Scp, Sri = torch.as_tensor(Sp.colptr).cuda(), torch.as_tensor(Sp.rowind).cuda()
     M = np.random.default_rng(1).standard_normal(Sp.nnz)
     Mt = torch.as_tensor(M.astype(np.float32 if prec == "f32" else np.float64)).cuda()
