@@ -473,11 +473,13 @@ k_numeric(NumericArgs a) {
                 // read again.
                 const TQ sigma = zero ? (TQ)0 : recip<TQ>(beta * (beta - alp));
                 if (stage == (WEIGHTED ? 1 : 0)) {
+                    // columns past |J_j| are zero, so their beta is an exact 0:
+                    // it leaves the largest and the NaN flag as they are, and only
+                    // the smallest needs the live columns' mask
                     const TQ ab = fabs(beta);
-                    const bool live = k < nJ;
-                    dmax = live ? fmax(dmax, ab) : dmax;
-                    dmin = live ? fmin(dmin, ab) : dmin;
-                    dnan |= live && !(ab == ab);
+                    dmax = fmax(dmax, ab);
+                    dmin = k < nJ ? fmin(dmin, ab) : dmin;
+                    dnan |= !(ab == ab);
                 }
                 if constexpr (WEIGHTED) {
                     if (g == 0) rinv_sh[q * NC + k] = ib;
