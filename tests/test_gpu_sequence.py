@@ -192,3 +192,31 @@ def test_sequence_replanned_orders(ctx, case):
         ctx.sync_status()
         check_maps(ctx, seq, A0, As, Ms, res2, "f32", 2, **kw)
     seq.close()
+
+
+def test_sequence_autotuner_small(ctx):
+    """The sequence-level autotuner on a 10^3 upwind sequence whose sources
+    the column threshold thins unevenly (Pe 1 to 100): it returns a full
+    variant order from the candidates it timed, leaves the sequence selected
+    with it, and the maps of the next run match the oracle."""
+    from paper_2406_17656_amd import autotune
+    kw = dict(kind="column", tau=0.85)
+    A0, As = P.config3(m=10)
+    dA0 = dev(A0)
+    dAs = [dev(A) for A in As]
+    vals = [d.val for d in dAs]
+    seq = ctx.sequence(dA0, dAs[0], len(As), prec="f32", power=2, replan_each_run=True, **kw)
+    menu = autotune.menu("f32")
+    res = autotune.tune_sequence(seq, vals, list(range(len(menu))), "f32", reps=1)
+    order = res["order"]
+    assert len(order) == min(16, len(menu)) and len(set(order)) == len(order)
+    assert all(0 <= v < len(menu) for v in order)
+    assert res["ms"] == res["timings"][",".join(map(str, order))]
+    Ms = seq.alloc_maps()
+    for m in Ms:
+        m.fill_(float("nan"))
+    res2 = torch.zeros(len(As), dtype=torch.float64, device="cuda")
+    seq.run(vals, Ms, res2)
+    ctx.sync_status()
+    check_maps(ctx, seq, A0, As, Ms, res2, "f32", 2, **kw)
+    seq.close()
