@@ -394,12 +394,15 @@ enum { kModeCount = 0, kModeFill = 1, kModePositions = 2 };
 
 // Bitmap word wi (rows 32 wi .. 32 wi + 31 of the chunk) belongs to lane
 // wi / WPL of the group (the lanes own consecutive row ranges, so ranks
-// follow a prefix over the lanes) but is stored at (wi % WPL) * GS + wi / WPL:
-// the passes in which every lane touches its own words hit GS consecutive
-// banks instead of GS / 4.
+// follow a prefix over the lanes).  The block's bitmaps are interleaved: word
+// w of a lane sits at w * kSymThreads + the lane's thread index, so that in
+// the passes where every lane touches its own words a wave reads or writes 64
+// consecutive words, the groups need no padding between them, and each of a
+// lane's words is a constant offset from one base address.  Relative to the
+// group's base (its first thread), word wi is at the slot below.
 template <int GS, int WPL>
 __device__ inline int word_slot(int wi) {
-    return ((wi & (WPL - 1)) * GS) | (wi / WPL);
+    return (wi & (WPL - 1)) * kSymThreads + wi / WPL;
 }
 
 // Rank of row d (relative to the chunk base) inside the chunk's bitmap.  The
@@ -441,15 +444,14 @@ k_union(UnionArgs a) {
     constexpr int kChunkWords = chunk_words<GS>();
     constexpr int kChunk = kChunkWords * 32;
     constexpr int kWPL = kChunkWords / GS;   // bitmap words per lane
-    // group stride padded by GS words: the groups of a wave start on
-    // different banks
-    __shared__ unsigned bm_all[kGroups][kChunkWords + GS];
-    __shared__ unsigned char pre_all[kGroups][kChunkWords + GS];
+    // the block's bitmaps and word prefixes, interleaved (see word_slot)
+    __shared__ unsigned bm_all[kChunkWords * kGroups];
+    __shared__ unsigned char pre_all[kChunkWords * kGroups];
     const int n = a.n;
     const int grp = threadIdx.x / GS;
     const int g = threadIdx.x % GS;
-    unsigned* bm = bm_all[grp];
-    unsigned char* wpre = pre_all[grp];
+    unsigned* bm = bm_all + grp * GS;
+    unsigned char* wpre = pre_all + grp * GS;
     auto slot = [](int wi) { return word_slot<GS, kWPL>(wi); };
     const int stride = gridDim.x * kGroups;
     auto q_len = [&](int l) { return a.Q_cnt ? a.Q_cnt[l] : a.Q_cp[l + 1] - a.Q_cp[l]; };
@@ -530,7 +532,7 @@ k_union(UnionArgs a) {
         int base = lo;
         while (base != INT_MAX) {
 #pragma unroll
-            for (int w = 0; w < kWPL; ++w) bm[w * GS + g] = 0u;
+            for (int w = 0; w < kWPL; ++w) bm[w * kSymThreads + g] = 0u;
             wave_sync();
             int next = INT_MAX;
             if (!big) {
@@ -561,7 +563,7 @@ k_union(UnionArgs a) {
             int c = 0;
 #pragma unroll
             for (int w = 0; w < kWPL; ++w) {
-                wd[w] = bm[w * GS + g];
+                wd[w] = bm[w * kSymThreads + g];
                 c += __popc(wd[w]);
             }
             const int pre = grp_excl_scan<GS>(c);
@@ -570,7 +572,7 @@ k_union(UnionArgs a) {
                 int run = running + pre;
 #pragma unroll
                 for (int w = 0; w < kWPL; ++w) {
-                    wpre[w * GS + g] = (unsigned char)min(run, 255);
+                    wpre[w * kSymThreads + g] = (unsigned char)min(run, 255);
                     run += __popc(wd[w]);
                 }
             }
@@ -632,7 +634,8 @@ k_union(UnionArgs a) {
 }
 
 // Eight lanes per column: one list per lane up to 8 lists, two up to 16 (eight
-// columns per wave either way, the most a CU's LDS holds at once); then 16
+// columns per wave either way; at 640 bytes of LDS per column of the positions
+// pass, eight such waves per SIMD fill a CU's LDS); then 16
 // lanes with two lists each (32 lists in registers); beyond that the memory
 // loops.  The rows held per list follow the longest list
 // (5, 8, 9 or 12; longer lists take the memory loops).  Bounds <= 0: unknown.
